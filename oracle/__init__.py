@@ -1,0 +1,300 @@
+"""FP64 CPU oracle of the STG wall-modelled MRT-LBM channel step (arXiv 2304.04214).
+
+TEST INFRASTRUCTURE ONLY.  Only the test suite, ``__graft_entry__.smoke()`` and
+the CPU-baseline leg of ``bench.py`` may import this package.  It shares no code
+with the HIP library ``paper_2304_04214_amd``; it is compiled from
+``oracle.cpp`` with g++ (``build()``), and reached through ctypes.
+
+Parity status per function (see the pins in ``tests/test_oracle_*.py``):
+every function below is pinned by a closed form, an identity or a printed
+value of the paper, except the whole-system step at turbulent sizes, whose
+agreement with anything but the HIP path is unpinned by the paper (it gives no
+worked example); its parts are pinned one by one.
+"""
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "oracle.cpp")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+OK, ERR_ARG, ERR_MACH, ERR_NONFINITE, ERR_NEWTON = 0, 1, 4, 5, 7
+
+# Appendix A.1 free rates (reading: omega_0,3,5,7 = 1, omega_1 = 1.19);
+# 9, 11, 13, 14, 15 are overwritten by 1/tau_eff inside the collision.
+PAPER_RATES = [1.0, 1.19, 1.6, 1.0, 1.2, 1.0, 1.2, 1.0, 1.2, 1.0,
+               1.6, 1.0, 1.6, 1.0, 1.0, 1.0, 1.98, 1.98, 1.98]
+
+
+def build(force=True):
+    """Compile oracle.cpp into liboracle.so (g++, OpenMP, -O2)."""
+    if not force and os.path.exists(_LIB) and os.path.getmtime(_LIB) >= os.path.getmtime(_SRC):
+        return _LIB
+    tmp = _LIB + ".tmp%d" % os.getpid()
+    cmd = ["g++", "-O2", "-std=c++17", "-fopenmp", "-fPIC", "-shared", "-Wall", "-o", tmp, _SRC]
+    subprocess.run(cmd, check=True)
+    os.replace(tmp, _LIB)
+    return _LIB
+
+
+class Cfg(C.Structure):
+    _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32),
+                ("ywall", C.c_int32), ("xbc", C.c_int32), ("wall_model", C.c_int32),
+                ("newton_max", C.c_int32), ("pad_", C.c_int32),
+                ("newton_tol", C.c_double), ("tau0", C.c_double), ("cs_smag", C.c_double),
+                ("s", C.c_double * 19), ("kappa", C.c_double), ("b_reich", C.c_double),
+                ("y_wall", C.c_double), ("u_conv", C.c_double), ("g", C.c_double * 3)]
+
+
+class Stg(C.Structure):
+    _fields_ = [("n_modes", C.c_int32), ("n_bins", C.c_int32),
+                ("q", C.c_void_p), ("sigma", C.c_void_p), ("kmag", C.c_void_p), ("d", C.c_void_p),
+                ("phi", C.c_void_p), ("omega", C.c_void_p), ("u_rans", C.c_void_p), ("R", C.c_void_p),
+                ("amp_bin", C.c_void_p), ("bin_of_y", C.c_void_p)]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build()
+        _lib = C.CDLL(_LIB)
+        P = C.c_void_p
+        D = C.c_double
+        I = C.c_int
+        sig = {
+            "oracle_set_mutation": (None, [I]),
+            "oracle_tables": (None, [P] * 6),
+            "oracle_feq": (None, [D, P, P]),
+            "oracle_meq": (None, [D, P, P]),
+            "oracle_guo": (None, [P, P, P]),
+            "oracle_collide_node": (None, [P, P, P, P, P, P]),
+            "oracle_tau_eff": (D, [D, D, D, D]),
+            "oracle_uplus": (D, [D, D, D]),
+            "oracle_duplus": (D, [D, D, D]),
+            "oracle_utau": (I, [P, D, P]),
+            "oracle_wall_force": (I, [P, D, P, P, I, P, P]),
+            "oracle_inlet_node": (None, [P, P, P, P]),
+            "oracle_cholesky": (None, [P, P]),
+            "oracle_stg_plane": (I, [P, P, D, P, P]),
+            "oracle_reichardt_inflow": (None, [P, D, P]),
+            "oracle_init": (I, [P, P, P, P, D, P, P]),
+            "oracle_stream_only": (I, [P, P, P]),
+            "oracle_step": (I, [P, P, D, P, P, P, P, P, I, P]),
+            "oracle_step_nodes": (I, [P, P, D, P, P, C.c_int64, P, P, P]),
+            "oracle_macro": (None, [P, P, P, P]),
+            "oracle_run": (I, [P, P, D, I, P, P, P, I, P]),
+        }
+        for name, (res, args) in sig.items():
+            fn = getattr(_lib, name)
+            fn.restype = res
+            fn.argtypes = args
+    return _lib
+
+
+def _p(a):
+    return None if a is None else a.ctypes.data_as(C.c_void_p)
+
+
+def _d(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def make_cfg(nx, ny, nz, *, ywall=0, xbc=0, wall_model=0, tau0=0.52, cs_smag=0.1, rates=None,
+             kappa=0.41, b_reich=7.8, y_wall=0.5, u_conv=0.1, g=(0.0, 0.0, 0.0),
+             newton_max=50, newton_tol=1e-14):
+    c = Cfg()
+    c.nx, c.ny, c.nz = nx, ny, nz
+    c.ywall, c.xbc, c.wall_model = ywall, xbc, wall_model
+    c.newton_max, c.newton_tol = newton_max, newton_tol
+    c.tau0, c.cs_smag = tau0, cs_smag
+    for i, v in enumerate(rates if rates is not None else PAPER_RATES):
+        c.s[i] = v
+    c.kappa, c.b_reich, c.y_wall, c.u_conv = kappa, b_reich, y_wall, u_conv
+    for a in range(3):
+        c.g[a] = g[a]
+    return c
+
+
+class StgInputs:
+    """Host FP64 STG inputs with their ctypes view (keeps arrays alive)."""
+
+    def __init__(self, q, sigma, kmag, d, phi, omega, u_rans, R, amp_bin, bin_of_y):
+        self.q, self.sigma, self.kmag, self.d = _d(q), _d(sigma), _d(kmag), _d(d)
+        self.phi, self.omega, self.u_rans, self.R = _d(phi), _d(omega), _d(u_rans), _d(R)
+        self.amp_bin = _d(amp_bin)
+        self.bin_of_y = np.ascontiguousarray(bin_of_y, dtype=np.int32)
+        s = Stg()
+        s.n_modes, s.n_bins = len(self.q), len(self.amp_bin)
+        s.q, s.sigma, s.kmag, s.d = _p(self.q), _p(self.sigma), _p(self.kmag), _p(self.d)
+        s.phi, s.omega, s.u_rans, s.R = _p(self.phi), _p(self.omega), _p(self.u_rans), _p(self.R)
+        s.amp_bin, s.bin_of_y = _p(self.amp_bin), _p(self.bin_of_y)
+        self.c = s
+
+
+def _ref(x):
+    return None if x is None else C.byref(x)
+
+
+# ---------------- building blocks ----------------
+
+def tables():
+    c = np.zeros((19, 3), np.int32)
+    w = np.zeros(19)
+    M = np.zeros((19, 19))
+    Mi = np.zeros((19, 19))
+    opp = np.zeros(19, np.int32)
+    refl = np.zeros(19, np.int32)
+    lib().oracle_tables(_p(c), _p(w), _p(M), _p(Mi), _p(opp), _p(refl))
+    return dict(c=c, w=w, M=M, Minv=Mi, opp=opp, refl=refl)
+
+
+def set_mutation(k):
+    lib().oracle_set_mutation(int(k))
+
+
+def feq(rho, u):
+    out = np.zeros(19)
+    lib().oracle_feq(float(rho), _p(_d(u)), _p(out))
+    return out
+
+
+def meq(rho, u):
+    out = np.zeros(19)
+    lib().oracle_meq(float(rho), _p(_d(u)), _p(out))
+    return out
+
+
+def guo(u, F):
+    out = np.zeros(19)
+    lib().oracle_guo(_p(_d(u)), _p(_d(F)), _p(out))
+    return out
+
+
+def collide_node(cfg, f, F):
+    out = np.zeros(19)
+    tau = np.zeros(1)
+    u = np.zeros(3)
+    lib().oracle_collide_node(C.byref(cfg), _p(_d(f)), _p(_d(F)), _p(out), _p(tau), _p(u))
+    return out, float(tau[0]), u
+
+
+def tau_eff(Qhalf, rho, tau0, cs):
+    return lib().oracle_tau_eff(Qhalf, rho, tau0, cs)
+
+
+def uplus(yp, kappa=0.41, B=7.8):
+    return lib().oracle_uplus(float(yp), kappa, B)
+
+
+def duplus(yp, kappa=0.41, B=7.8):
+    return lib().oracle_duplus(float(yp), kappa, B)
+
+
+def utau(cfg, uhat_abs):
+    out = np.zeros(1)
+    st = lib().oracle_utau(C.byref(cfg), float(uhat_abs), _p(out))
+    return st, float(out[0])
+
+
+def wall_force(cfg, rho_w, uw, u2, top):
+    F = np.zeros(3)
+    ut = np.zeros(1)
+    st = lib().oracle_wall_force(C.byref(cfg), float(rho_w), _p(_d(uw)), _p(_d(u2)), int(top), _p(F), _p(ut))
+    return st, F, float(ut[0])
+
+
+def inlet_node(f, uin):
+    out = np.zeros(19)
+    r = np.zeros(1)
+    lib().oracle_inlet_node(_p(_d(f)), _p(_d(uin)), _p(out), _p(r))
+    return out, float(r[0])
+
+
+def cholesky(R6):
+    a = np.zeros(6)
+    lib().oracle_cholesky(_p(_d(R6)), _p(a))
+    return a
+
+
+def stg_plane(cfg, stg, t, want_fluct=False):
+    uin = np.zeros((3, cfg.ny, cfg.nz))
+    fl = np.zeros((3, cfg.ny, cfg.nz)) if want_fluct else None
+    st = lib().oracle_stg_plane(C.byref(cfg), C.byref(stg.c), float(t), _p(uin), _p(fl))
+    return (st, uin, fl) if want_fluct else (st, uin)
+
+
+def reichardt_inflow(cfg, u_tau):
+    out = np.zeros((3, cfg.ny))
+    lib().oracle_reichardt_inflow(C.byref(cfg), float(u_tau), _p(out))
+    return out
+
+
+# ---------------- lattice operations ----------------
+
+def shape(cfg):
+    return (19, cfg.nx, cfg.ny, cfg.nz)
+
+
+def init(cfg, u, rho=None, pert=None, eps=0.0):
+    """f = f_eq(rho, u) + eps w pert; returns (f[19,nx,ny,nz], hist[5,ny,nz])."""
+    f = np.zeros(shape(cfg))
+    hist = np.zeros((5, cfg.ny, cfg.nz))
+    u = _d(u)
+    rho = None if rho is None else _d(rho)
+    pert = None if pert is None else _d(pert)
+    st = lib().oracle_init(C.byref(cfg), _p(rho), _p(u), _p(pert), float(eps), _p(f), _p(hist))
+    assert st == OK, st
+    return f, hist
+
+
+def stream_only(cfg, f):
+    out = np.zeros(shape(cfg))
+    st = lib().oracle_stream_only(C.byref(cfg), _p(_d(f)), _p(out))
+    assert st == OK, st
+    return out
+
+
+def step(cfg, f, hist, t_next, stg=None, planes=None, acc=None):
+    """One step; returns (status, f_new, hist_new).  acc[p,ny,9] accumulates sums in place."""
+    out = np.empty(shape(cfg))
+    hist_out = hist.copy() if hist is not None else None
+    pl = None if planes is None else np.ascontiguousarray(planes, dtype=np.int32)
+    st = lib().oracle_step(C.byref(cfg), _ref(stg.c if stg is not None else None), float(t_next),
+                           _p(_d(f)), _p(out), _p(None if hist is None else _d(hist)), _p(hist_out),
+                           _p(pl), 0 if pl is None else len(pl), _p(acc))
+    return st, out, hist_out
+
+
+def run(cfg, f, hist, t0, nsteps, stg=None, planes=None, acc=None):
+    """nsteps steps from time t0; returns (status, f, hist) as new arrays."""
+    f = _d(f).copy()
+    hist = None if hist is None else _d(hist).copy()
+    pl = None if planes is None else np.ascontiguousarray(planes, dtype=np.int32)
+    st = lib().oracle_run(C.byref(cfg), _ref(stg.c if stg is not None else None), float(t0), int(nsteps),
+                          _p(f), _p(hist), _p(pl), 0 if pl is None else len(pl), _p(acc))
+    return st, f, hist
+
+
+def step_nodes(cfg, f, hist, t_next, nodes, stg=None):
+    nodes = np.ascontiguousarray(nodes, dtype=np.int64)
+    out = np.zeros((19, len(nodes)))
+    u = np.zeros((3, len(nodes)))
+    st = lib().oracle_step_nodes(C.byref(cfg), _ref(stg.c if stg is not None else None), float(t_next),
+                                 _p(_d(f)), _p(None if hist is None else _d(hist)), len(nodes), _p(nodes),
+                                 _p(out), _p(u))
+    return st, out, u
+
+
+def macro(cfg, f):
+    N = cfg.nx * cfg.ny * cfg.nz
+    rho = np.zeros(N)
+    u = np.zeros(3 * N)
+    lib().oracle_macro(C.byref(cfg), _p(_d(f)), _p(rho), _p(u))
+    return rho.reshape(cfg.nx, cfg.ny, cfg.nz), u.reshape(3, cfg.nx, cfg.ny, cfg.nz)

@@ -1,0 +1,816 @@
+/*
+ * FP64 CPU oracle of one time step of the synthetic-turbulence-generator (STG)
+ * wall-modelled MRT lattice Boltzmann channel (Xue, Yao, Davidson,
+ * "Synthetic turbulence generator for the wall-modeled LES lattice Boltzmann
+ * method", arXiv 2304.04214).
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is the slow, plain reference that the
+ * HIP library is checked against.  Only the test suite, the smoke check and
+ * the CPU-baseline leg of the benchmark may load it.  It shares no code,
+ * header, table or constant with the HIP library: every table below is typed
+ * here from the paper.
+ *
+ * Structure: plain per-node loops in the order of the paper's Algorithm 1
+ * (Sec. III.B): streaming with boundary rules, the inlet branch (STG velocity,
+ * Zou-He density, regularised populations), the wall branch (base vector,
+ * projected speed, Newton solve for u_tau, wall force), then MRT collision with
+ * the Smagorinsky relaxation time.  The moment transform is the dense 19x19
+ * matrix of Appendix A.1 and its numerical inverse.
+ *
+ * Readings of the paper used here (where it is garbled, silent or ambiguous):
+ *  R1  m2_eq = 3 rho - (11/2) rho |u|^2  (the printed 11/2 rho (3 - |u|^2) is
+ *      not the projection of the equilibrium), Sec. II.A, Eq. (8).
+ *  R2  m4,6,8_eq = -(2/3) rho u_{x,y,z} (printed fraction inverted), Eq. (8).
+ *  R3  rates: omega_0,3,5,7 = 1, omega_1 = 1.19 (omega_1 is listed twice),
+ *      Appendix A.1.
+ *  R4  Guo forcing applied in moment space: m* += (I - S/2) M Fbar, with Fbar
+ *      the population form of Eq. (9) (the printed (1 - omega_i/2) mixes a
+ *      moment index with a population index).
+ *  R5  tau_eff = tau0/2 + sqrt(tau0^2 + 18 sqrt(2) C_smag Q^(1/2) / rho)/2,
+ *      C_smag = C_s^2, Delta = dx = dt = 1 (Eq. (15) misplaces rho; this form
+ *      is the root of Eq. (14) with Eq. (5) and Eq. (13)).
+ *  R6  Reichardt law u+ = ln(1 + k y+)/k + B [1 - e^(-y+/11) - (y+/11) e^(-y+/3)],
+ *      k = 0.41, B = 7.8 (the printed form has u+(1) = 0.80), Eq. (16).
+ *  R7  regularised inlet: fneq_i = w_i/(2 cs^4) Q_i : Pi_neq (the printed
+ *      w_i/cs^4 rebuilds 2 Pi_neq), Eq. (28).
+ *  R8  inlet density rho_in = (rho_0 + 2 rho_-)/(1 - u_in,x), rho_0 over
+ *      c_x = 0, rho_- over c_x < 0 (Zou-He mass balance), Eq. (30)-(31).
+ *  R9  force density F = rho g + F_w; rho u = sum f c + F/2, Eq. (11).
+ *  R10 wall-model velocities u_2 and u_w are the pre-force velocities j/rho of
+ *      the post-streaming (post-boundary) state; y_perp = 1/2 (halfway walls);
+ *      nu in y+ is the molecular nu0; F_w = -sign(u_hat) rho u_tau^2 e_x, A = 1.
+ *  R11 Newton start u_tau = sqrt(nu0 |u_hat| / y_perp); iterate until
+ *      |du| <= tol u_tau (max iterations given), then one more step.
+ *  R12 STG phase at the inlet: k (d_y y + d_z z) + omega t + phi, y = iy + 1/2,
+ *      z = iz; u' = s_b(y) a(y) v'; step n -> n+1 uses t = n+1.
+ *  R13 outlet: convective rule f_i = (f_i^prev + U_c f_i(x-1)) / (1 + U_c) for
+ *      c_x < 0 at x = nx-1, f(x-1) the post-streaming value of the same step.
+ *  R14 inlet and wall rules both apply at inlet/wall corner cells
+ *      (Algorithm 1 has two independent branches).
+ */
+#include <cmath>
+#include <cstdint>
+#include <cstdlib>
+#include <cstring>
+#include <vector>
+
+extern "C" {
+
+typedef struct {
+  int32_t nx, ny, nz;
+  int32_t ywall;       /* 0 periodic, 1 halfway bounce-back, 2 specular slip */
+  int32_t xbc;         /* 0 periodic, 1 STG inlet at x = 0 and convective outlet at x = nx-1 */
+  int32_t wall_model;  /* 1: Reichardt wall force in the first off-wall cells */
+  int32_t newton_max;  /* maximum Newton iterations (oracle converges to newton_tol) */
+  int32_t pad_;
+  double newton_tol;
+  double tau0;         /* molecular relaxation time, nu0 = (tau0 - 1/2)/3 */
+  double cs_smag;      /* Smagorinsky C_s, C_smag = C_s^2 */
+  double s[19];        /* relaxation rates; 9, 11, 13, 14, 15 are replaced by 1/tau_eff */
+  double kappa, b_reich, y_wall;
+  double u_conv;       /* outlet convection speed U_c */
+  double g[3];         /* body acceleration */
+} oracle_cfg;
+
+typedef struct {
+  int32_t n_modes, n_bins;
+  const double* q;        /* [N] spectral weights, sum 1 */
+  const double* sigma;    /* [3][N] unit amplitude directions, sigma . d = 0 */
+  const double* kmag;     /* [N] wavenumber magnitudes */
+  const double* d;        /* [3][N] unit wave directions */
+  const double* phi;      /* [N] phases */
+  const double* omega;    /* [N] temporal frequencies (rad per step) */
+  const double* u_rans;   /* [3][ny] mean inflow */
+  const double* R;        /* [6][ny] R11 R21 R22 R31 R32 R33 */
+  const double* amp_bin;  /* [n_bins] amplitude scalings s_b */
+  const int32_t* bin_of_y;/* [ny] */
+} oracle_stg;
+
+}  // extern "C"
+
+enum { OR_OK = 0, OR_ERR_ARG = 1, OR_ERR_MACH = 4, OR_ERR_NONFINITE = 5, OR_ERR_NEWTON = 7 };
+
+namespace {
+
+/* ---- Sec. II.A, Eq. (1): the D3Q19 velocity set, in the paper's order ---- */
+const int C[19][3] = {
+    {0, -1, -1}, {-1, 0, -1}, {0, 0, -1}, {1, 0, -1}, {0, 1, -1},
+    {-1, -1, 0}, {0, -1, 0},  {1, -1, 0}, {-1, 0, 0}, {0, 0, 0},
+    {1, 0, 0},   {-1, 1, 0},  {0, 1, 0},  {1, 1, 0},  {0, -1, 1},
+    {-1, 0, 1},  {0, 0, 1},   {1, 0, 1},  {0, 1, 1}};
+
+/* ---- Appendix A.1: the MRT matrix as printed ---- */
+const int MI[19][19] = {
+    {1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1},
+    {8, 8, -11, 8, 8, 8, -11, 8, -11, -30, -11, 8, -11, 8, 8, 8, -11, 8, 8},
+    {1, 1, -4, 1, 1, 1, -4, 1, -4, 12, -4, 1, -4, 1, 1, 1, -4, 1, 1},
+    {0, -1, 0, 1, 0, -1, 0, 1, -1, 0, 1, -1, 0, 1, 0, -1, 0, 1, 0},
+    {0, -1, 0, 1, 0, -1, 0, 1, 4, 0, -4, -1, 0, 1, 0, -1, 0, 1, 0},
+    {-1, 0, 0, 0, 1, -1, -1, -1, 0, 0, 0, 1, 1, 1, -1, 0, 0, 0, 1},
+    {-1, 0, 0, 0, 1, -1, 4, -1, 0, 0, 0, 1, -4, 1, -1, 0, 0, 0, 1},
+    {-1, -1, -1, -1, -1, 0, 0, 0, 0, 0, 0, 0, 0, 0, 1, 1, 1, 1, 1},
+    {-1, -1, 4, -1, -1, 0, 0, 0, 0, 0, 0, 0, 0, 0, 1, 1, -4, 1, 1},
+    {-2, 1, -1, 1, -2, 1, -1, 1, 2, 0, 2, 1, -1, 1, -2, 1, -1, 1, -2},
+    {-2, 1, 2, 1, -2, 1, 2, 1, -4, 0, -4, 1, 2, 1, -2, 1, 2, 1, -2},
+    {0, -1, -1, -1, 0, 1, 1, 1, 0, 0, 0, 1, 1, 1, 0, -1, -1, -1, 0},
+    {0, -1, 2, -1, 0, 1, -2, 1, 0, 0, 0, 1, -2, 1, 0, -1, 2, -1, 0},
+    {0, 0, 0, 0, 0, 1, 0, -1, 0, 0, 0, -1, 0, 1, 0, 0, 0, 0, 0},
+    {1, 0, 0, 0, -1, 0, 0, 0, 0, 0, 0, 0, 0, 0, -1, 0, 0, 0, 1},
+    {0, 1, 0, -1, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, -1, 0, 1, 0},
+    {0, 1, 0, -1, 0, -1, 0, 1, 0, 0, 0, -1, 0, 1, 0, 1, 0, -1, 0},
+    {-1, 0, 0, 0, 1, 1, 0, 1, 0, 0, 0, -1, 0, -1, -1, 0, 0, 0, 1},
+    {1, -1, 0, -1, 1, 0, 0, 0, 0, 0, 0, 0, 0, 0, -1, 1, 0, 1, -1}};
+
+const double CS2 = 1.0 / 3.0; /* Sec. II.A: c_s^2 = 1/3 */
+
+struct Tables {
+  double W[19];
+  double M[19][19];
+  double Minv[19][19];
+  int opp[19];
+  int refl_y[19];
+  Tables() {
+    /* Sec. II.A, Eq. (2): weights listed by index */
+    for (int i = 0; i < 19; ++i) W[i] = 1.0 / 36.0;
+    const int axis[6] = {2, 6, 8, 10, 12, 16};
+    for (int k = 0; k < 6; ++k) W[axis[k]] = 1.0 / 18.0;
+    W[9] = 1.0 / 3.0;
+    for (int a = 0; a < 19; ++a)
+      for (int b = 0; b < 19; ++b) M[a][b] = MI[a][b];
+    /* opposite and y-mirror directions found by search over the set */
+    for (int i = 0; i < 19; ++i) {
+      opp[i] = refl_y[i] = -1;
+      for (int j = 0; j < 19; ++j) {
+        if (C[j][0] == -C[i][0] && C[j][1] == -C[i][1] && C[j][2] == -C[i][2]) opp[i] = j;
+        if (C[j][0] == C[i][0] && C[j][1] == -C[i][1] && C[j][2] == C[i][2]) refl_y[i] = j;
+      }
+    }
+    invert();
+  }
+  /* Gauss-Jordan elimination with partial pivoting: M^-1 numerically */
+  void invert() {
+    double a[19][38];
+    for (int r = 0; r < 19; ++r)
+      for (int c = 0; c < 38; ++c) a[r][c] = c < 19 ? M[r][c] : (c - 19 == r ? 1.0 : 0.0);
+    for (int col = 0; col < 19; ++col) {
+      int piv = col;
+      for (int r = col + 1; r < 19; ++r)
+        if (std::fabs(a[r][col]) > std::fabs(a[piv][col])) piv = r;
+      if (piv != col)
+        for (int c = 0; c < 38; ++c) std::swap(a[piv][c], a[col][c]);
+      double p = a[col][col];
+      for (int c = 0; c < 38; ++c) a[col][c] /= p;
+      for (int r = 0; r < 19; ++r) {
+        if (r == col) continue;
+        double fac = a[r][col];
+        if (fac == 0.0) continue;
+        for (int c = 0; c < 38; ++c) a[r][c] -= fac * a[col][c];
+      }
+    }
+    for (int r = 0; r < 19; ++r)
+      for (int c = 0; c < 19; ++c) Minv[r][c] = a[r][19 + c];
+  }
+};
+
+const Tables& T() {
+  static Tables t;
+  return t;
+}
+
+/* Deliberate mistakes switched on only by tests that check a pin catches them. */
+int g_mutation = 0;
+
+inline double val(double x) { return x; }
+
+/* ---- Sec. III.A, Eq. (27): second-order equilibrium ---- */
+template <class R>
+void feq_poly(const R& rho, const R u[3], R out[19]) {
+  const Tables& t = T();
+  R uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+  for (int i = 0; i < 19; ++i) {
+    R cu = C[i][0] * u[0] + C[i][1] * u[1] + C[i][2] * u[2];
+    out[i] = t.W[i] * rho * (1.0 + cu / CS2 + cu * cu / (2.0 * CS2 * CS2) - uu / (2.0 * CS2));
+  }
+}
+
+/* ---- Sec. II.A, Eq. (8): equilibrium moments (readings R1, R2) ---- */
+template <class R>
+void meq_moments(const R& rho, const R u[3], R m[19]) {
+  const R ux = u[0], uy = u[1], uz = u[2];
+  const R uu = ux * ux + uy * uy + uz * uz;
+  m[0] = rho;
+  m[1] = -11.0 * rho + 19.0 * rho * uu;
+  m[2] = (g_mutation == 1) ? 5.5 * rho * (3.0 - uu) : 3.0 * rho - 5.5 * rho * uu;
+  const double c4 = (g_mutation == 2) ? -1.5 : -2.0 / 3.0;
+  m[3] = rho * ux;
+  m[4] = c4 * rho * ux;
+  m[5] = rho * uy;
+  m[6] = c4 * rho * uy;
+  m[7] = rho * uz;
+  m[8] = c4 * rho * uz;
+  m[9] = 2.0 * rho * ux * ux - rho * uy * uy - rho * uz * uz;
+  m[10] = -rho * ux * ux + 0.5 * rho * uy * uy + 0.5 * rho * uz * uz;
+  m[11] = rho * uy * uy - rho * uz * uz;
+  m[12] = -0.5 * rho * uy * uy + 0.5 * rho * uz * uz;
+  m[13] = rho * ux * uy;
+  m[14] = rho * uy * uz;
+  m[15] = rho * ux * uz;
+  m[16] = m[17] = m[18] = 0.0 * rho;
+}
+
+/* ---- Sec. II.A, Eq. (9): Guo forcing populations for force density F ---- */
+template <class R>
+void guo_populations(const R u[3], const R F[3], R out[19]) {
+  const Tables& t = T();
+  for (int i = 0; i < 19; ++i) {
+    R cu = C[i][0] * u[0] + C[i][1] * u[1] + C[i][2] * u[2];
+    R acc = 0.0 * u[0];
+    for (int a = 0; a < 3; ++a) {
+      R ua = (g_mutation == 3) ? 0.0 * u[a] : u[a];
+      acc = acc + ((C[i][a] - ua) / CS2 + cu * C[i][a] / (CS2 * CS2)) * F[a];
+    }
+    out[i] = t.W[i] * acc;
+  }
+}
+
+/* ---- Sec. II.B, Eq. (13)-(15): Smagorinsky relaxation time (reading R5) ---- */
+template <class R>
+R tau_eff_of(const R& Qhalf, const R& rho, double tau0, double cs_smag) {
+  using std::sqrt;
+  const double csmag = cs_smag * cs_smag;
+  return 0.5 * tau0 + 0.5 * sqrt(tau0 * tau0 + 18.0 * std::sqrt(2.0) * csmag * Qhalf / rho);
+}
+
+/* sqrt that is 0 with zero derivative at 0 (Pi_neq = 0 exactly) */
+template <class R>
+R safe_norm(const R& s2) {
+  using std::sqrt;
+  if (s2 == 0.0) return 0.0 * s2;
+  return sqrt(s2);
+}
+
+/*
+ * ---- Sec. II.A-II.B: MRT collision with forcing and Smagorinsky closure ----
+ * f: post-streaming populations of one node; F: force density.
+ * out: post-collision populations.  u_out (optional): rho u = sum f c + F/2.
+ */
+template <class R>
+void collide(const oracle_cfg& cfg, const R f[19], const R F[3], R out[19], R* tau_out, R u_out[3]) {
+  using std::sqrt;
+  const Tables& t = T();
+  R rho = 0.0 * f[0], j[3] = {0.0 * f[0], 0.0 * f[0], 0.0 * f[0]};
+  for (int i = 0; i < 19; ++i) {
+    rho = rho + f[i];
+    for (int a = 0; a < 3; ++a) j[a] = j[a] + f[i] * C[i][a];
+  }
+  R u[3];
+  for (int a = 0; a < 3; ++a) u[a] = (g_mutation == 4) ? j[a] / rho : (j[a] + 0.5 * F[a]) / rho; /* Eq. (11) */
+  /* Eq. (7): m = M f */
+  R m[19];
+  for (int k = 0; k < 19; ++k) {
+    R acc = 0.0 * f[0];
+    for (int i = 0; i < 19; ++i) acc = acc + t.M[k][i] * f[i];
+    m[k] = acc;
+  }
+  R meq[19];
+  meq_moments(rho, u, meq);
+  /* Eq. (12) and Pi = Pi_eq + Pi_neq with Pi_eq = rho cs^2 I + rho u u */
+  R Pn[3][3];
+  for (int a = 0; a < 3; ++a)
+    for (int b = 0; b < 3; ++b) {
+      R acc = 0.0 * f[0];
+      for (int i = 0; i < 19; ++i) acc = acc + f[i] * (double)(C[i][a] * C[i][b]);
+      Pn[a][b] = acc - rho * u[a] * u[b] - (a == b ? rho * CS2 : 0.0 * rho);
+    }
+  R q2 = 0.0 * f[0];
+  for (int a = 0; a < 3; ++a)
+    for (int b = 0; b < 3; ++b) q2 = q2 + Pn[a][b] * Pn[a][b];
+  R Qhalf = safe_norm(q2);
+  R tau = tau_eff_of(Qhalf, rho, cfg.tau0, cfg.cs_smag);
+  if (tau_out) *tau_out = tau;
+  R S[19];
+  for (int k = 0; k < 19; ++k) S[k] = cfg.s[k] + 0.0 * f[0];
+  const int visc[5] = {9, 11, 13, 14, 15}; /* Sec. II.A: tau_k set */
+  for (int k = 0; k < 5; ++k) S[visc[k]] = 1.0 / tau;
+  /* Eq. (9) projected to moments (reading R4) */
+  R Fb[19], Fm[19];
+  guo_populations(u, F, Fb);
+  for (int k = 0; k < 19; ++k) {
+    R acc = 0.0 * f[0];
+    for (int i = 0; i < 19; ++i) acc = acc + t.M[k][i] * Fb[i];
+    Fm[k] = acc;
+  }
+  /* Eq. (6): relax in moment space, then back to populations */
+  R ms[19];
+  for (int k = 0; k < 19; ++k) ms[k] = m[k] - S[k] * (m[k] - meq[k]) + (1.0 - 0.5 * S[k]) * Fm[k];
+  for (int i = 0; i < 19; ++i) {
+    R acc = 0.0 * f[0];
+    for (int k = 0; k < 19; ++k) acc = acc + t.Minv[i][k] * ms[k];
+    out[i] = acc;
+  }
+  if (u_out)
+    for (int a = 0; a < 3; ++a) u_out[a] = u[a];
+}
+
+/* ---- Sec. II.C, Eq. (16) with reading R6 ---- */
+template <class R>
+R uplus(const R& yp, double kappa, double B) {
+  using std::exp;
+  using std::log;
+  if (g_mutation == 5) return 2.5 * log(1.0 + 0.4 * yp) + 7.8 * (1.0 - exp(-yp / 11.0)) - yp * exp(-yp / 3.0);
+  return log(1.0 + kappa * yp) / kappa + B * (1.0 - exp(-yp / 11.0) - (yp / 11.0) * exp(-yp / 3.0));
+}
+template <class R>
+R duplus(const R& yp, double kappa, double B) {
+  using std::exp;
+  return 1.0 / (1.0 + kappa * yp) +
+         B * (exp(-yp / 11.0) / 11.0 - exp(-yp / 3.0) / 11.0 + (yp / 33.0) * exp(-yp / 3.0));
+}
+
+/* ---- Sec. II.C, Eq. (20): u_tau u+(y u_tau / nu) = |u_hat| by Newton (R11) ---- */
+template <class R>
+int solve_utau(const R& ua, double y, double nu, const oracle_cfg& cfg, R* out) {
+  using std::sqrt;
+  R ut = sqrt(nu * ua / y);
+  for (int it = 0; it < cfg.newton_max; ++it) {
+    R yp = y * ut / nu;
+    R up = uplus(yp, cfg.kappa, cfg.b_reich);
+    R g = ut * up - ua;
+    R dg = up + yp * duplus(yp, cfg.kappa, cfg.b_reich);
+    R du = g / dg;
+    ut = ut - du;
+    if (std::fabs(val(du)) <= cfg.newton_tol * std::fabs(val(ut))) {
+      yp = y * ut / nu;
+      up = uplus(yp, cfg.kappa, cfg.b_reich);
+      g = ut * up - ua;
+      dg = up + yp * duplus(yp, cfg.kappa, cfg.b_reich);
+      ut = ut - g / dg; /* one more step: exact implicit-function derivative */
+      *out = ut;
+      return OR_OK;
+    }
+  }
+  *out = ut;
+  return OR_ERR_NEWTON;
+}
+
+/* ---- Sec. II.C, Eq. (18)-(21): wall force in a first off-wall cell (R10) ---- */
+template <class R>
+int wall_force(const oracle_cfg& cfg, const R& rho_w, const R uw[3], const R u2[3], int top, R F[3],
+               R* utau_out) {
+  using std::sqrt;
+  const double n[3] = {0.0, top ? -1.0 : 1.0, 0.0};
+  for (int a = 0; a < 3; ++a) F[a] = 0.0 * rho_w;
+  if (utau_out) *utau_out = 0.0 * rho_w;
+  R un = u2[0] * n[0] + u2[1] * n[1] + u2[2] * n[2];
+  R tv[3];
+  for (int a = 0; a < 3; ++a) tv[a] = u2[a] - un * n[a];
+  R tn2 = tv[0] * tv[0] + tv[1] * tv[1] + tv[2] * tv[2];
+  if (val(tn2) == 0.0) return OR_OK;
+  R tn = sqrt(tn2);
+  R e[3];
+  for (int a = 0; a < 3; ++a) e[a] = tv[a] / tn; /* Eq. (18) */
+  R uhat = uw[0] * e[0] + uw[1] * e[1] + uw[2] * e[2]; /* Eq. (19) */
+  if (val(uhat) == 0.0) return OR_OK;
+  const double sgn = val(uhat) > 0.0 ? 1.0 : -1.0;
+  R ua = sgn * uhat;
+  const double nu0 = (cfg.tau0 - 0.5) * CS2; /* Eq. (5) */
+  R ut;
+  int st = solve_utau(ua, cfg.y_wall, nu0, cfg, &ut);
+  R tauw = rho_w * ut * ut; /* tau_w = rho u_tau^2 */
+  for (int a = 0; a < 3; ++a) F[a] = -sgn * tauw * e[a]; /* Eq. (21), A = 1 */
+  if (utau_out) *utau_out = ut;
+  return st;
+}
+
+/* ---- Sec. III.A, Eq. (26)-(31): regularised inlet populations (R7, R8) ---- */
+template <class R>
+void inlet_regularize(const R f[19], const R uin[3], R out[19], R* rho_in_out) {
+  const Tables& t = T();
+  R rho0 = 0.0 * f[9], rhom = 0.0 * f[9];
+  for (int i = 0; i < 19; ++i) {
+    if (C[i][0] == 0) rho0 = rho0 + f[i];
+    if (C[i][0] < 0) rhom = rhom + f[i];
+  }
+  R rho_in = (g_mutation == 6) ? (2.0 * rho0 + rhom) / (1.0 + uin[0]) : (rho0 + 2.0 * rhom) / (1.0 - uin[0]);
+  R feq[19];
+  feq_poly(rho_in, uin, feq);
+  R fneq[19];
+  for (int i = 0; i < 19; ++i)
+    if (C[i][0] <= 0) fneq[i] = f[i] - feq[i];
+  for (int i = 0; i < 19; ++i)
+    if (C[i][0] > 0) fneq[i] = fneq[t.opp[i]];
+  R Pi[3][3];
+  for (int a = 0; a < 3; ++a)
+    for (int b = 0; b < 3; ++b) {
+      R acc = 0.0 * f[9];
+      for (int i = 0; i < 19; ++i) acc = acc + ((double)(C[i][a] * C[i][b]) - (a == b ? CS2 : 0.0)) * fneq[i];
+      Pi[a][b] = acc; /* Eq. (29) */
+    }
+  const double fac = (g_mutation == 7) ? 1.0 / (CS2 * CS2) : 1.0 / (2.0 * CS2 * CS2);
+  for (int i = 0; i < 19; ++i) {
+    R qp = 0.0 * f[9];
+    for (int a = 0; a < 3; ++a)
+      for (int b = 0; b < 3; ++b) qp = qp + ((double)(C[i][a] * C[i][b]) - (a == b ? CS2 : 0.0)) * Pi[a][b];
+    out[i] = feq[i] + t.W[i] * fac * qp; /* Eq. (26), (28) */
+  }
+  if (rho_in_out) *rho_in_out = rho_in;
+}
+
+/* ---- Sec. III.A, Eq. (24): Cholesky factor of R, [a11 a21 a22 a31 a32 a33] ---- */
+void cholesky(const double R6[6], double a[6]) {
+  /* R6 = R11 R21 R22 R31 R32 R33 */
+  a[0] = std::sqrt(R6[0]);
+  a[1] = R6[1] / a[0];
+  a[2] = std::sqrt(R6[2] - a[1] * a[1]);
+  a[3] = R6[3] / a[0];
+  a[4] = (R6[4] - a[1] * a[3]) / a[2];
+  a[5] = std::sqrt(R6[5] - a[3] * a[3] - a[4] * a[4]);
+}
+
+/* ---- Sec. III.A, Eq. (22)-(25): STG inlet velocity plane at time t (R12) ---- */
+int stg_plane(const oracle_cfg& cfg, const oracle_stg& s, double t, double* uin, double* fluct) {
+  const int ny = cfg.ny, nz = cfg.nz, N = s.n_modes;
+  int st = OR_OK;
+  for (int y = 0; y < ny; ++y) {
+    double R6[6], a[6];
+    for (int k = 0; k < 6; ++k) R6[k] = s.R[k * ny + y];
+    cholesky(R6, a);
+    const double sb = s.amp_bin[s.bin_of_y[y]];
+    const double yc = y + 0.5;
+    for (int z = 0; z < nz; ++z) {
+      double v[3] = {0, 0, 0};
+      for (int n = 0; n < N; ++n) {
+        const double ph = s.kmag[n] * (s.d[1 * N + n] * yc + s.d[2 * N + n] * z) + s.omega[n] * t + s.phi[n];
+        const double c = std::cos(ph);
+        const double amp = std::sqrt(6.0 * s.q[n]); /* Eq. (25): sqrt(6) sqrt(q^n) */
+        for (int a3 = 0; a3 < 3; ++a3) v[a3] += amp * s.sigma[a3 * N + n] * c;
+      }
+      /* Eq. (23): u' = a v' (lower triangular a), scaled by s_b */
+      double up[3];
+      up[0] = a[0] * v[0];
+      up[1] = a[1] * v[0] + a[2] * v[1];
+      up[2] = a[3] * v[0] + a[4] * v[1] + a[5] * v[2];
+      for (int a3 = 0; a3 < 3; ++a3) {
+        const size_t o = ((size_t)a3 * ny + y) * nz + z;
+        uin[o] = s.u_rans[a3 * ny + y] + sb * up[a3]; /* Eq. (22) */
+        if (fluct) fluct[o] = up[a3];
+      }
+      /* Sec. III.A: |u_in . n| < 0.3 c_s */
+      if (!(std::fabs(uin[((size_t)0 * ny + y) * nz + z]) < 0.3 * std::sqrt(CS2))) st = OR_ERR_MACH;
+    }
+  }
+  return st;
+}
+
+/* ---- state access ---- */
+struct Ctx {
+  const oracle_cfg* cfg;
+  const double* f;     /* [19][nx][ny][nz] post-collision state s_n */
+  const double* hist;  /* [5][ny][nz] outlet history (post-boundary f at x = nx-1, c_x < 0) */
+  const double* uin;   /* [3][ny][nz] inlet velocity at t_{n+1} */
+  size_t N;
+  int nx, ny, nz;
+  size_t at(int i, int x, int y, int z) const { return (size_t)i * N + ((size_t)x * ny + y) * nz + z; }
+};
+
+const int OUT5[5] = {1, 5, 8, 11, 15}; /* directions with c_x < 0, outlet history order */
+
+/* Sec. II.A, Eq. (3): pull streaming with the wall rules (Sec. II.C, IV.A). */
+bool pulled(const Ctx& c, int i, int x, int y, int z, double* v) {
+  const oracle_cfg& cf = *c.cfg;
+  const Tables& t = T();
+  int xs = x - C[i][0], ys = y - C[i][1];
+  int zs = ((z - C[i][2]) % c.nz + c.nz) % c.nz; /* periodic span */
+  if (cf.xbc == 0) xs = (xs % c.nx + c.nx) % c.nx;
+  if (ys < 0 || ys >= c.ny) {
+    if (cf.ywall == 0) {
+      ys = (ys % c.ny + c.ny) % c.ny;
+    } else if (cf.ywall == 1) { /* halfway bounce-back: the population that left towards the wall */
+      *v = c.f[c.at(t.opp[i], x, y, z)];
+      return true;
+    } else { /* specular reflection at the halfway wall */
+      if (xs < 0 || xs >= c.nx) return false;
+      *v = c.f[c.at(t.refl_y[i], xs, y, zs)];
+      return true;
+    }
+  }
+  if (xs < 0 || xs >= c.nx) return false;
+  *v = c.f[c.at(i, xs, ys, zs)];
+  return true;
+}
+
+/* Post-streaming, post-boundary populations of one node (Algorithm 1 inlet branch). */
+void post_boundary(const Ctx& c, int x, int y, int z, double fo[19], double hist_new[5], bool* is_outlet) {
+  const oracle_cfg& cf = *c.cfg;
+  for (int i = 0; i < 19; ++i) {
+    double v = 0.0;
+    fo[i] = pulled(c, i, x, y, z, &v) ? v : 0.0;
+  }
+  *is_outlet = false;
+  if (cf.xbc == 1 && x == c.nx - 1) { /* convective outlet (R13) */
+    *is_outlet = true;
+    for (int k = 0; k < 5; ++k) {
+      const int i = OUT5[k];
+      double up = 0.0;
+      pulled(c, i, x - 1, y, z, &up);
+      const double prev = c.hist[((size_t)k * c.ny + y) * c.nz + z];
+      fo[i] = (prev + cf.u_conv * up) / (1.0 + cf.u_conv);
+      hist_new[k] = fo[i];
+    }
+  }
+  if (cf.xbc == 1 && x == 0) { /* STG inlet, Algorithm 1 steps 6-7 */
+    double u[3];
+    for (int a = 0; a < 3; ++a) u[a] = c.uin[((size_t)a * c.ny + y) * c.nz + z];
+    double out[19];
+    inlet_regularize(fo, u, out, (double*)nullptr);
+    for (int i = 0; i < 19; ++i) fo[i] = out[i];
+  }
+}
+
+void pre_force_velocity(const double f[19], double* rho, double u[3]) {
+  double r = 0, j[3] = {0, 0, 0};
+  for (int i = 0; i < 19; ++i) {
+    r += f[i];
+    for (int a = 0; a < 3; ++a) j[a] += f[i] * C[i][a];
+  }
+  *rho = r;
+  for (int a = 0; a < 3; ++a) u[a] = j[a] / r;
+}
+
+bool is_wall_cell(const oracle_cfg& cf, int y) {
+  return cf.wall_model == 1 && cf.ywall != 0 && (y == 0 || y == cf.ny - 1);
+}
+
+/* One node of Algorithm 1: boundaries, wall branch, stream-collide.  Returns status. */
+int node_update(const Ctx& c, int x, int y, int z, double out[19], double hist_new[5], bool* is_outlet,
+                double u_stat[3]) {
+  const oracle_cfg& cf = *c.cfg;
+  double f[19];
+  post_boundary(c, x, y, z, f, hist_new, is_outlet);
+  double rho, uw[3];
+  pre_force_velocity(f, &rho, uw);
+  double F[3] = {rho * cf.g[0], rho * cf.g[1], rho * cf.g[2]}; /* R9 */
+  int st = OR_OK;
+  if (is_wall_cell(cf, y)) { /* Algorithm 1 steps 9-14 */
+    const int top = (y == cf.ny - 1);
+    const int y2 = top ? y - 1 : y + 1;
+    double f2[19], h2[5], rho2, u2[3];
+    bool o2;
+    post_boundary(c, x, y2, z, f2, h2, &o2);
+    pre_force_velocity(f2, &rho2, u2);
+    double Fw[3];
+    st = wall_force(cf, rho, uw, u2, top, Fw, (double*)nullptr);
+    for (int a = 0; a < 3; ++a) F[a] += Fw[a];
+  }
+  double tau;
+  collide(cf, f, F, out, &tau, u_stat);
+  if (!(rho > 0.0) || !std::isfinite(rho)) st = OR_ERR_NONFINITE;
+  for (int i = 0; i < 19; ++i)
+    if (!std::isfinite(out[i])) st = OR_ERR_NONFINITE;
+  return st;
+}
+
+bool cfg_ok(const oracle_cfg* cf) {
+  if (!cf || cf->nx < 1 || cf->ny < 1 || cf->nz < 1) return false;
+  if (cf->xbc == 1 && cf->nx < 3) return false;
+  if (cf->wall_model == 1 && cf->ny < 3) return false;
+  if (!(cf->tau0 > 0.5)) return false;
+  return true;
+}
+
+}  // namespace
+
+extern "C" {
+
+/* ---------------- small building blocks, exported for the pins ---------------- */
+
+void oracle_set_mutation(int k) { g_mutation = k; }
+
+void oracle_tables(int32_t* c /*[19][3]*/, double* w /*[19]*/, double* M /*[19][19]*/, double* Minv,
+                   int32_t* opp, int32_t* refl) {
+  const Tables& t = T();
+  for (int i = 0; i < 19; ++i) {
+    for (int a = 0; a < 3; ++a) c[i * 3 + a] = C[i][a];
+    w[i] = t.W[i];
+    opp[i] = t.opp[i];
+    refl[i] = t.refl_y[i];
+    for (int k = 0; k < 19; ++k) {
+      M[i * 19 + k] = t.M[i][k];
+      Minv[i * 19 + k] = t.Minv[i][k];
+    }
+  }
+}
+
+void oracle_feq(double rho, const double* u, double* out) { feq_poly(rho, u, out); }
+void oracle_meq(double rho, const double* u, double* out) { meq_moments(rho, u, out); }
+void oracle_guo(const double* u, const double* F, double* out) { guo_populations(u, F, out); }
+
+void oracle_collide_node(const oracle_cfg* cfg, const double* f, const double* F, double* out, double* tau_eff,
+                         double* u) {
+  collide(*cfg, f, F, out, tau_eff, u);
+}
+
+double oracle_tau_eff(double Qhalf, double rho, double tau0, double cs_smag) {
+  return tau_eff_of(Qhalf, rho, tau0, cs_smag);
+}
+
+double oracle_uplus(double yp, double kappa, double B) { return uplus(yp, kappa, B); }
+double oracle_duplus(double yp, double kappa, double B) { return duplus(yp, kappa, B); }
+
+int oracle_utau(const oracle_cfg* cfg, double uhat_abs, double* ut) {
+  const double nu0 = (cfg->tau0 - 0.5) * CS2;
+  return solve_utau(uhat_abs, cfg->y_wall, nu0, *cfg, ut);
+}
+
+int oracle_wall_force(const oracle_cfg* cfg, double rho_w, const double* uw, const double* u2, int top,
+                      double* F, double* utau) {
+  return wall_force(*cfg, rho_w, uw, u2, top, F, utau);
+}
+
+void oracle_inlet_node(const double* f, const double* uin, double* out, double* rho_in) {
+  inlet_regularize(f, uin, out, rho_in);
+}
+
+void oracle_cholesky(const double* R6, double* a) { cholesky(R6, a); }
+
+int oracle_stg_plane(const oracle_cfg* cfg, const oracle_stg* s, double t, double* uin, double* fluct) {
+  if (!cfg_ok(cfg) || !s) return OR_ERR_ARG;
+  return stg_plane(*cfg, *s, t, uin, fluct);
+}
+
+/* Reichardt inflow U(y) = u_tau u+(d u_tau / nu0), d the distance to the nearer wall. */
+void oracle_reichardt_inflow(const oracle_cfg* cfg, double u_tau, double* u_rans /*[3][ny]*/) {
+  const int ny = cfg->ny;
+  const double nu0 = (cfg->tau0 - 0.5) * CS2;
+  for (int y = 0; y < ny; ++y) {
+    const double d = std::fmin(y + 0.5, ny - y - 0.5);
+    u_rans[y] = u_tau * uplus(d * u_tau / nu0, cfg->kappa, cfg->b_reich);
+    u_rans[ny + y] = 0.0;
+    u_rans[2 * ny + y] = 0.0;
+  }
+}
+
+/* ---------------- whole-lattice operations ---------------- */
+
+/* f_i = f_eq_i(rho, u) + eps w_i pert_i; outlet history from the same state. */
+int oracle_init(const oracle_cfg* cfg, const double* rho /*[N] or NULL*/, const double* u /*[3][N]*/,
+                const double* pert /*[19][N] or NULL*/, double eps, double* f, double* hist) {
+  if (!cfg_ok(cfg)) return OR_ERR_ARG;
+  const Tables& t = T();
+  const int nx = cfg->nx, ny = cfg->ny, nz = cfg->nz;
+  const size_t N = (size_t)nx * ny * nz;
+#pragma omp parallel for schedule(static)
+  for (long long n = 0; n < (long long)N; ++n) {
+    double uu[3] = {u[n], u[N + n], u[2 * N + n]}, fe[19];
+    const double r = rho ? rho[n] : 1.0;
+    feq_poly(r, uu, fe);
+    for (int i = 0; i < 19; ++i) f[(size_t)i * N + n] = fe[i] + (pert ? eps * t.W[i] * pert[(size_t)i * N + n] : 0.0);
+  }
+  if (hist)
+    for (int k = 0; k < 5; ++k)
+      for (int y = 0; y < ny; ++y)
+        for (int z = 0; z < nz; ++z)
+          hist[((size_t)k * ny + y) * nz + z] = f[(size_t)OUT5[k] * N + ((size_t)(nx - 1) * ny + y) * nz + z];
+  return OR_OK;
+}
+
+/* Streaming with wall rules only; unset populations (outside the x range) are -1. */
+int oracle_stream_only(const oracle_cfg* cfg, const double* fin, double* fout) {
+  if (!cfg_ok(cfg)) return OR_ERR_ARG;
+  Ctx c{cfg, fin, nullptr, nullptr, (size_t)cfg->nx * cfg->ny * cfg->nz, cfg->nx, cfg->ny, cfg->nz};
+#pragma omp parallel for collapse(2) schedule(static)
+  for (int x = 0; x < c.nx; ++x)
+    for (int y = 0; y < c.ny; ++y)
+      for (int z = 0; z < c.nz; ++z)
+        for (int i = 0; i < 19; ++i) {
+          double v;
+          fout[c.at(i, x, y, z)] = pulled(c, i, x, y, z, &v) ? v : -1.0;
+        }
+  return OR_OK;
+}
+
+/*
+ * One full step s_n -> s_{n+1} (Algorithm 1).  t_next is the STG time of the
+ * new state.  hist_in/hist_out: outlet history (may not alias).  Statistics:
+ * for each x in planes[], acc[p][y][0..8] += sum over z of
+ * (u, v, w, uu, vv, ww, uv, uw, vw) with the force-corrected velocity.
+ */
+int oracle_step(const oracle_cfg* cfg, const oracle_stg* stg, double t_next, const double* fin, double* fout,
+                const double* hist_in, double* hist_out, const int32_t* planes, int32_t n_planes, double* acc) {
+  if (!cfg_ok(cfg) || !fin || !fout) return OR_ERR_ARG;
+  if (cfg->xbc == 1 && (!stg || !hist_in || !hist_out)) return OR_ERR_ARG;
+  const int nx = cfg->nx, ny = cfg->ny, nz = cfg->nz;
+  std::vector<double> uin;
+  int st_all = OR_OK;
+  if (cfg->xbc == 1) {
+    uin.resize((size_t)3 * ny * nz);
+    int st = stg_plane(*cfg, *stg, t_next, uin.data(), nullptr);
+    if (st != OR_OK) st_all = st;
+  }
+  Ctx c{cfg, fin, hist_in, uin.empty() ? nullptr : uin.data(), (size_t)nx * ny * nz, nx, ny, nz};
+  std::vector<int> plane_of(nx, -1);
+  for (int p = 0; p < n_planes; ++p)
+    if (planes[p] >= 0 && planes[p] < nx) plane_of[planes[p]] = p;
+  int st_err = OR_OK;
+#pragma omp parallel for collapse(2) schedule(static)
+  for (int x = 0; x < nx; ++x)
+    for (int y = 0; y < ny; ++y) {
+      double sums[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+      int st_local = OR_OK;
+      for (int z = 0; z < nz; ++z) {
+        double out[19], hn[5], u[3];
+        bool is_out;
+        int st = node_update(c, x, y, z, out, hn, &is_out, u);
+        if (st != OR_OK) st_local = st;
+        for (int i = 0; i < 19; ++i) fout[c.at(i, x, y, z)] = out[i];
+        if (is_out)
+          for (int k = 0; k < 5; ++k) hist_out[((size_t)k * ny + y) * nz + z] = hn[k];
+        sums[0] += u[0];
+        sums[1] += u[1];
+        sums[2] += u[2];
+        sums[3] += u[0] * u[0];
+        sums[4] += u[1] * u[1];
+        sums[5] += u[2] * u[2];
+        sums[6] += u[0] * u[1];
+        sums[7] += u[0] * u[2];
+        sums[8] += u[1] * u[2];
+      }
+      if (plane_of[x] >= 0 && acc)
+        for (int k = 0; k < 9; ++k) acc[((size_t)plane_of[x] * ny + y) * 9 + k] += sums[k];
+      if (st_local != OR_OK) {
+#pragma omp critical
+        st_err = st_local;
+      }
+    }
+  return st_err != OR_OK ? st_err : st_all;
+}
+
+/*
+ * The same update evaluated at a list of nodes only (for comparisons at full
+ * lattice sizes): out[19][n_nodes], u_out[3][n_nodes] (force-corrected u).
+ */
+int oracle_step_nodes(const oracle_cfg* cfg, const oracle_stg* stg, double t_next, const double* fin,
+                      const double* hist_in, int64_t n_nodes, const int64_t* nodes, double* out, double* u_out) {
+  if (!cfg_ok(cfg) || !fin) return OR_ERR_ARG;
+  if (cfg->xbc == 1 && (!stg || !hist_in)) return OR_ERR_ARG;
+  const int nx = cfg->nx, ny = cfg->ny, nz = cfg->nz;
+  std::vector<double> uin;
+  int st_all = OR_OK;
+  if (cfg->xbc == 1) {
+    uin.resize((size_t)3 * ny * nz);
+    st_all = stg_plane(*cfg, *stg, t_next, uin.data(), nullptr);
+  }
+  Ctx c{cfg, fin, hist_in, uin.empty() ? nullptr : uin.data(), (size_t)nx * ny * nz, nx, ny, nz};
+  int st_err = OR_OK;
+#pragma omp parallel for schedule(dynamic, 64)
+  for (long long k = 0; k < (long long)n_nodes; ++k) {
+    const int64_t n = nodes[k];
+    const int z = (int)(n % nz), y = (int)((n / nz) % ny), x = (int)(n / ((int64_t)nz * ny));
+    double o[19], hn[5], u[3];
+    bool is_out;
+    int st = node_update(c, x, y, z, o, hn, &is_out, u);
+    if (st != OR_OK) {
+#pragma omp critical
+      st_err = st;
+    }
+    for (int i = 0; i < 19; ++i) out[(size_t)i * n_nodes + k] = o[i];
+    if (u_out)
+      for (int a = 0; a < 3; ++a) u_out[(size_t)a * n_nodes + k] = u[a];
+  }
+  return st_err != OR_OK ? st_err : st_all;
+}
+
+/* Macroscopic fields without force: rho = sum f, u = sum f c / rho. */
+void oracle_macro(const oracle_cfg* cfg, const double* f, double* rho, double* u) {
+  const size_t N = (size_t)cfg->nx * cfg->ny * cfg->nz;
+#pragma omp parallel for schedule(static)
+  for (long long n = 0; n < (long long)N; ++n) {
+    double fl[19], r, uu[3];
+    for (int i = 0; i < 19; ++i) fl[i] = f[(size_t)i * N + n];
+    pre_force_velocity(fl, &r, uu);
+    rho[n] = r;
+    for (int a = 0; a < 3; ++a) u[(size_t)a * N + n] = uu[a];
+  }
+}
+
+}  // extern "C"
+
+extern "C" {
+/* nsteps steps from t0 (STG time t0 + n + 1 for step n); f and hist updated in place. */
+int oracle_run(const oracle_cfg* cfg, const oracle_stg* stg, double t0, int32_t nsteps, double* f, double* hist,
+               const int32_t* planes, int32_t n_planes, double* acc) {
+  if (!cfg_ok(cfg) || !f) return OR_ERR_ARG;
+  const size_t N = (size_t)cfg->nx * cfg->ny * cfg->nz;
+  std::vector<double> tmp(19 * N), htmp(hist ? (size_t)5 * cfg->ny * cfg->nz : 0);
+  int st_all = OR_OK;
+  for (int n = 0; n < nsteps; ++n) {
+    if (hist) std::memcpy(htmp.data(), hist, htmp.size() * sizeof(double));
+    int st = oracle_step(cfg, stg, t0 + n + 1, f, tmp.data(), hist, hist ? htmp.data() : nullptr, planes,
+                         n_planes, acc);
+    if (st != OR_OK) st_all = st;
+    std::memcpy(f, tmp.data(), 19 * N * sizeof(double));
+    if (hist) std::memcpy(hist, htmp.data(), htmp.size() * sizeof(double));
+  }
+  return st_all;
+}
+}  // extern "C"
