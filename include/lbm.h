@@ -1,0 +1,208 @@
+/*
+ * lbm.h - C ABI of the MI355X (gfx950) library for the wall-modelled MRT
+ * lattice Boltzmann channel with a synthetic-turbulence-generator inlet
+ * (Xue, Yao, Davidson, arXiv 2304.04214).
+ *
+ * Conventions
+ *  - Every call returns lbm_status (0 = LBM_OK).  Nothing throws or aborts
+ *    across the ABI.  Argument and shape errors are returned synchronously;
+ *    errors detected on the device (non-finite or non-positive density, inlet
+ *    Mach limit) are latched in a device word and returned by lbm_sync() or
+ *    lbm_stats(LBM_STATS_READ).
+ *  - Pointers named "device" are HIP device pointers.  Population and
+ *    outlet-history buffers are CALLER-OWNED: the library never frees them,
+ *    and they must outlive the work enqueued on them.  The handle owns only
+ *    small tables (STG trigonometric tables, Cholesky factors, statistics
+ *    accumulators, an error word).
+ *  - All work is enqueued, in order, on the HIP stream given to lbm_create()
+ *    (asynchronous to the host).  A handle is not thread-safe.
+ *  - Lattice: x streamwise (nx), y wall-normal (ny), z spanwise (nz, periodic).
+ *    Node (x, y, z) has linear index n = (x*ny + y)*nz + z.  Populations are
+ *    stored structure-of-arrays: population i of node n at element i*N + n,
+ *    N = nx*ny*nz, with i the D3Q19 index in the paper's order (Sec. II.A,
+ *    Eq. (1): lexicographic in (c_z, c_y, c_x), opposite of i is 18 - i).
+ *    The stored state is the post-collision population set s_n of time n.
+ */
+#ifndef LBM_H
+#define LBM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct lbm_ctx* lbm_handle;
+
+typedef enum {
+  LBM_OK = 0,
+  LBM_ERR_ARG = 1,       /* bad argument (NULL, out of range, unsupported combination) */
+  LBM_ERR_SHAPE = 2,     /* sizes out of range or buffers misaligned */
+  LBM_ERR_HIP = 3,       /* a HIP runtime call failed */
+  LBM_ERR_MACH = 4,      /* inlet |u_in,x| >= 0.3 c_s (Sec. III.A, below Eq. (30)) */
+  LBM_ERR_NONFINITE = 5, /* a node's density became non-finite or non-positive */
+  LBM_ERR_STATE = 6      /* call out of order (no STG bound, statistics not attached, ...) */
+} lbm_status;
+
+enum { LBM_STORE_F32 = 0, LBM_STORE_F16DEV = 1 };
+enum { LBM_Y_PERIODIC = 0, LBM_Y_BOUNCEBACK = 1, LBM_Y_SLIP = 2 };
+enum { LBM_X_PERIODIC = 0, LBM_X_INFLOW = 1 };
+enum { LBM_STATS_ATTACH = 1, LBM_STATS_DETACH = 2, LBM_STATS_RESET = 3, LBM_STATS_READ = 4 };
+
+/*
+ * Problem statement (Sec. II, Sec. IV.A).
+ *  storage     LBM_STORE_F32: populations as float.  LBM_STORE_F16DEV:
+ *              populations stored as IEEE half deviations h_i = f_i - w_i
+ *              (rounded to nearest even); collision is computed in float.
+ *  ywall       walls halfway below y = 0 and above y = ny-1: LBM_Y_SLIP is the
+ *              paper's slip wall (specular reflection), LBM_Y_BOUNCEBACK is
+ *              halfway bounce-back; LBM_Y_PERIODIC has no walls.
+ *  xbc         LBM_X_INFLOW: STG inlet at x = 0 (regularised populations,
+ *              Sec. III.A, Eq. (26)-(31)) and convective outlet at x = nx-1
+ *              for c_x < 0: f_i = (f_i^prev + u_conv f_i(x-1)) / (1 + u_conv).
+ *  wall_model  1: Reichardt wall force in the first off-wall cells (Sec. II.C,
+ *              Eq. (16)-(21)), u_tau by newton_iters Newton steps.
+ *  tau0        molecular relaxation time (> 1/2), nu0 = (tau0 - 1/2)/3 (Eq. (5)).
+ *  cs_smag     Smagorinsky C_s, C_smag = C_s^2 (Sec. II.B).  0 disables it.
+ *  s[19]       MRT relaxation rates (Appendix A.1); s[9], s[11], s[13], s[14],
+ *              s[15] are replaced per node by 1/tau_eff (Eq. (15)).
+ *  kappa, b_reich, y_wall  Reichardt constants (0.41, 7.8) and the distance of
+ *              the first cell centre from the wall (0.5).
+ *  u_conv      outlet convection speed.
+ *  g[3]        uniform body acceleration; force density rho g (Eq. (9), (11)).
+ */
+typedef struct {
+  int32_t nx, ny, nz;
+  int32_t storage;
+  int32_t ywall;
+  int32_t xbc;
+  int32_t wall_model;
+  int32_t newton_iters;
+  double tau0;
+  double cs_smag;
+  double s[19];
+  double kappa, b_reich, y_wall;
+  double u_conv;
+  double g[3];
+} lbm_config;
+
+/*
+ * Inlet synthetic turbulence (Sec. III.A, Eq. (22)-(25)).  All pointers are
+ * device pointers; the arrays are read when the table is bound (every call
+ * that receives a non-NULL lbm_stg binds it again).
+ *  q[N], sigma[3][N], kmag[N], d[3][N], phi[N], omega[N]   mode table: weights
+ *      (sum 1), unit amplitude directions (sigma . d = 0), wavenumbers, unit
+ *      wave directions, phases, temporal frequencies (rad per step).  The mode
+ *      phase at inlet node (y, z) and time t is
+ *      kmag (d_y (y + 1/2) + d_z z) + omega t + phi.
+ *  u_rans[3][ny]  mean inflow;  R[6][ny] Reynolds stresses (R11 R21 R22 R31 R32 R33,
+ *      symmetric positive definite); amp_bin[n_bins] amplitude scalings s_b;
+ *      bin_of_y[ny] bin of each row.  u' = s_b(y) a(y) v', a = chol(R).
+ *  u_in[3][ny][nz]   (written) inlet velocity plane;  fluct[3][ny][nz] (written,
+ *      optional, may be NULL) a(y) v' before the s_b scaling.
+ *  1 <= n_modes <= LBM_MAX_MODES.
+ */
+#define LBM_MAX_MODES 1024
+typedef struct {
+  int32_t n_modes, n_bins;
+  const double *q, *sigma, *kmag, *d, *phi, *omega;
+  const double *u_rans, *R, *amp_bin;
+  const int32_t* bin_of_y;
+  float* u_in;
+  float* fluct;
+} lbm_stg;
+
+/*
+ * Create a handle.  f_a, f_b: device population buffers of 19*N elements
+ * (float for LBM_STORE_F32, 16-bit for LBM_STORE_F16DEV), 256-byte aligned;
+ * the state lives in f_a first and moves between the two each step.
+ * hist_a, hist_b: device float buffers [5][ny][nz] for the outlet history
+ * (required when xbc = LBM_X_INFLOW, else may be NULL), alternating with the
+ * populations.  hip_stream: the hipStream_t all work goes on (NULL = default).
+ * Limits: nx >= 1 (>= 3 with LBM_X_INFLOW), ny >= 4, nz >= 1, N < 2^31.
+ */
+lbm_status lbm_create(const lbm_config* cfg, void* f_a, void* f_b, float* hist_a, float* hist_b,
+                      void* hip_stream, lbm_handle* out);
+lbm_status lbm_destroy(lbm_handle h);
+
+/* Point the handle at another pair of buffers (checkpoint restore); the state
+   is taken to be in f_a / hist_a at time index `time`. */
+lbm_status lbm_set_state(lbm_handle h, void* f_a, void* f_b, float* hist_a, float* hist_b, int64_t time);
+/* The buffers that currently hold the state, and its time index n. */
+lbm_status lbm_get_state(lbm_handle h, void** f_cur, float** hist_cur, int64_t* time);
+
+/*
+ * Initial state f_i = f_eq_i(rho, u) + eps w_i pert_i (second-order
+ * equilibrium, Sec. III.A Eq. (27)), written into the current buffer; the
+ * outlet history is taken from the same state at x = nx-1.  rho [N] (NULL:
+ * 1), u [3][N], pert [19][N] (NULL: none): device float arrays.
+ */
+lbm_status lbm_init_equilibrium(lbm_handle h, const float* rho, const float* u, const float* pert, float eps);
+
+/* Mean inflow U(y) = u_tau u+(d u_tau / nu0), d = min(y + 1/2, ny - y - 1/2),
+   with the Reichardt law of Sec. II.C; writes device double u_rans[3][ny]. */
+lbm_status lbm_inflow_reichardt(lbm_handle h, double u_tau, double* u_rans);
+
+/*
+ * Inlet velocity at time t (Algorithm 1 steps 4-5, Eq. (22)-(25)) into
+ * stg->u_in (and stg->fluct).  Binds stg when non-NULL.  Mach violations are
+ * latched (LBM_ERR_MACH at the next lbm_sync()).
+ */
+lbm_status stg_inlet_fill(lbm_handle h, const lbm_stg* stg, double t);
+
+/*
+ * Advance nsteps time steps (Algorithm 1): for each step n -> n+1 the inlet
+ * plane is filled for t = n+1 (when xbc = LBM_X_INFLOW), then one fused
+ * pull-stream / boundary / wall-model / MRT-Smagorinsky collision kernel runs
+ * over all nodes.  stg: bound when non-NULL; required (now or earlier) with
+ * LBM_X_INFLOW.  Asynchronous on the handle's stream.
+ */
+lbm_status lbm_step(lbm_handle h, const lbm_stg* stg, int32_t nsteps);
+
+/* Streaming with the wall rules only, current buffer -> other buffer, no
+   collision; populations with no source (outside the x range) are set to -1.
+   The state then lives in the other buffer (time index unchanged).
+   LBM_STORE_F32 only. */
+lbm_status lbm_stream_only(lbm_handle h);
+
+/* Current state as float populations [19][N] (f_i = w_i + h_i for
+   LBM_STORE_F16DEV) into device buffer out. */
+lbm_status lbm_export_f32(lbm_handle h, float* out);
+
+/*
+ * Plane statistics (Sec. IV.A: statistics over a time window).  For each x
+ * in x_planes (host array), per row y, the sums over z and over steps of
+ * u, v, w, uu, vv, ww, uv, uw, vw of the force-corrected velocity
+ * (Eq. (11)) are accumulated in FP64 on the device during lbm_step.
+ *   ATTACH  x_planes[n_planes] (distinct, in [0, nx)); allocates and zeroes
+ *           the accumulators and starts accumulating.
+ *   DETACH  stop accumulating (accumulators kept).
+ *   RESET   zero the accumulators and the sample count.
+ *   READ    synchronise; host_out[n_planes][ny][9] = the means over z and the
+ *           sampled steps; *n_samples = number of steps accumulated.  Returns
+ *           any latched device error.
+ */
+lbm_status lbm_stats(lbm_handle h, int32_t op, const int32_t* x_planes, int32_t n_planes, double* host_out,
+                     int64_t* n_samples);
+
+/* Wait for the handle's stream; return and clear any latched device error. */
+lbm_status lbm_sync(lbm_handle h);
+const char* lbm_status_str(lbm_status s);
+
+/* When enabled, every collide-stream launch is bracketed by HIP events on
+   the handle's stream; *total_ms and *launches report the summed kernel time
+   since the last reset (reading synchronises).  enable = 2 resets. */
+lbm_status lbm_kernel_timing(lbm_handle h, int32_t enable, double* total_ms, int64_t* launches);
+
+/* Plain device copy kernel (bandwidth calibration): dst[0:bytes) = src[0:bytes),
+   bytes a multiple of 16, both 16-byte aligned. */
+lbm_status lbm_copy_probe(const void* src, void* dst, int64_t bytes, void* hip_stream);
+
+/* Host copies of the library's lattice tables (no device work): c[19][3]
+   (c_x, c_y, c_z), w[19], opp[19], y-mirror[19]. */
+void lbm_lattice_tables(int32_t* c, double* w, int32_t* opp, int32_t* refl_y);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LBM_H */

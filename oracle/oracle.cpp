@@ -316,9 +316,13 @@ void collide(const oracle_cfg& cfg, const R f[19], const R F[3], R out[19], R* t
 template <class R>
 R uplus(const R& yp, double kappa, double B) {
   using std::exp;
+  using std::expm1;
   using std::log;
+  using std::log1p;
   if (g_mutation == 5) return 2.5 * log(1.0 + 0.4 * yp) + 7.8 * (1.0 - exp(-yp / 11.0)) - yp * exp(-yp / 3.0);
-  return log(1.0 + kappa * yp) / kappa + B * (1.0 - exp(-yp / 11.0) - (yp / 11.0) * exp(-yp / 3.0));
+  /* ln(1 + k y+) and 1 - e^(-y+/11) evaluated as log1p / -expm1: the same
+     function, without the cancellation at small y+ */
+  return log1p(kappa * yp) / kappa + B * (-expm1(-yp / 11.0) - (yp / 11.0) * exp(-yp / 3.0));
 }
 template <class R>
 R duplus(const R& yp, double kappa, double B) {

@@ -1,0 +1,231 @@
+"""Python binding of the HIP channel library: device buffers from PyTorch,
+every step of the method runs in the library's kernels.
+
+    ch = Channel(768, 64, 192, tau0=..., ywall="slip", xbc="inflow", wall_model=True)
+    ch.set_stg(mode_table, u_rans, R, amp_bin, bin_of_y)
+    ch.init(u)                      # f = f_eq(1, u)
+    ch.step(1000)
+    means, n = ch.stats_read()
+"""
+import ctypes as C
+
+import numpy as np
+import torch
+
+from . import _abi as A
+
+PAPER_RATES = (1.0, 1.19, 1.6, 1.0, 1.2, 1.0, 1.2, 1.0, 1.2, 1.0,
+               1.6, 1.0, 1.6, 1.0, 1.0, 1.0, 1.98, 1.98, 1.98)
+_YWALL = {"periodic": A.Y_PERIODIC, "bounceback": A.Y_BOUNCEBACK, "slip": A.Y_SLIP}
+_XBC = {"periodic": A.X_PERIODIC, "inflow": A.X_INFLOW}
+_STORE = {"f32": A.STORE_F32, "f16dev": A.STORE_F16DEV}
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _dev(x, dtype, device):
+    if isinstance(x, torch.Tensor):
+        return x.to(device=device, dtype=dtype).contiguous()
+    return torch.as_tensor(np.ascontiguousarray(x), dtype=dtype, device=device).contiguous()
+
+
+class Channel:
+    """One D3Q19 channel lattice on one GPU (state double-buffered in HBM)."""
+
+    def __init__(self, nx, ny, nz, *, tau0, storage="f32", ywall="slip", xbc="periodic", wall_model=False,
+                 cs_smag=0.1, rates=None, kappa=0.41, b_reich=7.8, y_wall=0.5, u_conv=0.1, g=(0.0, 0.0, 0.0),
+                 newton_iters=8, device=None):
+        self.device = torch.device(device if device is not None else "cuda")
+        self.nx, self.ny, self.nz = nx, ny, nz
+        self.N = nx * ny * nz
+        self.storage = storage
+        cfg = A.Config()
+        cfg.nx, cfg.ny, cfg.nz = nx, ny, nz
+        cfg.storage = _STORE[storage]
+        cfg.ywall = _YWALL[ywall]
+        cfg.xbc = _XBC[xbc]
+        cfg.wall_model = 1 if wall_model else 0
+        cfg.newton_iters = newton_iters
+        cfg.tau0, cfg.cs_smag = tau0, cs_smag
+        for i, v in enumerate(rates if rates is not None else PAPER_RATES):
+            cfg.s[i] = v
+        cfg.kappa, cfg.b_reich, cfg.y_wall, cfg.u_conv = kappa, b_reich, y_wall, u_conv
+        for a in range(3):
+            cfg.g[a] = g[a]
+        self.cfg = cfg
+        dt = torch.float32 if storage == "f32" else torch.float16
+        shape = (19, nx, ny, nz)
+        self.f = [torch.empty(shape, dtype=dt, device=self.device) for _ in range(2)]
+        self.hist = [torch.zeros((5, ny, nz), dtype=torch.float32, device=self.device) for _ in range(2)]
+        self._stg = None
+        h = C.c_void_p()
+        stream = torch.cuda.current_stream(self.device).cuda_stream
+        st = A.lib().lbm_create(C.byref(cfg), _ptr(self.f[0]), _ptr(self.f[1]), _ptr(self.hist[0]),
+                                _ptr(self.hist[1]), C.c_void_p(stream), C.byref(h))
+        A.check(st, "lbm_create")
+        self._h = h
+
+    # ---- lifetime ----
+    def close(self):
+        if getattr(self, "_h", None):
+            A.lib().lbm_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ---- inputs ----
+    def inflow_reichardt(self, u_tau):
+        """Reichardt mean inflow U(y) computed by the library: device float64 [3, ny]."""
+        out = torch.zeros((3, self.ny), dtype=torch.float64, device=self.device)
+        A.check(A.lib().lbm_inflow_reichardt(self._h, float(u_tau), _ptr(out)), "lbm_inflow_reichardt")
+        return out
+
+    def set_stg(self, modes, u_rans, R, amp_bin, bin_of_y, want_fluct=False):
+        """Bind the inlet STG inputs (mode table dict q, sigma, kmag, d, phi, omega)."""
+        dev = self.device
+        keep = dict((k, _dev(modes[k], torch.float64, dev)) for k in ("q", "sigma", "kmag", "d", "phi", "omega"))
+        keep["u_rans"] = _dev(u_rans, torch.float64, dev)
+        keep["R"] = _dev(R, torch.float64, dev)
+        keep["amp_bin"] = _dev(amp_bin, torch.float64, dev)
+        keep["bin_of_y"] = _dev(bin_of_y, torch.int32, dev)
+        keep["u_in"] = torch.zeros((3, self.ny, self.nz), dtype=torch.float32, device=dev)
+        keep["fluct"] = torch.zeros((3, self.ny, self.nz), dtype=torch.float32, device=dev) if want_fluct else None
+        s = A.Stg()
+        s.n_modes = int(keep["q"].numel())
+        s.n_bins = int(keep["amp_bin"].numel())
+        for k in ("q", "sigma", "kmag", "d", "phi", "omega", "u_rans", "R", "amp_bin", "bin_of_y", "u_in", "fluct"):
+            setattr(s, k, None if keep[k] is None else keep[k].data_ptr())
+        self._stg_tensors = keep
+        self._stg = s
+        self._stg_dirty = True
+        return keep
+
+    def _stg_arg(self):
+        if self._stg is None:
+            return None
+        if self._stg_dirty:
+            self._stg_dirty = False
+            return C.byref(self._stg)
+        return None
+
+    def set_amp_bin(self, amp_bin):
+        """Replace the amplitude scalings s_b (rebinds the STG tables on the next call)."""
+        self._stg_tensors["amp_bin"].copy_(_dev(amp_bin, torch.float64, self.device))
+        self._stg_dirty = True
+
+    @property
+    def u_in(self):
+        return self._stg_tensors["u_in"]
+
+    @property
+    def fluct(self):
+        return self._stg_tensors["fluct"]
+
+    def init(self, u, rho=None, pert=None, eps=0.0):
+        """f = f_eq(rho, u) + eps w pert in the current buffer; time index set to 0."""
+        dev = self.device
+        u = _dev(u, torch.float32, dev).reshape(3, self.N)
+        rho = None if rho is None else _dev(rho, torch.float32, dev).reshape(self.N)
+        pert = None if pert is None else _dev(pert, torch.float32, dev).reshape(19, self.N)
+        A.check(A.lib().lbm_set_state(self._h, _ptr(self.f[0]), _ptr(self.f[1]), _ptr(self.hist[0]),
+                                      _ptr(self.hist[1]), 0), "lbm_set_state")
+        A.check(A.lib().lbm_init_equilibrium(self._h, _ptr(rho), _ptr(u), _ptr(pert), float(eps)),
+                "lbm_init_equilibrium")
+        self._keep_init = (u, rho, pert)  # alive until the enqueued kernel has read them
+
+    # ---- time stepping ----
+    def stg_fill(self, t):
+        A.check(A.lib().stg_inlet_fill(self._h, self._stg_arg(), float(t)), "stg_inlet_fill")
+        return self.u_in
+
+    def step(self, n=1):
+        A.check(A.lib().lbm_step(self._h, self._stg_arg(), int(n)), "lbm_step")
+
+    def stream_only(self):
+        A.check(A.lib().lbm_stream_only(self._h), "lbm_stream_only")
+
+    def sync(self):
+        A.check(A.lib().lbm_sync(self._h), "lbm_sync")
+
+    # ---- state ----
+    def _cur(self):
+        fp = C.c_void_p()
+        hp = C.c_void_p()
+        t = C.c_int64()
+        A.check(A.lib().lbm_get_state(self._h, C.byref(fp), C.byref(hp), C.byref(t)), "lbm_get_state")
+        k = 0 if fp.value == self.f[0].data_ptr() else 1
+        return k, t.value
+
+    @property
+    def time(self):
+        return self._cur()[1]
+
+    def state(self):
+        """(populations buffer, outlet-history buffer) that hold the current state."""
+        k, _ = self._cur()
+        return self.f[k], self.hist[k]
+
+    def populations(self):
+        """Current state as float32 [19, nx, ny, nz] (library export)."""
+        out = torch.empty((19, self.nx, self.ny, self.nz), dtype=torch.float32, device=self.device)
+        A.check(A.lib().lbm_export_f32(self._h, _ptr(out)), "lbm_export_f32")
+        return out
+
+    def set_state(self, f_cur, hist_cur, time):
+        """Restore a state (checkpoint): copies into the buffers and sets the time index."""
+        self.f[0].copy_(f_cur)
+        self.hist[0].copy_(hist_cur)
+        A.check(A.lib().lbm_set_state(self._h, _ptr(self.f[0]), _ptr(self.f[1]), _ptr(self.hist[0]),
+                                      _ptr(self.hist[1]), int(time)), "lbm_set_state")
+
+    # ---- statistics ----
+    def stats_attach(self, planes):
+        arr = (C.c_int32 * len(planes))(*[int(p) for p in planes])
+        A.check(A.lib().lbm_stats(self._h, A.STATS_ATTACH, arr, len(planes), None, None), "lbm_stats attach")
+        self._planes = list(planes)
+
+    def stats_detach(self):
+        A.check(A.lib().lbm_stats(self._h, A.STATS_DETACH, None, 0, None, None), "lbm_stats detach")
+
+    def stats_reset(self):
+        A.check(A.lib().lbm_stats(self._h, A.STATS_RESET, None, 0, None, None), "lbm_stats reset")
+
+    def stats_read(self):
+        """Means over z and sampled steps: array [n_planes, ny, 9] (u v w uu vv ww uv uw vw), n_samples."""
+        out = np.zeros((len(self._planes), self.ny, 9))
+        n = C.c_int64()
+        A.check(A.lib().lbm_stats(self._h, A.STATS_READ, None, 0, out.ctypes.data_as(C.c_void_p), C.byref(n)),
+                "lbm_stats read")
+        return out, n.value
+
+    # ---- timing ----
+    def kernel_timing(self, enable):
+        ms = C.c_double()
+        n = C.c_int64()
+        A.check(A.lib().lbm_kernel_timing(self._h, int(enable), C.byref(ms), C.byref(n)), "lbm_kernel_timing")
+        return ms.value, n.value
+
+
+def copy_probe(src, dst):
+    """Plain device copy kernel of the library (bandwidth calibration)."""
+    nbytes = src.numel() * src.element_size()
+    stream = torch.cuda.current_stream(src.device).cuda_stream
+    A.check(A.lib().lbm_copy_probe(_ptr(src), _ptr(dst), nbytes, C.c_void_p(stream)), "lbm_copy_probe")
+
+
+def lattice_tables():
+    """The library's own lattice tables (host data): c[19,3], w[19], opp[19], refl_y[19]."""
+    c = np.zeros((19, 3), np.int32)
+    w = np.zeros(19)
+    opp = np.zeros(19, np.int32)
+    refl = np.zeros(19, np.int32)
+    P = C.c_void_p
+    A.lib().lbm_lattice_tables(c.ctypes.data_as(P), w.ctypes.data_as(P), opp.ctypes.data_as(P),
+                               refl.ctypes.data_as(P))
+    return dict(c=c, w=w, opp=opp, refl=refl)

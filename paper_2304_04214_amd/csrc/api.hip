@@ -1,0 +1,379 @@
+// C ABI of the library: argument checking, handle state, launch sequencing.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "internal.h"
+
+using lbm::Q;
+
+namespace {
+
+#define HIPCHK(expr)                        \
+  do {                                      \
+    hipError_t e_ = (expr);                 \
+    if (e_ != hipSuccess) return LBM_ERR_HIP; \
+  } while (0)
+
+bool aligned256(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 255u) == 0; }
+
+lbm_status check_config(const lbm_config* c) {
+  if (!c) return LBM_ERR_ARG;
+  if (c->nx < 1 || c->ny < lbm::YROWS || c->nz < 1) return LBM_ERR_SHAPE;
+  if (c->xbc == LBM_X_INFLOW && c->nx < 3) return LBM_ERR_SHAPE;
+  const int64_t N = (int64_t)c->nx * c->ny * c->nz;
+  if (N >= (int64_t(1) << 31)) return LBM_ERR_SHAPE;
+  if (c->storage != LBM_STORE_F32 && c->storage != LBM_STORE_F16DEV) return LBM_ERR_ARG;
+  if (c->ywall < LBM_Y_PERIODIC || c->ywall > LBM_Y_SLIP) return LBM_ERR_ARG;
+  if (c->xbc != LBM_X_PERIODIC && c->xbc != LBM_X_INFLOW) return LBM_ERR_ARG;
+  if (c->wall_model != 0 && c->wall_model != 1) return LBM_ERR_ARG;
+  if (c->wall_model == 1 && c->ywall == LBM_Y_PERIODIC) return LBM_ERR_ARG;
+  if (c->newton_iters < 0 || c->newton_iters > 64) return LBM_ERR_ARG;
+  if (!(c->tau0 > 0.5) || !(c->cs_smag >= 0.0)) return LBM_ERR_ARG;
+  if (c->wall_model == 1 && (!(c->kappa > 0.0) || !(c->y_wall > 0.0))) return LBM_ERR_ARG;
+  if (c->xbc == LBM_X_INFLOW && !(c->u_conv >= 0.0)) return LBM_ERR_ARG;
+  return LBM_OK;
+}
+
+lbm_status check_stg(const lbm_ctx* h, const lbm_stg* s) {
+  if (!s) return LBM_ERR_ARG;
+  if (s->n_modes < 1 || s->n_modes > LBM_MAX_MODES || s->n_bins < 1) return LBM_ERR_ARG;
+  if (!s->q || !s->sigma || !s->kmag || !s->d || !s->phi || !s->omega || !s->u_rans || !s->R || !s->amp_bin ||
+      !s->bin_of_y || !s->u_in)
+    return LBM_ERR_ARG;
+  (void)h;
+  return LBM_OK;
+}
+
+lbm_status bind_stg(lbm_ctx* h, const lbm_stg* s) {
+  lbm_status st = check_stg(h, s);
+  if (st != LBM_OK) return st;
+  h->stg = *s;
+  HIPCHK(lbm::launch_stg_bind(h, s));
+  h->stg_bound = true;
+  return LBM_OK;
+}
+
+lbm_status take_error(lbm_ctx* h) {
+  int err = 0;
+  HIPCHK(hipMemcpyAsync(&err, h->d_err, sizeof(int), hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(hipStreamSynchronize(h->stream));
+  if (err) {
+    HIPCHK(hipMemsetAsync(h->d_err, 0, sizeof(int), h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+  }
+  if (err & lbm::ERRBIT_NONFINITE) return LBM_ERR_NONFINITE;
+  if (err & lbm::ERRBIT_MACH) return LBM_ERR_MACH;
+  return LBM_OK;
+}
+
+void free_tables(lbm_ctx* h) {
+  lbm::StgTables& t = h->tab;
+  if (t.amp3) (void)hipFree(t.amp3);
+  if (t.ky) (void)hipFree(t.ky);
+  if (t.trigz) (void)hipFree(t.trigz);
+  if (t.chol) (void)hipFree(t.chol);
+  if (t.sb) (void)hipFree(t.sb);
+  if (t.urans) (void)hipFree(t.urans);
+  t = lbm::StgTables();
+}
+
+hipError_t collide_launch(lbm_ctx* h, int src, int dst) {
+  if (!h->timing) return lbm::launch_collide(h, src, dst);
+  const size_t need = 2 * (size_t)(h->ev_used + 1);
+  while (h->ev.size() < need) {
+    hipEvent_t e;
+    hipError_t r = hipEventCreate(&e);
+    if (r != hipSuccess) return r;
+    h->ev.push_back(e);
+  }
+  hipError_t r = hipEventRecord(h->ev[2 * h->ev_used], h->stream);
+  if (r != hipSuccess) return r;
+  r = lbm::launch_collide(h, src, dst);
+  if (r != hipSuccess) return r;
+  r = hipEventRecord(h->ev[2 * h->ev_used + 1], h->stream);
+  if (r != hipSuccess) return r;
+  ++h->ev_used;
+  return hipSuccess;
+}
+
+hipError_t harvest_timing(lbm_ctx* h) {
+  if (h->ev_used == 0) return hipSuccess;
+  hipError_t r = hipEventSynchronize(h->ev[2 * h->ev_used - 1]);
+  if (r != hipSuccess) return r;
+  for (int64_t k = 0; k < h->ev_used; ++k) {
+    float ms = 0.f;
+    r = hipEventElapsedTime(&ms, h->ev[2 * k], h->ev[2 * k + 1]);
+    if (r != hipSuccess) return r;
+    h->timed_ms += ms;
+    ++h->timed_launches;
+  }
+  h->ev_used = 0;
+  return hipSuccess;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* lbm_status_str(lbm_status s) {
+  switch (s) {
+    case LBM_OK: return "ok";
+    case LBM_ERR_ARG: return "invalid argument";
+    case LBM_ERR_SHAPE: return "invalid shape or alignment";
+    case LBM_ERR_HIP: return "HIP runtime error";
+    case LBM_ERR_MACH: return "inlet velocity above 0.3 c_s";
+    case LBM_ERR_NONFINITE: return "non-finite or non-positive density";
+    case LBM_ERR_STATE: return "call out of order";
+  }
+  return "unknown status";
+}
+
+lbm_status lbm_create(const lbm_config* cfg, void* f_a, void* f_b, float* hist_a, float* hist_b, void* hip_stream,
+                      lbm_handle* out) {
+  if (!out) return LBM_ERR_ARG;
+  *out = nullptr;
+  lbm_status st = check_config(cfg);
+  if (st != LBM_OK) return st;
+  if (!f_a || !f_b || f_a == f_b) return LBM_ERR_ARG;
+  if (!aligned256(f_a) || !aligned256(f_b)) return LBM_ERR_SHAPE;
+  if (cfg->xbc == LBM_X_INFLOW && (!hist_a || !hist_b || hist_a == hist_b)) return LBM_ERR_ARG;
+  lbm_ctx* h = new (std::nothrow) lbm_ctx();
+  if (!h) return LBM_ERR_ARG;
+  h->cfg = *cfg;
+  if (h->cfg.newton_iters == 0 && h->cfg.wall_model) h->cfg.newton_iters = 8;
+  h->stream = static_cast<hipStream_t>(hip_stream);
+  if (hipGetDevice(&h->device) != hipSuccess) {
+    delete h;
+    return LBM_ERR_HIP;
+  }
+  h->f[0] = f_a;
+  h->f[1] = f_b;
+  h->hist[0] = hist_a;
+  h->hist[1] = hist_b;
+  h->N = (int64_t)cfg->nx * cfg->ny * cfg->nz;
+  h->zc = (cfg->nz + lbm::ZT - 1) / lbm::ZT;
+  h->yg = (cfg->ny + lbm::YROWS - 1) / lbm::YROWS;
+  const int64_t nb = (int64_t)cfg->nx * h->yg * h->zc;
+  if (nb >= (int64_t(1) << 31)) {
+    delete h;
+    return LBM_ERR_SHAPE;
+  }
+  h->nblocks = (int)nb;
+  if (hipMalloc(&h->d_err, sizeof(int)) != hipSuccess) {
+    delete h;
+    return LBM_ERR_HIP;
+  }
+  if (hipMalloc(&h->d_plane_of_x, sizeof(int) * cfg->nx) != hipSuccess) {
+    (void)hipFree(h->d_err);
+    delete h;
+    return LBM_ERR_HIP;
+  }
+  std::vector<int> none(cfg->nx, -1);
+  if (hipMemcpy(h->d_plane_of_x, none.data(), sizeof(int) * cfg->nx, hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemset(h->d_err, 0, sizeof(int)) != hipSuccess) {
+    (void)hipFree(h->d_err);
+    (void)hipFree(h->d_plane_of_x);
+    delete h;
+    return LBM_ERR_HIP;
+  }
+  *out = h;
+  return LBM_OK;
+}
+
+lbm_status lbm_destroy(lbm_handle h) {
+  if (!h) return LBM_ERR_ARG;
+  (void)hipStreamSynchronize(h->stream);
+  free_tables(h);
+  if (h->d_stats) (void)hipFree(h->d_stats);
+  if (h->d_plane_of_x) (void)hipFree(h->d_plane_of_x);
+  if (h->d_err) (void)hipFree(h->d_err);
+  for (hipEvent_t e : h->ev) (void)hipEventDestroy(e);
+  delete h;
+  return LBM_OK;
+}
+
+lbm_status lbm_set_state(lbm_handle h, void* f_a, void* f_b, float* hist_a, float* hist_b, int64_t time) {
+  if (!h || !f_a || !f_b || f_a == f_b) return LBM_ERR_ARG;
+  if (!aligned256(f_a) || !aligned256(f_b)) return LBM_ERR_SHAPE;
+  if (h->cfg.xbc == LBM_X_INFLOW && (!hist_a || !hist_b || hist_a == hist_b)) return LBM_ERR_ARG;
+  if (time < 0) return LBM_ERR_ARG;
+  h->f[0] = f_a;
+  h->f[1] = f_b;
+  h->hist[0] = hist_a;
+  h->hist[1] = hist_b;
+  h->cur = 0;
+  h->time = time;
+  return LBM_OK;
+}
+
+lbm_status lbm_get_state(lbm_handle h, void** f_cur, float** hist_cur, int64_t* time) {
+  if (!h) return LBM_ERR_ARG;
+  if (f_cur) *f_cur = h->f[h->cur];
+  if (hist_cur) *hist_cur = h->hist[h->cur];
+  if (time) *time = h->time;
+  return LBM_OK;
+}
+
+lbm_status lbm_init_equilibrium(lbm_handle h, const float* rho, const float* u, const float* pert, float eps) {
+  if (!h || !u) return LBM_ERR_ARG;
+  HIPCHK(lbm::launch_init(h, rho, u, pert, eps));
+  return LBM_OK;
+}
+
+lbm_status lbm_inflow_reichardt(lbm_handle h, double u_tau, double* u_rans) {
+  if (!h || !u_rans || !(u_tau >= 0.0)) return LBM_ERR_ARG;
+  HIPCHK(lbm::launch_inflow_reichardt(h, u_tau, u_rans));
+  return LBM_OK;
+}
+
+lbm_status stg_inlet_fill(lbm_handle h, const lbm_stg* stg, double t) {
+  if (!h) return LBM_ERR_ARG;
+  if (stg) {
+    lbm_status st = bind_stg(h, stg);
+    if (st != LBM_OK) return st;
+  }
+  if (!h->stg_bound) return LBM_ERR_STATE;
+  HIPCHK(lbm::launch_stg_fill(h, t));
+  return LBM_OK;
+}
+
+lbm_status lbm_step(lbm_handle h, const lbm_stg* stg, int32_t nsteps) {
+  if (!h || nsteps < 0) return LBM_ERR_ARG;
+  if (stg) {
+    lbm_status st = bind_stg(h, stg);
+    if (st != LBM_OK) return st;
+  }
+  const bool inflow = h->cfg.xbc == LBM_X_INFLOW;
+  if (inflow && !h->stg_bound) return LBM_ERR_STATE;
+  for (int32_t n = 0; n < nsteps; ++n) {
+    if (inflow) HIPCHK(lbm::launch_stg_fill(h, (double)(h->time + 1)));
+    HIPCHK(collide_launch(h, h->cur, 1 - h->cur));
+    h->cur = 1 - h->cur;
+    ++h->time;
+    if (h->stats_on) ++h->n_samples;
+  }
+  return LBM_OK;
+}
+
+lbm_status lbm_stream_only(lbm_handle h) {
+  if (!h) return LBM_ERR_ARG;
+  if (h->cfg.storage != LBM_STORE_F32) return LBM_ERR_ARG;
+  HIPCHK(lbm::launch_stream_only(h, h->cur, 1 - h->cur));
+  h->cur = 1 - h->cur;
+  return LBM_OK;
+}
+
+lbm_status lbm_export_f32(lbm_handle h, float* out) {
+  if (!h || !out) return LBM_ERR_ARG;
+  HIPCHK(lbm::launch_export(h, out));
+  return LBM_OK;
+}
+
+lbm_status lbm_stats(lbm_handle h, int32_t op, const int32_t* x_planes, int32_t n_planes, double* host_out,
+                     int64_t* n_samples) {
+  if (!h) return LBM_ERR_ARG;
+  const int nx = h->cfg.nx, ny = h->cfg.ny;
+  switch (op) {
+    case LBM_STATS_ATTACH: {
+      if (!x_planes || n_planes < 1 || n_planes > nx) return LBM_ERR_ARG;
+      std::vector<int> map(nx, -1);
+      for (int p = 0; p < n_planes; ++p) {
+        const int x = x_planes[p];
+        if (x < 0 || x >= nx || map[x] >= 0) return LBM_ERR_ARG;
+        map[x] = p;
+      }
+      HIPCHK(hipStreamSynchronize(h->stream));
+      if (h->d_stats) {
+        HIPCHK(hipFree(h->d_stats));
+        h->d_stats = nullptr;
+      }
+      const size_t bytes = sizeof(double) * (size_t)n_planes * ny * h->zc * 9;
+      HIPCHK(hipMalloc(&h->d_stats, bytes));
+      HIPCHK(hipMemsetAsync(h->d_stats, 0, bytes, h->stream));
+      HIPCHK(hipMemcpyAsync(h->d_plane_of_x, map.data(), sizeof(int) * nx, hipMemcpyHostToDevice, h->stream));
+      HIPCHK(hipStreamSynchronize(h->stream));
+      h->n_planes = n_planes;
+      h->n_samples = 0;
+      h->stats_on = 1;
+      return LBM_OK;
+    }
+    case LBM_STATS_DETACH:
+      h->stats_on = 0;
+      return LBM_OK;
+    case LBM_STATS_RESET: {
+      if (!h->d_stats) return LBM_ERR_STATE;
+      const size_t bytes = sizeof(double) * (size_t)h->n_planes * ny * h->zc * 9;
+      HIPCHK(hipMemsetAsync(h->d_stats, 0, bytes, h->stream));
+      h->n_samples = 0;
+      return LBM_OK;
+    }
+    case LBM_STATS_READ: {
+      if (!h->d_stats) return LBM_ERR_STATE;
+      if (!host_out) return LBM_ERR_ARG;
+      const size_t cnt = (size_t)h->n_planes * ny * h->zc * 9;
+      std::vector<double> raw(cnt);
+      HIPCHK(hipMemcpyAsync(raw.data(), h->d_stats, sizeof(double) * cnt, hipMemcpyDeviceToHost, h->stream));
+      lbm_status st = take_error(h);
+      // fixed-order sum over the z-chunks, then the mean over z and samples
+      const double denom = (double)h->n_samples * h->cfg.nz;
+      for (int p = 0; p < h->n_planes; ++p)
+        for (int y = 0; y < ny; ++y)
+          for (int k = 0; k < 9; ++k) {
+            double acc = 0.0;
+            for (int c = 0; c < h->zc; ++c) acc += raw[(((size_t)p * ny + y) * h->zc + c) * 9 + k];
+            host_out[((size_t)p * ny + y) * 9 + k] = denom > 0 ? acc / denom : 0.0;
+          }
+      if (n_samples) *n_samples = h->n_samples;
+      return st;
+    }
+    default:
+      return LBM_ERR_ARG;
+  }
+}
+
+lbm_status lbm_sync(lbm_handle h) {
+  if (!h) return LBM_ERR_ARG;
+  HIPCHK(hipStreamSynchronize(h->stream));
+  return take_error(h);
+}
+
+lbm_status lbm_kernel_timing(lbm_handle h, int32_t enable, double* total_ms, int64_t* launches) {
+  if (!h) return LBM_ERR_ARG;
+  HIPCHK(harvest_timing(h));
+  if (total_ms) *total_ms = h->timed_ms;
+  if (launches) *launches = h->timed_launches;
+  if (enable == 2) {
+    h->timed_ms = 0.0;
+    h->timed_launches = 0;
+    h->timing = 1;
+  } else {
+    h->timing = enable ? 1 : 0;
+  }
+  return LBM_OK;
+}
+
+lbm_status lbm_copy_probe(const void* src, void* dst, int64_t bytes, void* hip_stream) {
+  if (!src || !dst || bytes <= 0 || (bytes & 15) != 0) return LBM_ERR_ARG;
+  if ((reinterpret_cast<uintptr_t>(src) & 15u) || (reinterpret_cast<uintptr_t>(dst) & 15u)) return LBM_ERR_SHAPE;
+  HIPCHK(lbm::launch_copy(src, dst, bytes, static_cast<hipStream_t>(hip_stream)));
+  return LBM_OK;
+}
+
+void lbm_lattice_tables(int32_t* c, double* w, int32_t* opp, int32_t* refl_y) {
+  for (int i = 0; i < Q; ++i) {
+    if (c) {
+      c[3 * i] = lbm::CX[i];
+      c[3 * i + 1] = lbm::CY[i];
+      c[3 * i + 2] = lbm::CZ[i];
+    }
+    if (w) w[i] = lbm::WD[i];
+    if (opp) opp[i] = lbm::opp(i);
+    if (refl_y) refl_y[i] = lbm::REFLY[i];
+  }
+}
+
+}  // extern "C"

@@ -1,0 +1,595 @@
+// Fused pull-stream / boundary / wall-model / MRT-Smagorinsky collision
+// kernel for the D3Q19 channel (Algorithm 1 of Xue, Yao, Davidson,
+// arXiv 2304.04214), plus the initialisation, export, stream-only and copy
+// kernels.
+//
+// Mapping: one thread per node.  A wave is 64 consecutive z nodes of one
+// (x, y) row; a block is 4 such rows (256 threads) of the same x and z-chunk.
+// x and y are wave-uniform (scalar registers), so every boundary decision is
+// a scalar branch and every population load is base(scalar) + z(vector).
+// Blocks are renumbered so each XCD walks a contiguous range of the lattice
+// (neighbouring z-chunks share the partly-used cache lines of the +-1 shifts).
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+
+#include "internal.h"
+
+namespace lbm {
+namespace {
+
+__device__ __forceinline__ int xcd_remap(int b, int nb) {
+  const int q = nb >> 3, r = nb & 7;
+  const int xcd = b & 7, idx = b >> 3;
+  return (xcd < r) ? xcd * (q + 1) + idx : r * (q + 1) + (xcd - r) * q + idx;
+}
+
+__device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
+// Population storage: float, or half deviations h_i = f_i - w_i.
+template <bool F16>
+struct Pop;
+template <>
+struct Pop<false> {
+  __device__ static __forceinline__ float ld(const void* base, int, int idx) {
+    return static_cast<const float*>(base)[idx];
+  }
+  __device__ static __forceinline__ void st(void* base, int, int idx, float v) {
+    static_cast<float*>(base)[idx] = v;
+  }
+};
+template <>
+struct Pop<true> {
+  __device__ static __forceinline__ float ld(const void* base, int i, int idx) {
+    return (float)WD[i] + (float)static_cast<const _Float16*>(base)[idx];
+  }
+  __device__ static __forceinline__ void st(void* base, int i, int idx, float v) {
+    static_cast<_Float16*>(base)[idx] = (_Float16)(v - (float)WD[i]);
+  }
+};
+
+// Wave-uniform source rows of one node row (x, y).
+struct Geo {
+  int x, y;
+  int xs[3];
+  bool xok[3];  // index c_x + 1: source x = x - c_x and whether it lies in the lattice
+  int ys[3];
+  bool yout[3];  // index c_y + 1: source y and whether it lies beyond a wall
+};
+
+__device__ __forceinline__ Geo make_geo(const CollideArgs& a, int x, int y) {
+  Geo g;
+  g.x = x;
+  g.y = y;
+#pragma unroll
+  for (int c = -1; c <= 1; ++c) {
+    int s = x - c;
+    bool ok = true;
+    if (a.xbc == LBM_X_PERIODIC) {
+      s = s < 0 ? s + a.nx : (s >= a.nx ? s - a.nx : s);
+    } else {
+      ok = s >= 0 && s < a.nx;
+      s = s < 0 ? 0 : (s >= a.nx ? a.nx - 1 : s);
+    }
+    g.xs[c + 1] = s;
+    g.xok[c + 1] = ok;
+    int t = y - c;
+    bool out = t < 0 || t >= a.ny;
+    if (a.ywall == LBM_Y_PERIODIC) {
+      t = t < 0 ? t + a.ny : (t >= a.ny ? t - a.ny : t);
+      out = false;
+    } else {
+      t = t < 0 ? 0 : (t >= a.ny ? a.ny - 1 : t);
+    }
+    g.ys[c + 1] = t;
+    g.yout[c + 1] = out;
+  }
+  return g;
+}
+
+__device__ __forceinline__ int rowoff(const CollideArgs& a, int x, int y) { return (x * a.ny + y) * a.nz; }
+
+// Pull of direction i into node (g.x, g.y, z) with the wall rules
+// (Eq. (3); halfway bounce-back or specular slip at the y walls).  Sources
+// outside the x range (inlet unknowns, outlet) return `unset`.
+template <bool F16>
+__device__ __forceinline__ float pull_dir(const CollideArgs& a, const Geo& g, int i, int z, int zm, int zp,
+                                          float unset) {
+  const int cx = CX[i], cy = CY[i], cz = CZ[i];
+  const int zs = cz == 1 ? zm : (cz == -1 ? zp : z);
+  if (cy != 0 && g.yout[cy + 1]) {
+    if (a.ywall == LBM_Y_BOUNCEBACK) return Pop<F16>::ld(a.src[opp(i)], opp(i), rowoff(a, g.x, g.y) + z);
+    if (!g.xok[cx + 1]) return unset;
+    return Pop<F16>::ld(a.src[REFLY[i]], REFLY[i], rowoff(a, g.xs[cx + 1], g.y) + zs);
+  }
+  if (!g.xok[cx + 1]) return unset;
+  return Pop<F16>::ld(a.src[i], i, rowoff(a, g.xs[cx + 1], g.ys[cy + 1]) + zs);
+}
+
+// Regularised inlet populations (Sec. III.A, Eq. (26)-(31)): Zou-He density
+// from the known c_x <= 0 populations, second-order equilibrium at u_in, and
+// the non-equilibrium part rebuilt from Pi_neq with the unknown c_x > 0
+// non-equilibrium populations taken equal to their opposites.
+__device__ __forceinline__ void inlet_regularize(const CollideArgs& a, int y, int z, float f[Q]) {
+  const int pl = a.ny * a.nz, o = y * a.nz + z;
+  const float ux = a.u_in[o], uy = a.u_in[pl + o], uz = a.u_in[2 * pl + o];
+  float rho0 = 0.f, rhom = 0.f;
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    if (CX[i] == 0) rho0 += f[i];
+    if (CX[i] == -1) rhom += f[i];
+  }
+  const float rin = (rho0 + 2.f * rhom) / (1.f - ux);
+  const float uu15 = 1.5f * (ux * ux + uy * uy + uz * uz);
+  float feq[Q];
+  float pxx = 0.f, pyy = 0.f, pzz = 0.f, pxy = 0.f, pyz = 0.f, pxz = 0.f;
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    const float cu = CX[i] * ux + CY[i] * uy + CZ[i] * uz;
+    feq[i] = (float)WD[i] * rin * (1.f + 3.f * cu + 4.5f * cu * cu - uu15);
+    if (CX[i] <= 0) {
+      const float fn = (CX[i] == 0 ? 1.f : 2.f) * (f[i] - feq[i]);
+      pxx += (CX[i] * CX[i] - 1.f / 3.f) * fn;
+      pyy += (CY[i] * CY[i] - 1.f / 3.f) * fn;
+      pzz += (CZ[i] * CZ[i] - 1.f / 3.f) * fn;
+      pxy += (CX[i] * CY[i]) * fn;
+      pyz += (CY[i] * CZ[i]) * fn;
+      pxz += (CX[i] * CZ[i]) * fn;
+    }
+  }
+  const float tr3 = (pxx + pyy + pzz) * (1.f / 3.f);
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    const float cpc = CX[i] * CX[i] * pxx + CY[i] * CY[i] * pyy + CZ[i] * CZ[i] * pzz +
+                      2.f * (CX[i] * CY[i] * pxy + CY[i] * CZ[i] * pyz + CX[i] * CZ[i] * pxz);
+    f[i] = feq[i] + 4.5f * (float)WD[i] * (cpc - tr3);
+  }
+}
+
+// Reichardt wall force of a first off-wall cell (Sec. II.C, Eq. (16)-(21)):
+// base vector from the tangential part of u_2, projected speed u_hat, u_tau
+// from a fixed number of Newton steps on u_tau u+(y u_tau / nu0) = |u_hat|,
+// F_w = -sign(u_hat) rho u_tau^2 e_x.  The wall normal is along y.
+__device__ __forceinline__ void wall_force(const CollideArgs& a, float rho, float uwx, float uwz, float u2x,
+                                           float u2z, float& fx, float& fz) {
+  fx = 0.f;
+  fz = 0.f;
+  const float tn2 = u2x * u2x + u2z * u2z;
+  if (!(tn2 > 0.f)) return;
+  const float itn = 1.f / sqrtf(tn2);
+  const float ex = u2x * itn, ez = u2z * itn;
+  const float uhat = uwx * ex + uwz * ez;
+  if (uhat == 0.f) return;
+  const float ua = fabsf(uhat);
+  float ut = sqrtf(a.nu0 * ua / a.y_wall);
+  for (int it = 0; it < a.newton_iters; ++it) {
+    const float yp = a.y_wall * ut * a.inv_nu0;
+    const float e1 = expf(yp * (-1.f / 11.f)), e3 = expf(yp * (-1.f / 3.f));
+    const float up = log1pf(a.kappa * yp) * a.inv_kappa - a.b_reich * (expm1f(yp * (-1.f / 11.f)) + yp * (1.f / 11.f) * e3);
+    const float dup = 1.f / (1.f + a.kappa * yp) +
+                      a.b_reich * ((e1 - e3) * (1.f / 11.f) + yp * (1.f / 33.f) * e3);
+    ut -= (ut * up - ua) / (up + yp * dup);
+  }
+  const float tw = (uhat > 0.f ? -1.f : 1.f) * rho * ut * ut;
+  fx = tw * ex;
+  fz = tw * ez;
+}
+
+// MRT collision with Guo forcing in moment space and the Smagorinsky
+// relaxation time (Sec. II.A-II.B, Eq. (6)-(15)), written as
+// f* = f + M^-1 delta with delta_k = -s_k (m_k - m_eq_k) + (1 - s_k/2) F_k.
+// The moment transform uses the even/odd split of the basis over the
+// opposite-direction pairs (i, 18 - i).  Returns the force-corrected velocity.
+template <bool FORCE>
+__device__ __forceinline__ void collide(const CollideArgs& a, float f[Q], float rho, float jx, float jy, float jz,
+                                        float Fx, float Fy, float Fz, float& ux, float& uy, float& uz) {
+  float s[9], d[9];
+#pragma unroll
+  for (int k = 0; k < 9; ++k) {
+    s[k] = f[k] + f[18 - k];
+    d[k] = f[k] - f[18 - k];
+  }
+  const float f9 = f[9];
+  const float A = s[0] + s[1] + s[3] + s[4] + s[5] + s[7];
+  const float Bx = s[2] + s[6] + s[8];
+  const float T04 = s[0] + s[4], T26 = s[2] + s[6], T1357 = s[1] + s[3] + s[5] + s[7];
+  const float m1 = 8.f * A - 11.f * Bx - 30.f * f9;
+  const float m2 = A - 4.f * Bx + 12.f * f9;
+  const float m9 = 2.f * (s[8] - T04) + T1357 - T26;
+  const float m10 = -2.f * T04 + T1357 + 2.f * T26 - 4.f * s[8];
+  const float m11 = (s[5] + s[6] + s[7]) - (s[1] + s[2] + s[3]);
+  const float m12 = (s[5] + s[7] - 2.f * s[6]) - (s[1] + s[3] - 2.f * s[2]);
+  const float m13 = s[5] - s[7], m14 = s[0] - s[4], m15 = s[1] - s[3];
+  const float m4 = (d[3] + d[7]) - (d[1] + d[5]) + 4.f * d[8];
+  const float m6 = d[4] - (d[0] + d[5] + d[7]) + 4.f * d[6];
+  const float m8 = 4.f * d[2] - (d[0] + d[1] + d[3] + d[4]);
+  const float m16 = (d[1] + d[7]) - (d[3] + d[5]);
+  const float m17 = (d[4] + d[5] + d[7]) - d[0];
+  const float m18 = (d[0] + d[4]) - (d[1] + d[3]);
+
+  // Eq. (11): rho u = j + F/2;  Eq. (8) equilibria (with the readings of m2, m4,6,8)
+  const float ir = 1.f / rho;
+  const float px = FORCE ? jx + 0.5f * Fx : jx;
+  const float py = FORCE ? jy + 0.5f * Fy : jy;
+  const float pz = FORCE ? jz + 0.5f * Fz : jz;
+  ux = px * ir;
+  uy = py * ir;
+  uz = pz * ir;
+  const float uxx = ux * ux, uyy = uy * uy, uzz = uz * uz, uu = uxx + uyy + uzz;
+  const float e1 = m1 - rho * (19.f * uu - 11.f);
+  const float e2 = m2 - rho * (3.f - 5.5f * uu);
+  const float e4 = m4 + (2.f / 3.f) * px;
+  const float e6 = m6 + (2.f / 3.f) * py;
+  const float e8 = m8 + (2.f / 3.f) * pz;
+  const float q9 = rho * (2.f * uxx - uyy - uzz);
+  const float q11 = rho * (uyy - uzz);
+  const float e9 = m9 - q9, e10 = m10 + 0.5f * q9;
+  const float e11 = m11 - q11, e12 = m12 + 0.5f * q11;
+  const float e13 = m13 - px * uy, e14 = m14 - py * uz, e15 = m15 - px * uz;
+
+  // Sec. II.B: Pi_neq from the non-equilibrium moments, Q^(1/2) = |Pi_neq|,
+  // tau_eff = tau0/2 + sqrt(tau0^2 + 18 sqrt(2) C_smag Q^(1/2) / rho)/2
+  const float dc2 = e1 * (1.f / 19.f);
+  const float pxx = (e9 + dc2) * (1.f / 3.f);
+  const float pyy = 0.5f * (dc2 - pxx + e11), pzz = 0.5f * (dc2 - pxx - e11);
+  const float q2 = pxx * pxx + pyy * pyy + pzz * pzz + 2.f * (e13 * e13 + e14 * e14 + e15 * e15);
+  const float tau = 0.5f * a.tau0 + 0.5f * sqrtf(a.tau0sq + a.smag * sqrtf(q2) * ir);
+  const float sv = 1.f / tau;
+  const float hv = 1.f - 0.5f * sv;
+
+  // Guo forcing moments M Fbar = (1/rho) d m_eq/du . F
+  float F1 = 0.f, F2 = 0.f, F4 = 0.f, F6 = 0.f, F8 = 0.f, F9 = 0.f, F10 = 0.f, F11 = 0.f, F12 = 0.f;
+  float F13 = 0.f, F14 = 0.f, F15 = 0.f;
+  if (FORCE) {
+    const float uF = ux * Fx + uy * Fy + uz * Fz;
+    F1 = 38.f * uF;
+    F2 = -11.f * uF;
+    F4 = (-2.f / 3.f) * Fx;
+    F6 = (-2.f / 3.f) * Fy;
+    F8 = (-2.f / 3.f) * Fz;
+    F9 = 2.f * (2.f * ux * Fx - uy * Fy - uz * Fz);
+    F10 = -0.5f * F9;
+    F11 = 2.f * (uy * Fy - uz * Fz);
+    F12 = -0.5f * F11;
+    F13 = ux * Fy + uy * Fx;
+    F14 = uy * Fz + uz * Fy;
+    F15 = ux * Fz + uz * Fx;
+  }
+  // delta_k / D_k
+  const float a1 = FORCE ? -a.rs[1] * e1 + a.rf[1] * F1 : -a.rs[1] * e1;
+  const float a2 = FORCE ? -a.rs[2] * e2 + a.rf[2] * F2 : -a.rs[2] * e2;
+  const float a9 = (FORCE ? -sv * e9 + hv * F9 : -sv * e9) * (1.f / 36.f);
+  const float a10 = FORCE ? -a.rs[10] * e10 + a.rf[10] * F10 : -a.rs[10] * e10;
+  const float a11 = (FORCE ? -sv * e11 + hv * F11 : -sv * e11) * (1.f / 12.f);
+  const float a12 = FORCE ? -a.rs[12] * e12 + a.rf[12] * F12 : -a.rs[12] * e12;
+  const float a13 = (FORCE ? -sv * e13 + hv * F13 : -sv * e13) * 0.25f;
+  const float a14 = (FORCE ? -sv * e14 + hv * F14 : -sv * e14) * 0.25f;
+  const float a15 = (FORCE ? -sv * e15 + hv * F15 : -sv * e15) * 0.25f;
+  const float b3 = 0.1f * Fx, b5 = 0.1f * Fy, b7 = 0.1f * Fz;
+  const float b4 = FORCE ? -a.rs[4] * e4 + a.rf[4] * F4 : -a.rs[4] * e4;
+  const float b6 = FORCE ? -a.rs[6] * e6 + a.rf[6] * F6 : -a.rs[6] * e6;
+  const float b8 = FORCE ? -a.rs[8] * e8 + a.rf[8] * F8 : -a.rs[8] * e8;
+  const float b16 = -a.rs[16] * m16, b17 = -a.rs[17] * m17, b18 = -a.rs[18] * m18;
+
+  // f* = f + M^T diag(1/D) delta, assembled per opposite pair
+  const float P = 8.f * a1 + a2, Qx = -11.f * a1 - 4.f * a2, R9 = -30.f * a1 + 12.f * a2;
+  const float b910 = a9 + a10, c1112 = a11 + a12;
+  const float h = 2.f * a10 - a9, kk = 2.f * a12 - a11;
+  float E[9], O[9];
+  E[0] = P - 2.f * b910 + a14;
+  E[4] = P - 2.f * b910 - a14;
+  E[1] = P + b910 - c1112 + a15;
+  E[3] = P + b910 - c1112 - a15;
+  E[5] = P + b910 + c1112 + a13;
+  E[7] = P + b910 + c1112 - a13;
+  E[2] = Qx + h + kk;
+  E[6] = Qx + h - kk;
+  E[8] = Qx + 2.f * a9 - 4.f * a10;
+  const float B34 = FORCE ? b3 + b4 : b4, B56 = FORCE ? b5 + b6 : b6, B78 = FORCE ? b7 + b8 : b8;
+  O[0] = -B56 - B78 - b17 + b18;
+  O[4] = B56 - B78 + b17 + b18;
+  O[1] = -B34 - B78 + b16 - b18;
+  O[3] = B34 - B78 - b16 - b18;
+  O[5] = -B34 - B56 - b16 + b17;
+  O[7] = B34 - B56 + b16 + b17;
+  O[2] = 4.f * b8 - (FORCE ? b7 : 0.f);
+  O[6] = 4.f * b6 - (FORCE ? b5 : 0.f);
+  O[8] = 4.f * b4 - (FORCE ? b3 : 0.f);
+#pragma unroll
+  for (int k = 0; k < 9; ++k) {
+    const float lo = f[k], hi = f[18 - k];
+    f[k] = lo + E[k] + O[k];
+    f[18 - k] = hi + E[k] - O[k];
+  }
+  f[9] = f9 + R9;
+}
+
+template <bool F16>
+__global__ __launch_bounds__(BLOCK) void collide_kernel(CollideArgs a) {
+  __shared__ float lds_u2[2][2][ZT];
+  const int L = xcd_remap(blockIdx.x, a.nblocks);
+  const int zci = L % a.zc;
+  const int rest = L / a.zc;
+  const int gy = rest % a.yg;
+  const int x = rest / a.yg;
+  const int lane = threadIdx.x & (ZT - 1);
+  const int ty = uni(threadIdx.x >> 6);
+  const int base = min(YROWS * gy, a.ny - YROWS);
+  const int y = base + ty;
+  const bool owned = y >= YROWS * gy;  // rows shared with the previous group (ragged ny) are helpers only
+  const int zraw = zci * ZT + lane;
+  const bool active = zraw < a.nz;
+  const int z = active ? zraw : a.nz - 1;
+  const int zm = z == 0 ? a.nz - 1 : z - 1;
+  const int zp = z == a.nz - 1 ? 0 : z + 1;
+
+  const Geo g = make_geo(a, x, y);
+  float f[Q];
+#pragma unroll
+  for (int i = 0; i < Q; ++i) f[i] = pull_dir<F16>(a, g, i, z, zm, zp, 0.f);
+
+  const bool inflow = a.xbc == LBM_X_INFLOW;
+  if (inflow && x == a.nx - 1) {  // convective outlet for c_x < 0
+    const Geo g2 = make_geo(a, x - 1, y);
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+      const int i = OUT5[k];
+      const float up = pull_dir<F16>(a, g2, i, z, zm, zp, 0.f);
+      const int hidx = (k * a.ny + y) * a.nz + z;
+      const float v = (a.hist_in[hidx] + a.u_conv * up) * a.inv_1pu;
+      f[i] = v;
+      if (active && owned) a.hist_out[hidx] = v;
+    }
+  }
+  if (inflow && x == 0) inlet_regularize(a, y, z, f);
+
+  // density and momentum before the force (Eq. (10)-(11))
+  float rho = 0.f;
+#pragma unroll
+  for (int i = 0; i < Q; ++i) rho += f[i];
+  const float jx = (f[3] + f[7] + f[10] + f[13] + f[17]) - (f[1] + f[5] + f[8] + f[11] + f[15]);
+  const float jy = (f[4] + f[11] + f[12] + f[13] + f[18]) - (f[0] + f[5] + f[6] + f[7] + f[14]);
+  const float jz = (f[14] + f[15] + f[16] + f[17] + f[18]) - (f[0] + f[1] + f[2] + f[3] + f[4]);
+
+  float Fx = 0.f, Fy = 0.f, Fz = 0.f;
+  bool force = a.has_g != 0;
+  if (force) {
+    Fx = rho * a.g[0];
+    Fy = rho * a.g[1];
+    Fz = rho * a.g[2];
+  }
+  if (a.wall_model) {
+    const bool bot = base == 0, top = base == a.ny - YROWS;
+    if (bot || top) {  // block-uniform: the block holds a wall row and its neighbour
+      const float ir = 1.f / rho;
+      if (bot && y == 1) {
+        lds_u2[0][0][lane] = jx * ir;
+        lds_u2[0][1][lane] = jz * ir;
+      }
+      if (top && y == a.ny - 2) {
+        lds_u2[1][0][lane] = jx * ir;
+        lds_u2[1][1][lane] = jz * ir;
+      }
+      __syncthreads();
+      const bool wb = bot && y == 0, wt = top && y == a.ny - 1;
+      if (wb || wt) {
+        const int w = wb ? 0 : 1;
+        float fwx, fwz;
+        wall_force(a, rho, jx * ir, jz * ir, lds_u2[w][0][lane], lds_u2[w][1][lane], fwx, fwz);
+        Fx += fwx;
+        Fz += fwz;
+        force = true;
+      }
+    }
+  }
+
+  float ux, uy, uz;
+  if (force)
+    collide<true>(a, f, rho, jx, jy, jz, Fx, Fy, Fz, ux, uy, uz);
+  else
+    collide<false>(a, f, rho, jx, jy, jz, 0.f, 0.f, 0.f, ux, uy, uz);
+
+  if (!(rho > 0.f && rho < 1e30f)) atomicOr(a.err, ERRBIT_NONFINITE);
+
+  const int n = rowoff(a, x, y) + z;
+  if (active && owned) {
+#pragma unroll
+    for (int i = 0; i < Q; ++i) Pop<F16>::st(a.dst[i], i, n, f[i]);
+  }
+
+  if (a.stats_on) {
+    const int p = a.plane_of_x[x];
+    if (p >= 0 && owned) {
+      const bool on = active;
+      double v[9];
+      const double dx = ux, dy = uy, dz = uz;
+      v[0] = on ? dx : 0.0;
+      v[1] = on ? dy : 0.0;
+      v[2] = on ? dz : 0.0;
+      v[3] = on ? dx * dx : 0.0;
+      v[4] = on ? dy * dy : 0.0;
+      v[5] = on ? dz * dz : 0.0;
+      v[6] = on ? dx * dy : 0.0;
+      v[7] = on ? dx * dz : 0.0;
+      v[8] = on ? dy * dz : 0.0;
+#pragma unroll
+      for (int k = 0; k < 9; ++k)
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) v[k] += __shfl_xor(v[k], off, ZT);
+      if (lane == 0) {
+        double* s = a.stats + (((size_t)p * a.ny + y) * a.zc + zci) * 9;
+#pragma unroll
+        for (int k = 0; k < 9; ++k) s[k] += v[k];
+      }
+    }
+  }
+}
+
+// Pull with the wall rules only (debug map); unset populations are -1.
+__global__ __launch_bounds__(BLOCK) void stream_only_kernel(CollideArgs a) {
+  const int L = blockIdx.x;
+  const int zci = L % a.zc;
+  const int rest = L / a.zc;
+  const int gy = rest % a.yg;
+  const int x = rest / a.yg;
+  const int lane = threadIdx.x & (ZT - 1);
+  const int ty = uni(threadIdx.x >> 6);
+  const int base = min(YROWS * gy, a.ny - YROWS);
+  const int y = base + ty;
+  const bool owned = y >= YROWS * gy;
+  const int z = zci * ZT + lane;
+  if (z >= a.nz || !owned) return;
+  const int zm = z == 0 ? a.nz - 1 : z - 1;
+  const int zp = z == a.nz - 1 ? 0 : z + 1;
+  const Geo g = make_geo(a, x, y);
+  const int n = rowoff(a, x, y) + z;
+#pragma unroll
+  for (int i = 0; i < Q; ++i) Pop<false>::st(a.dst[i], i, n, pull_dir<false>(a, g, i, z, zm, zp, -1.f));
+}
+
+struct PtrTable {
+  void* p[Q];
+};
+
+template <bool F16>
+__global__ void init_kernel(PtrTable dstp, float* hist, const float* rho, const float* u, const float* pert,
+                            float eps, int nx, int ny, int nz, int N) {
+  const int n = blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= N) return;
+  const float r = rho ? rho[n] : 1.f;
+  const float ux = u[n], uy = u[N + n], uz = u[2 * N + n];
+  const float uu15 = 1.5f * (ux * ux + uy * uy + uz * uz);
+  const int z = n % nz, y = (n / nz) % ny, x = n / (nz * ny);
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    const float cu = CX[i] * ux + CY[i] * uy + CZ[i] * uz;
+    float v = (float)WD[i] * r * (1.f + 3.f * cu + 4.5f * cu * cu - uu15);
+    if (pert) v += eps * (float)WD[i] * pert[(size_t)i * N + n];
+    Pop<F16>::st(dstp.p[i], i, n, v);
+    if (hist && x == nx - 1) {
+#pragma unroll
+      for (int k = 0; k < 5; ++k)
+        if (OUT5[k] == i) hist[(k * ny + y) * nz + z] = v;
+    }
+  }
+}
+
+template <bool F16>
+__global__ void export_kernel(PtrTable srcp, float* out, int N) {
+  const int n = blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= N) return;
+#pragma unroll
+  for (int i = 0; i < Q; ++i) out[(size_t)i * N + n] = Pop<F16>::ld(srcp.p[i], i, n);
+}
+
+__global__ void copy_kernel(const float4* __restrict__ src, float4* __restrict__ dst, int64_t n4) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n4; k += stride) dst[k] = src[k];
+}
+
+const double kD[Q] = {19, 2394, 252, 10, 40, 10, 40, 10, 40, 36, 72, 12, 24, 4, 4, 4, 8, 8, 8};
+
+void fill_args(lbm_ctx* h, CollideArgs& a, int src, int dst) {
+  const lbm_config& c = h->cfg;
+  const size_t es = c.storage == LBM_STORE_F16DEV ? 2 : 4;
+  for (int i = 0; i < Q; ++i) {
+    a.src[i] = static_cast<const char*>(h->f[src]) + (size_t)i * h->N * es;
+    a.dst[i] = static_cast<char*>(h->f[dst]) + (size_t)i * h->N * es;
+  }
+  a.hist_in = h->hist[src];
+  a.hist_out = h->hist[dst];
+  a.u_in = h->stg_bound ? h->stg.u_in : nullptr;
+  a.stats = h->d_stats;
+  a.plane_of_x = h->d_plane_of_x;
+  a.err = h->d_err;
+  a.nx = c.nx;
+  a.ny = c.ny;
+  a.nz = c.nz;
+  a.zc = h->zc;
+  a.yg = h->yg;
+  a.nblocks = h->nblocks;
+  a.ywall = c.ywall;
+  a.xbc = c.xbc;
+  a.wall_model = c.wall_model;
+  a.newton_iters = c.newton_iters;
+  a.stats_on = h->stats_on && h->d_stats != nullptr;
+  a.has_g = (c.g[0] != 0.0 || c.g[1] != 0.0 || c.g[2] != 0.0) ? 1 : 0;
+  a.tau0 = (float)c.tau0;
+  a.tau0sq = (float)(c.tau0 * c.tau0);
+  a.smag = (float)(18.0 * std::sqrt(2.0) * c.cs_smag * c.cs_smag);
+  for (int k = 0; k < 3; ++k) a.g[k] = (float)c.g[k];
+  const double nu0 = (c.tau0 - 0.5) / 3.0;
+  a.nu0 = (float)nu0;
+  a.inv_nu0 = (float)(1.0 / nu0);
+  a.y_wall = (float)c.y_wall;
+  a.kappa = (float)c.kappa;
+  a.inv_kappa = (float)(1.0 / c.kappa);
+  a.b_reich = (float)c.b_reich;
+  a.u_conv = (float)c.u_conv;
+  a.inv_1pu = (float)(1.0 / (1.0 + c.u_conv));
+  for (int k = 0; k < Q; ++k) {
+    a.rs[k] = (float)(c.s[k] / kD[k]);
+    a.rf[k] = (float)((1.0 - 0.5 * c.s[k]) / kD[k]);
+  }
+}
+
+}  // namespace
+
+hipError_t launch_collide(lbm_ctx* h, int src, int dst) {
+  CollideArgs a;
+  fill_args(h, a, src, dst);
+  if (h->cfg.storage == LBM_STORE_F16DEV)
+    collide_kernel<true><<<h->nblocks, BLOCK, 0, h->stream>>>(a);
+  else
+    collide_kernel<false><<<h->nblocks, BLOCK, 0, h->stream>>>(a);
+  return hipGetLastError();
+}
+
+hipError_t launch_stream_only(lbm_ctx* h, int src, int dst) {
+  CollideArgs a;
+  fill_args(h, a, src, dst);
+  stream_only_kernel<<<h->nblocks, BLOCK, 0, h->stream>>>(a);
+  return hipGetLastError();
+}
+
+// The 19 per-direction base pointers of buffer `which`.
+static PtrTable dir_pointers(lbm_ctx* h, int which) {
+  const size_t es = h->cfg.storage == LBM_STORE_F16DEV ? 2 : 4;
+  PtrTable t;
+  for (int i = 0; i < Q; ++i) t.p[i] = static_cast<char*>(h->f[which]) + (size_t)i * h->N * es;
+  return t;
+}
+
+hipError_t launch_init(lbm_ctx* h, const float* rho, const float* u, const float* pert, float eps) {
+  const PtrTable t = dir_pointers(h, h->cur);
+  const int N = (int)h->N;
+  const int nb = (N + 255) / 256;
+  float* hist = h->cfg.xbc == LBM_X_INFLOW ? h->hist[h->cur] : nullptr;
+  if (h->cfg.storage == LBM_STORE_F16DEV)
+    init_kernel<true><<<nb, 256, 0, h->stream>>>(t, hist, rho, u, pert, eps, h->cfg.nx, h->cfg.ny, h->cfg.nz, N);
+  else
+    init_kernel<false><<<nb, 256, 0, h->stream>>>(t, hist, rho, u, pert, eps, h->cfg.nx, h->cfg.ny, h->cfg.nz, N);
+  return hipGetLastError();
+}
+
+hipError_t launch_export(lbm_ctx* h, float* out) {
+  const PtrTable t = dir_pointers(h, h->cur);
+  const int N = (int)h->N;
+  const int nb = (N + 255) / 256;
+  if (h->cfg.storage == LBM_STORE_F16DEV)
+    export_kernel<true><<<nb, 256, 0, h->stream>>>(t, out, N);
+  else
+    export_kernel<false><<<nb, 256, 0, h->stream>>>(t, out, N);
+  return hipGetLastError();
+}
+
+hipError_t launch_copy(const void* src, void* dst, int64_t bytes, hipStream_t s) {
+  const int64_t n4 = bytes / 16;
+  int64_t nb = (n4 + 255) / 256;
+  if (nb > 65536) nb = 65536;
+  if (nb < 1) nb = 1;
+  copy_kernel<<<(unsigned)nb, 256, 0, s>>>(static_cast<const float4*>(src), static_cast<float4*>(dst), n4);
+  return hipGetLastError();
+}
+
+}  // namespace lbm

@@ -1,0 +1,91 @@
+// Internal declarations shared by the library's translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <vector>
+
+#include "../../include/lbm.h"
+#include "lattice.h"
+
+namespace lbm {
+
+// Bits of the device error word.
+constexpr int ERRBIT_MACH = 1;
+constexpr int ERRBIT_NONFINITE = 2;
+
+constexpr int ZT = 64;     // z-lanes per wave (one wave = one (x, y) row segment)
+constexpr int YROWS = 4;   // rows (waves) per collide block
+constexpr int BLOCK = ZT * YROWS;
+
+// Arguments of the fused collide-stream kernel (passed by value).
+struct CollideArgs {
+  const void* src[Q];  // per-direction base of the state s_n
+  void* dst[Q];        // per-direction base of s_{n+1}
+  const float* hist_in;   // [5][ny][nz]
+  float* hist_out;        // [5][ny][nz]
+  const float* u_in;      // [3][ny][nz]
+  double* stats;          // [n_planes][ny][zc][9]
+  const int* plane_of_x;  // [nx], -1 when not sampled
+  int* err;
+  int nx, ny, nz, zc, yg, nblocks;
+  int ywall, xbc, wall_model, newton_iters, stats_on, has_g;
+  float tau0, tau0sq, smag;  // smag = 18 sqrt(2) C_s^2
+  float g[3];
+  float nu0, inv_nu0, y_wall, kappa, inv_kappa, b_reich;
+  float u_conv, inv_1pu;
+  float rs[Q], rf[Q];  // s_k / D_k and (1 - s_k/2) / D_k for the fixed-rate moments
+};
+
+struct StgTables {
+  int n_modes = 0;
+  int cap_trigz = 0, cap_amp3 = 0, cap_ky = 0, cap_chol = 0, cap_sb = 0, cap_urans = 0;
+  float* amp3 = nullptr;    // [3][N] sqrt(6 q) sigma
+  double* ky = nullptr;     // [N] kmag d_y
+  float2* trigz = nullptr;  // [N][nz] (cos, sin)(kmag d_z z mod 2 pi)
+  float* chol = nullptr;    // [6][ny]
+  float* sb = nullptr;      // [ny] amplitude scaling of each row
+  float* urans = nullptr;   // [3][ny]
+};
+
+}  // namespace lbm
+
+struct lbm_ctx {
+  lbm_config cfg{};
+  hipStream_t stream = nullptr;
+  int device = 0;
+  void* f[2] = {nullptr, nullptr};
+  float* hist[2] = {nullptr, nullptr};
+  int cur = 0;
+  int64_t time = 0;
+  int64_t N = 0;
+  int zc = 0, yg = 0, nblocks = 0;
+  int* d_err = nullptr;
+  int* d_plane_of_x = nullptr;
+  double* d_stats = nullptr;
+  int n_planes = 0;
+  int stats_on = 0;
+  int64_t n_samples = 0;
+  bool stg_bound = false;
+  lbm_stg stg{};
+  lbm::StgTables tab;
+  int timing = 0;
+  std::vector<hipEvent_t> ev;  // pairs (start, stop) of timed launches
+  int64_t ev_used = 0;
+  double timed_ms = 0.0;
+  int64_t timed_launches = 0;
+};
+
+namespace lbm {
+// collide.hip
+hipError_t launch_collide(lbm_ctx* h, int src, int dst);
+hipError_t launch_stream_only(lbm_ctx* h, int src, int dst);
+hipError_t launch_init(lbm_ctx* h, const float* rho, const float* u, const float* pert, float eps);
+hipError_t launch_export(lbm_ctx* h, float* out);
+hipError_t launch_copy(const void* src, void* dst, int64_t bytes, hipStream_t s);
+// stg.hip
+hipError_t launch_stg_bind(lbm_ctx* h, const lbm_stg* s);
+hipError_t launch_stg_fill(lbm_ctx* h, double t);
+hipError_t launch_inflow_reichardt(lbm_ctx* h, double u_tau, double* u_rans);
+}  // namespace lbm

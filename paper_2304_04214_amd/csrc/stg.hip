@@ -1,0 +1,176 @@
+// Synthetic turbulence generator for the inlet plane (Sec. III.A,
+// Eq. (22)-(25); Algorithm 1 steps 3-5) and the Reichardt mean inflow.
+//
+// Binding precomputes the time-independent tables: mode amplitudes
+// sqrt(6 q) sigma, the spanwise phase factors (cos, sin)(k d_z z) reduced in
+// FP64, the Cholesky factors a(y) of R(y) and the per-row scalings s_b.
+// Filling evaluates, per step, the (y, t)-dependent phase
+// k d_y (y + 1/2) + omega t + phi in FP64 (reduced mod 2 pi), and combines it
+// with the spanwise factor by angle addition, so the FP32 cosines never see a
+// large argument.  The mode sum itself is FP32.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+
+#include "internal.h"
+
+namespace lbm {
+namespace {
+
+constexpr double TWO_PI = 6.283185307179586476925286766559;
+constexpr float MACH_LIMIT = 0.17320508075688773f;  // 0.3 c_s, c_s = 1/sqrt(3)
+
+__global__ void stg_bind_kernel(lbm_stg s, StgTables t, int ny, int nz) {
+  const int N = s.n_modes;
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t nzN = (int64_t)N * nz;
+  if (k < nzN) {
+    const int n = (int)(k / nz), z = (int)(k % nz);
+    const double ph = fmod(s.kmag[n] * s.d[2 * N + n] * (double)z, TWO_PI);
+    double sn, cs;
+    sincos(ph, &sn, &cs);
+    t.trigz[k] = make_float2((float)cs, (float)sn);
+    return;
+  }
+  const int64_t k2 = k - nzN;
+  if (k2 < N) {
+    const int n = (int)k2;
+    const double a = sqrt(6.0 * s.q[n]);  // Eq. (25): sqrt(6) sqrt(q^n)
+    for (int c = 0; c < 3; ++c) t.amp3[c * N + n] = (float)(a * s.sigma[c * N + n]);
+    t.ky[n] = s.kmag[n] * s.d[N + n];
+    return;
+  }
+  const int64_t k3 = k2 - N;
+  if (k3 < ny) {
+    const int y = (int)k3;
+    // Eq. (24): lower Cholesky factor of R (FP64), a11 a21 a22 a31 a32 a33
+    const double R11 = s.R[y], R21 = s.R[ny + y], R22 = s.R[2 * ny + y];
+    const double R31 = s.R[3 * ny + y], R32 = s.R[4 * ny + y], R33 = s.R[5 * ny + y];
+    const double a11 = sqrt(R11);
+    const double a21 = R21 / a11;
+    const double a22 = sqrt(R22 - a21 * a21);
+    const double a31 = R31 / a11;
+    const double a32 = (R32 - a21 * a31) / a22;
+    const double a33 = sqrt(R33 - a31 * a31 - a32 * a32);
+    t.chol[y] = (float)a11;
+    t.chol[ny + y] = (float)a21;
+    t.chol[2 * ny + y] = (float)a22;
+    t.chol[3 * ny + y] = (float)a31;
+    t.chol[4 * ny + y] = (float)a32;
+    t.chol[5 * ny + y] = (float)a33;
+    int b = s.bin_of_y[y];
+    b = b < 0 ? 0 : (b >= s.n_bins ? s.n_bins - 1 : b);  // out-of-range bins are clamped
+    t.sb[y] = (float)s.amp_bin[b];
+    for (int c = 0; c < 3; ++c) t.urans[c * ny + y] = (float)s.u_rans[c * ny + y];
+  }
+}
+
+// One wave per inlet row y, 64 spanwise nodes per wave, 4 rows per block.
+__global__ __launch_bounds__(256) void stg_fill_kernel(lbm_stg s, StgTables t, int ny, int nz, double time,
+                                                       int* err) {
+  __shared__ float2 rowph[4][LBM_MAX_MODES];
+  const int lane = threadIdx.x & 63;
+  const int w = threadIdx.x >> 6;
+  const int yr = blockIdx.y * 4 + w;
+  const int y = yr < ny ? yr : ny - 1;
+  const int z = blockIdx.x * 64 + lane;
+  const int N = s.n_modes;
+  // (y, t)-dependent phase of every mode, FP64 then reduced to [0, 2 pi)
+  for (int n = lane; n < N; n += 64) {
+    const double ph = fmod(t.ky[n] * (y + 0.5) + s.omega[n] * time + s.phi[n], TWO_PI);
+    double sn, cs;
+    sincos(ph, &sn, &cs);
+    rowph[w][n] = make_float2((float)cs, (float)sn);
+  }
+  __syncthreads();
+  if (yr >= ny || z >= nz) return;
+  float v0 = 0.f, v1 = 0.f, v2 = 0.f;
+  const float2* tz = t.trigz + z;
+  for (int n = 0; n < N; ++n) {
+    const float2 a = rowph[w][n];
+    const float2 b = tz[(int64_t)n * nz];
+    const float c = a.x * b.x - a.y * b.y;  // cos(alpha + beta)
+    v0 += t.amp3[n] * c;
+    v1 += t.amp3[N + n] * c;
+    v2 += t.amp3[2 * N + n] * c;
+  }
+  // Eq. (23): u' = a v' with the lower-triangular Cholesky factor; Eq. (22)
+  const float a11 = t.chol[y], a21 = t.chol[ny + y], a22 = t.chol[2 * ny + y];
+  const float a31 = t.chol[3 * ny + y], a32 = t.chol[4 * ny + y], a33 = t.chol[5 * ny + y];
+  const float p0 = a11 * v0;
+  const float p1 = a21 * v0 + a22 * v1;
+  const float p2 = a31 * v0 + a32 * v1 + a33 * v2;
+  const float sb = t.sb[y];
+  const int o = y * nz + z, pl = ny * nz;
+  const float ux = t.urans[y] + sb * p0;
+  s.u_in[o] = ux;
+  s.u_in[pl + o] = t.urans[ny + y] + sb * p1;
+  s.u_in[2 * pl + o] = t.urans[2 * ny + y] + sb * p2;
+  if (s.fluct) {
+    s.fluct[o] = p0;
+    s.fluct[pl + o] = p1;
+    s.fluct[2 * pl + o] = p2;
+  }
+  if (!(fabsf(ux) < MACH_LIMIT)) atomicOr(err, ERRBIT_MACH);
+}
+
+// Reichardt law with the constants of the configuration (Sec. II.C, Eq. (16)).
+__global__ void inflow_reichardt_kernel(double* u, int ny, double u_tau, double nu0, double kappa, double B) {
+  const int y = blockIdx.x * blockDim.x + threadIdx.x;
+  if (y >= ny) return;
+  const double d = fmin(y + 0.5, ny - y - 0.5);
+  const double yp = d * u_tau / nu0;
+  const double up = log1p(kappa * yp) / kappa - B * (expm1(-yp / 11.0) + (yp / 11.0) * exp(-yp / 3.0));
+  u[y] = u_tau * up;
+  u[ny + y] = 0.0;
+  u[2 * ny + y] = 0.0;
+}
+
+template <class T>
+hipError_t grow(T** p, int* cap, int need) {
+  if (*p && *cap >= need) return hipSuccess;
+  if (*p) {
+    hipError_t e = hipFree(*p);
+    if (e != hipSuccess) return e;
+    *p = nullptr;
+  }
+  hipError_t e = hipMalloc(reinterpret_cast<void**>(p), sizeof(T) * (size_t)need);
+  if (e == hipSuccess) *cap = need;
+  return e;
+}
+
+}  // namespace
+
+hipError_t launch_stg_bind(lbm_ctx* h, const lbm_stg* s) {
+  const int N = s->n_modes, ny = h->cfg.ny, nz = h->cfg.nz;
+  StgTables& t = h->tab;
+  hipError_t e;
+  if ((e = grow(&t.trigz, &t.cap_trigz, N * nz)) != hipSuccess) return e;
+  if ((e = grow(&t.amp3, &t.cap_amp3, 3 * N)) != hipSuccess) return e;
+  if ((e = grow(&t.ky, &t.cap_ky, N)) != hipSuccess) return e;
+  if ((e = grow(&t.chol, &t.cap_chol, 6 * ny)) != hipSuccess) return e;
+  if ((e = grow(&t.sb, &t.cap_sb, ny)) != hipSuccess) return e;
+  if ((e = grow(&t.urans, &t.cap_urans, 3 * ny)) != hipSuccess) return e;
+  t.n_modes = N;
+  const int64_t total = (int64_t)N * nz + N + ny;
+  const int nb = (int)((total + 255) / 256);
+  stg_bind_kernel<<<nb, 256, 0, h->stream>>>(*s, t, ny, nz);
+  return hipGetLastError();
+}
+
+hipError_t launch_stg_fill(lbm_ctx* h, double time) {
+  const int ny = h->cfg.ny, nz = h->cfg.nz;
+  dim3 grid((nz + 63) / 64, (ny + 3) / 4);
+  stg_fill_kernel<<<grid, 256, 0, h->stream>>>(h->stg, h->tab, ny, nz, time, h->d_err);
+  return hipGetLastError();
+}
+
+hipError_t launch_inflow_reichardt(lbm_ctx* h, double u_tau, double* u_rans) {
+  const int ny = h->cfg.ny;
+  const double nu0 = (h->cfg.tau0 - 0.5) / 3.0;
+  inflow_reichardt_kernel<<<(ny + 63) / 64, 64, 0, h->stream>>>(u_rans, ny, u_tau, nu0, h->cfg.kappa,
+                                                                 h->cfg.b_reich);
+  return hipGetLastError();
+}
+
+}  // namespace lbm

@@ -13,9 +13,14 @@ def pytest_configure(config):
 
 
 @pytest.fixture(scope="session", autouse=True)
-def _oracle_built():
+def _built():
+    """Build the oracle, and the HIP library only if nothing is built yet."""
     import oracle
     oracle.build(force=False)
+    from paper_2304_04214_amd import _abi
+    if not os.path.exists(_abi.LIB_PATH):
+        from paper_2304_04214_amd.build import build
+        build()
     yield
 
 

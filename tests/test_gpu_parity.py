@@ -1,0 +1,199 @@
+"""Parity of the HIP path with the FP64 oracle on the same seeded inputs.
+
+Sizes span several 64-wide z tiles with a ragged tail, y groups with a ragged
+tail, and every boundary combination.  Tolerances:
+  * streaming index map: bit-exact (integer-coded FP32 populations < 2^24);
+  * FP32 fields over 20 steps: 1e-5 relative L-inf;
+  * FP16-deviation storage over 20 steps: 2e-4 relative L-inf (half-ulp
+    rounding of deviations |h| < 2^-6 is <= 2^-18 per step, about 20 such
+    roundings accumulate, against max f = 1/3).
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from paper_2304_04214_amd import _abi as A
+from paper_2304_04214_amd.channel import Channel
+from parity_cases import Case, rel_linf
+
+pytestmark = [pytest.mark.gpu,
+              pytest.mark.skipif(not torch.cuda.is_available(), reason="needs a GPU")]
+
+TOL32 = 1e-5
+TOL16 = 2e-4
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+@pytest.mark.parametrize("ywall,xbc,shape", [
+    ("periodic", "periodic", (5, 6, 70)),
+    ("bounceback", "periodic", (5, 10, 70)),
+    ("slip", "periodic", (4, 9, 3)),
+    ("bounceback", "inflow", (5, 6, 130)),
+    ("slip", "inflow", (6, 10, 65)),
+    ("slip", "inflow", (3, 4, 1)),
+])
+def test_stream_index_map_bit_exact(ywall, xbc, shape):
+    nx, ny, nz = shape
+    _say("stream map", ywall, xbc, shape)
+    ch = Channel(nx, ny, nz, tau0=0.6, ywall=ywall, xbc=xbc, wall_model=False)
+    codes = np.arange(19 * nx * ny * nz, dtype=np.float64).reshape(19, nx, ny, nz)
+    assert codes.max() < 2 ** 24
+    ch.f[0].copy_(torch.as_tensor(codes, dtype=torch.float32))
+    ch.stream_only()
+    ch.sync()
+    gpu = ch.populations().cpu().numpy().astype(np.float64)
+    ocfg = O.make_cfg(nx, ny, nz, ywall={"periodic": 0, "bounceback": 1, "slip": 2}[ywall],
+                      xbc={"periodic": 0, "inflow": 1}[xbc])
+    ref = O.stream_only(ocfg, codes)
+    assert np.array_equal(gpu, ref)
+
+
+PARITY_CASES = {
+    "periodic-smag-force": dict(shape=(6, 9, 70), kw=dict(ywall="periodic", xbc="periodic", wall_model=False,
+                                                         g=(2e-5, -1e-5, 5e-6), tau0=0.53)),
+    "bounceback-wallmodel": dict(shape=(5, 10, 70), kw=dict(ywall="bounceback", xbc="periodic", wall_model=True,
+                                                           g=(1e-5, 0.0, 0.0))),
+    "slip-wallmodel": dict(shape=(4, 6, 67), kw=dict(ywall="slip", xbc="periodic", wall_model=True)),
+    "slip-inflow-wallmodel": dict(shape=(7, 10, 70), kw=dict(ywall="slip", xbc="inflow", wall_model=True,
+                                                            n_modes=40)),
+    "bounceback-inflow-ny4": dict(shape=(5, 4, 66), kw=dict(ywall="bounceback", xbc="inflow", wall_model=True)),
+    "slip-inflow-nz1": dict(shape=(3, 5, 1), kw=dict(ywall="slip", xbc="inflow", wall_model=True)),
+    "re1000-like": dict(shape=(8, 12, 64), kw=dict(ywall="slip", xbc="inflow", wall_model=True,
+                                                  tau0=0.5004270558446486, u_tau=0.004448498381757104,
+                                                  n_modes=50)),
+}
+
+
+@pytest.mark.parametrize("name", list(PARITY_CASES))
+def test_fp32_fields_match_oracle_over_20_steps(name):
+    spec = PARITY_CASES[name]
+    _say("parity", name, spec["shape"])
+    c = Case(*spec["shape"], **spec["kw"])
+    c.ch.step(20)
+    c.ch.sync()
+    st, f_or, hist_or, _ = c.run_oracle(20)
+    assert st == O.OK
+    f_g, hist_g = c.gpu_state()
+    err = rel_linf(f_g, f_or)
+    dev = np.abs(f_g - f_or).max() / np.abs(f_or - O.tables()["w"][:, None, None, None]).max()
+    _say("  rel Linf %.3e   (vs max |f - w|: %.3e)" % (err, dev))
+    assert err <= TOL32
+    if c.xbc == "inflow":
+        assert rel_linf(hist_g, hist_or) <= TOL32
+
+
+def test_c1_oracle_config_50_steps():
+    """The 64x32x32 FP64-oracle configuration (bounce-back walls, wall model, STG N=100,
+    tau 0.52, C_s 0.1) in FP32 on the GPU: fields after 20 and 50 steps."""
+    _say("c1 config")
+    c = Case(64, 32, 32, ywall="bounceback", xbc="inflow", wall_model=True, tau0=0.52, cs_smag=0.1,
+             n_modes=100, seed=1)
+    c.ch.step(20)
+    c.ch.sync()
+    st, f20, h20, _ = c.run_oracle(20)
+    assert st == O.OK
+    f_g, _ = c.gpu_state()
+    e20 = rel_linf(f_g, f20)
+    c.ch.step(30)
+    c.ch.sync()
+    st, f50, _, _ = O.run(c.ocfg, f20, h20, 20, 30, stg=c.stg_or)
+    f_g, _ = c.gpu_state()
+    e50 = rel_linf(f_g, f50)
+    _say("  rel Linf 20 steps %.3e, 50 steps %.3e" % (e20, e50))
+    assert e20 <= TOL32
+    assert e50 <= 5 * TOL32
+
+
+def test_statistics_match_oracle():
+    c = Case(8, 10, 70, ywall="slip", xbc="inflow", wall_model=True, n_modes=30)
+    planes = [1, 4, 7]
+    c.ch.step(3)
+    c.ch.stats_attach(planes)
+    c.ch.step(10)
+    means, n = c.ch.stats_read()
+    assert n == 10
+    _, f3, h3, _ = c.run_oracle(3)
+    acc = np.zeros((3, c.ny, 9))
+    O.run(c.ocfg, f3, h3, 3, 10, stg=c.stg_or, planes=planes, acc=acc)
+    ref = acc / (10 * c.nz)
+    err = np.abs(means - ref).max() / np.abs(ref).max()
+    _say("stats rel err %.3e" % err)
+    assert err <= TOL32
+
+
+@pytest.mark.parametrize("t", [0.0, 1.0, 137.0, 5000.0])
+def test_stg_plane_matches_oracle(t):
+    c = Case(4, 10, 70, ywall="slip", xbc="inflow", wall_model=True, n_modes=300, amp_scale=3.0)
+    u = c.ch.stg_fill(t).cpu().numpy()
+    st, ref, fl = O.stg_plane(c.ocfg, c.stg_or, t, want_fluct=True)
+    assert st == O.OK
+    err = np.abs(u - ref).max() / np.abs(ref).max()
+    errf = np.abs(c.ch.fluct.cpu().numpy() - fl).max() / np.abs(fl).max()
+    _say("stg t=%g rel err %.3e fluct %.3e" % (t, err, errf))
+    assert err <= TOL32 and errf <= 1e-5 * 50
+
+
+def test_reichardt_inflow_matches_oracle_fp64():
+    c = Case(4, 64, 8, ywall="slip", xbc="inflow", wall_model=True, tau0=0.5004270558446486,
+             u_tau=0.004448498381757104)
+    assert np.abs(c.U_g.cpu().numpy() - c.U_or).max() <= 1e-13 * np.abs(c.U_or).max()
+
+
+def test_lattice_tables_match_oracle_tables():
+    from paper_2304_04214_amd.channel import lattice_tables
+    a, b = lattice_tables(), O.tables()
+    assert np.array_equal(a["c"], b["c"]) and np.array_equal(a["opp"], b["opp"])
+    assert np.array_equal(a["refl"], b["refl"]) and np.array_equal(a["w"], b["w"])
+
+
+def test_mach_guard_is_reported():
+    c = Case(4, 6, 8, ywall="slip", xbc="inflow", wall_model=False, n_modes=4)
+    c.ch.sync()
+    c.ch._stg_tensors["u_rans"][0].fill_(0.2)
+    c.ch._stg_dirty = True
+    c.ch.stg_fill(1.0)
+    with pytest.raises(A.LbmError) as e:
+        c.ch.sync()
+    assert e.value.status == A.LBM_ERR_MACH
+    c.ch.sync()  # the error is cleared once reported
+
+
+def test_nonfinite_density_is_reported():
+    c = Case(4, 6, 8, ywall="slip", xbc="periodic", wall_model=False)
+    c.ch.sync()
+    c.ch.f[0][3, 1, 2, 5] = float("nan")
+    c.ch.step(1)
+    with pytest.raises(A.LbmError) as e:
+        c.ch.sync()
+    assert e.value.status == A.LBM_ERR_NONFINITE
+
+
+@pytest.mark.parametrize("name", ["slip-inflow-wallmodel", "periodic-smag-force"])
+def test_fp16_deviation_storage_matches_oracle(name):
+    spec = PARITY_CASES[name]
+    _say("fp16 parity", name)
+    c = Case(*spec["shape"], storage="f16dev", **spec["kw"])
+    c.ch.step(20)
+    c.ch.sync()
+    st, f_or, _, _ = c.run_oracle(20)
+    f_g, _ = c.gpu_state()
+    err = rel_linf(f_g, f_or)
+    _say("  fp16 rel Linf %.3e" % err)
+    assert err <= TOL16
+
+
+def test_bad_arguments_rejected():
+    with pytest.raises(A.LbmError) as e:
+        Channel(4, 3, 8, tau0=0.6)  # ny < 4
+    assert e.value.status == A.LBM_ERR_SHAPE
+    with pytest.raises(A.LbmError) as e:
+        Channel(4, 8, 8, tau0=0.5)
+    assert e.value.status == A.LBM_ERR_ARG
+    ch = Channel(4, 8, 8, tau0=0.6, xbc="inflow", ywall="slip")
+    with pytest.raises(A.LbmError) as e:
+        ch.step(1)  # no STG bound
+    assert e.value.status == A.LBM_ERR_STATE

@@ -56,13 +56,15 @@ def test_first_cell_yplus_matches_paper():
 
 @pytest.mark.parametrize("tau0,uhat", [(0.5004270558446486, 0.06), (0.5001393543659287, 0.055),
                                        (0.5002787087318575, 0.05), (0.52, 0.03), (0.52, 1e-5),
-                                       (0.8, 0.2), (0.5001, 1e-3)])
+                                       (0.8, 0.2), (0.5001, 1e-3), (0.52, 1e-9), (0.52, 1e-12)])
 def test_newton_solves_wall_law(tau0, uhat):
     cfg = O.make_cfg(4, 4, 4, tau0=tau0)
     nu = (tau0 - 0.5) / 3
     st, ut = O.utau(cfg, uhat)
     assert st == O.OK
     assert ut * O.uplus(cfg.y_wall * ut / nu) == pytest.approx(uhat, rel=1e-13)
+    if uhat < 1e-6:  # viscous sublayer: u_tau^2 y / nu = u_hat to leading order
+        assert ut == pytest.approx(np.sqrt(nu * uhat / cfg.y_wall), rel=1e-5)
 
 
 def test_newton_round_trip():
