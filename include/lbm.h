@@ -17,11 +17,16 @@
  *  - All work is enqueued, in order, on the HIP stream given to lbm_create()
  *    (asynchronous to the host).  A handle is not thread-safe.
  *  - Lattice: x streamwise (nx), y wall-normal (ny), z spanwise (nz, periodic).
- *    Node (x, y, z) has linear index n = (x*ny + y)*nz + z.  Populations are
- *    stored structure-of-arrays: population i of node n at element i*N + n,
- *    N = nx*ny*nz, with i the D3Q19 index in the paper's order (Sec. II.A,
+ *    Node (x, y, z) has linear index n = (x*ny + y)*nz + z in every
+ *    node-field argument ("SoA [c][N]": component c of node n at c*N + n,
+ *    N = nx*ny*nz).  i is the D3Q19 index in the paper's order (Sec. II.A,
  *    Eq. (1): lexicographic in (c_z, c_y, c_x), opposite of i is 18 - i).
- *    The stored state is the post-collision population set s_n of time n.
+ *  - Population buffers use 64-node bricks: with zc = ceil(nz/64), population
+ *    i of node (x, y, z) is element ((x*zc + z/64)*ny + y)*1216 + 64*i + z%64
+ *    (1216 = 19*64); a buffer holds 19*nx*ny*zc*64 elements (lbm_state_elems).
+ *    Elements of the padding nodes z >= nz are never read.  lbm_import_f32 /
+ *    lbm_export_f32 convert from / to SoA float [19][N].  The stored state is
+ *    the post-collision population set s_n of time n.
  */
 #ifndef LBM_H
 #define LBM_H
@@ -112,14 +117,19 @@ typedef struct {
   float* fluct;
 } lbm_stg;
 
+/* Number of elements of one population buffer for cfg (19*nx*ny*zc*64);
+   validates cfg like lbm_create (no device work). */
+lbm_status lbm_state_elems(const lbm_config* cfg, int64_t* elems);
+
 /*
- * Create a handle.  f_a, f_b: device population buffers of 19*N elements
- * (float for LBM_STORE_F32, 16-bit for LBM_STORE_F16DEV), 256-byte aligned;
- * the state lives in f_a first and moves between the two each step.
+ * Create a handle.  f_a, f_b: device population buffers of lbm_state_elems()
+ * elements (float for LBM_STORE_F32, 16-bit for LBM_STORE_F16DEV), 256-byte
+ * aligned; the state lives in f_a first and moves between the two each step.
  * hist_a, hist_b: device float buffers [5][ny][nz] for the outlet history
  * (required when xbc = LBM_X_INFLOW, else may be NULL), alternating with the
  * populations.  hip_stream: the hipStream_t all work goes on (NULL = default).
- * Limits: nx >= 1 (>= 3 with LBM_X_INFLOW), ny >= 4, nz >= 1, N < 2^31.
+ * Limits: nx >= 1 (>= 3 with LBM_X_INFLOW), ny >= 4, nz >= 1, N < 2^31,
+ * lbm_state_elems() < 2^32.
  */
 lbm_status lbm_create(const lbm_config* cfg, void* f_a, void* f_b, float* hist_a, float* hist_b,
                       void* hip_stream, lbm_handle* out);
@@ -165,9 +175,12 @@ lbm_status lbm_step(lbm_handle h, const lbm_stg* stg, int32_t nsteps);
    LBM_STORE_F32 only. */
 lbm_status lbm_stream_only(lbm_handle h);
 
-/* Current state as float populations [19][N] (f_i = w_i + h_i for
-   LBM_STORE_F16DEV) into device buffer out. */
+/* Current state as float populations, SoA [19][N] (f_i = w_i + h_i for
+   LBM_STORE_F16DEV), into device buffer out. */
 lbm_status lbm_export_f32(lbm_handle h, float* out);
+/* Overwrite the current state from float populations, SoA [19][N] (device
+   buffer in; rounded to h_i = f_i - w_i in half for LBM_STORE_F16DEV). */
+lbm_status lbm_import_f32(lbm_handle h, const float* in);
 
 /*
  * Plane statistics (Sec. IV.A: statistics over a time window).  For each x

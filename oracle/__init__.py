@@ -90,6 +90,7 @@ def lib():
             "oracle_step_nodes": (I, [P, P, D, P, P, C.c_int64, P, P, P]),
             "oracle_macro": (None, [P, P, P, P]),
             "oracle_run": (I, [P, P, D, I, P, P, P, I, P]),
+            "oracle_num_threads": (I, []),
         }
         for name, (res, args) in sig.items():
             fn = getattr(_lib, name)
@@ -298,3 +299,8 @@ def macro(cfg, f):
     u = np.zeros(3 * N)
     lib().oracle_macro(C.byref(cfg), _p(_d(f)), _p(rho), _p(u))
     return rho.reshape(cfg.nx, cfg.ny, cfg.nz), u.reshape(3, cfg.nx, cfg.ny, cfg.nz)
+
+
+def num_threads():
+    """OpenMP threads the oracle's parallel loops use."""
+    return int(lib().oracle_num_threads())

@@ -818,3 +818,14 @@ int oracle_run(const oracle_cfg* cfg, const oracle_stg* stg, double t0, int32_t 
   return st_all;
 }
 }  // extern "C"
+
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+extern "C" int oracle_num_threads(void) {
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
+}

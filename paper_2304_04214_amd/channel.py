@@ -56,7 +56,11 @@ class Channel:
             cfg.g[a] = g[a]
         self.cfg = cfg
         dt = torch.float32 if storage == "f32" else torch.float16
-        shape = (19, nx, ny, nz)
+        elems = C.c_int64()
+        A.check(A.lib().lbm_state_elems(C.byref(cfg), C.byref(elems)), "lbm_state_elems")
+        self.zc = (nz + 63) // 64
+        shape = (nx, self.zc, ny, 19, 64)  # 64-node bricks, see include/lbm.h
+        assert elems.value == nx * self.zc * ny * 19 * 64
         self.f = [torch.empty(shape, dtype=dt, device=self.device) for _ in range(2)]
         self.hist = [torch.zeros((5, ny, nz), dtype=torch.float32, device=self.device) for _ in range(2)]
         self._stg = None
@@ -176,6 +180,12 @@ class Channel:
         out = torch.empty((19, self.nx, self.ny, self.nz), dtype=torch.float32, device=self.device)
         A.check(A.lib().lbm_export_f32(self._h, _ptr(out)), "lbm_export_f32")
         return out
+
+    def load_populations(self, f):
+        """Overwrite the current state from float populations [19, nx, ny, nz] (library import)."""
+        f = _dev(f, torch.float32, self.device).reshape(19, self.N)
+        A.check(A.lib().lbm_import_f32(self._h, _ptr(f)), "lbm_import_f32")
+        self._keep_import = f
 
     def set_state(self, f_cur, hist_cur, time):
         """Restore a state (checkpoint): copies into the buffers and sets the time index."""

@@ -26,6 +26,8 @@ lbm_status check_config(const lbm_config* c) {
   if (c->xbc == LBM_X_INFLOW && c->nx < 3) return LBM_ERR_SHAPE;
   const int64_t N = (int64_t)c->nx * c->ny * c->nz;
   if (N >= (int64_t(1) << 31)) return LBM_ERR_SHAPE;
+  const int64_t zc = (c->nz + lbm::ZT - 1) / lbm::ZT;
+  if ((int64_t)c->nx * c->ny * zc * lbm::ZT * Q >= (int64_t(1) << 32)) return LBM_ERR_SHAPE;
   if (c->storage != LBM_STORE_F32 && c->storage != LBM_STORE_F16DEV) return LBM_ERR_ARG;
   if (c->ywall < LBM_Y_PERIODIC || c->ywall > LBM_Y_SLIP) return LBM_ERR_ARG;
   if (c->xbc != LBM_X_PERIODIC && c->xbc != LBM_X_INFLOW) return LBM_ERR_ARG;
@@ -130,6 +132,14 @@ const char* lbm_status_str(lbm_status s) {
     case LBM_ERR_STATE: return "call out of order";
   }
   return "unknown status";
+}
+
+lbm_status lbm_state_elems(const lbm_config* cfg, int64_t* elems) {
+  if (!elems) return LBM_ERR_ARG;
+  lbm_status st = check_config(cfg);
+  if (st != LBM_OK) return st;
+  *elems = (int64_t)Q * cfg->nx * cfg->ny * ((cfg->nz + lbm::ZT - 1) / lbm::ZT) * lbm::ZT;
+  return LBM_OK;
 }
 
 lbm_status lbm_create(const lbm_config* cfg, void* f_a, void* f_b, float* hist_a, float* hist_b, void* hip_stream,
@@ -270,6 +280,12 @@ lbm_status lbm_stream_only(lbm_handle h) {
 lbm_status lbm_export_f32(lbm_handle h, float* out) {
   if (!h || !out) return LBM_ERR_ARG;
   HIPCHK(lbm::launch_export(h, out));
+  return LBM_OK;
+}
+
+lbm_status lbm_import_f32(lbm_handle h, const float* in) {
+  if (!h || !in) return LBM_ERR_ARG;
+  HIPCHK(lbm::launch_import(h, in));
   return LBM_OK;
 }
 

@@ -1,14 +1,20 @@
 // Fused pull-stream / boundary / wall-model / MRT-Smagorinsky collision
 // kernel for the D3Q19 channel (Algorithm 1 of Xue, Yao, Davidson,
-// arXiv 2304.04214), plus the initialisation, export, stream-only and copy
-// kernels.
+// arXiv 2304.04214), plus the initialisation, import/export, stream-only and
+// copy kernels.
 //
-// Mapping: one thread per node.  A wave is 64 consecutive z nodes of one
-// (x, y) row; a block is 4 such rows (256 threads) of the same x and z-chunk.
-// x and y are wave-uniform (scalar registers), so every boundary decision is
-// a scalar branch and every population load is base(scalar) + z(vector).
-// Blocks are renumbered so each XCD walks a contiguous range of the lattice
-// (neighbouring z-chunks share the partly-used cache lines of the +-1 shifts).
+// Population layout: 64-node bricks.  The 19 populations of the 64 nodes
+// (x, y, 64 zc .. 64 zc + 63) are one contiguous block of 19 x 64 elements,
+// and bricks are ordered (x, zc, y): element (i, x, y, z) sits at
+// ((x zc_n + z/64) ny + y) 1216 + 64 i + z%64.  A wave (64 lanes) owns one
+// brick: its 19 stores are one contiguous 4864-byte (float) run, and its pulls
+// come from the 3 x 3 neighbouring (x, y) bricks plus one element of the
+// z-neighbouring bricks for the +-1 z shifts.
+//
+// Mapping: one thread per node.  A block is 4 consecutive y rows (4 waves) of
+// one (x, z-chunk).  x and y are wave-uniform (scalar registers), so every
+// boundary decision is a scalar select and each population load is
+// scalar base + per-lane column offset.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -18,12 +24,6 @@
 namespace lbm {
 namespace {
 
-__device__ __forceinline__ int xcd_remap(int b, int nb) {
-  const int q = nb >> 3, r = nb & 7;
-  const int xcd = b & 7, idx = b >> 3;
-  return (xcd < r) ? xcd * (q + 1) + idx : r * (q + 1) + (xcd - r) * q + idx;
-}
-
 __device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
 // Population storage: float, or half deviations h_i = f_i - w_i.
@@ -31,20 +31,27 @@ template <bool F16>
 struct Pop;
 template <>
 struct Pop<false> {
-  __device__ static __forceinline__ float ld(const void* base, int, int idx) {
-    return static_cast<const float*>(base)[idx];
+  __device__ static __forceinline__ float ld(const void* base, int, uint32_t e) {
+    return static_cast<const float*>(base)[e];
   }
-  __device__ static __forceinline__ void st(void* base, int, int idx, float v) {
-    static_cast<float*>(base)[idx] = v;
+  __device__ static __forceinline__ void st(void* base, int, uint32_t e, float v) {
+    __builtin_nontemporal_store(v, static_cast<float*>(base) + e);  // streamed once, not re-read
+  }
+  __device__ static __forceinline__ void st_plain(void* base, int, uint32_t e, float v) {
+    static_cast<float*>(base)[e] = v;
   }
 };
 template <>
 struct Pop<true> {
-  __device__ static __forceinline__ float ld(const void* base, int i, int idx) {
-    return (float)WD[i] + (float)static_cast<const _Float16*>(base)[idx];
+  __device__ static __forceinline__ float ld(const void* base, int i, uint32_t e) {
+    return (float)WD[i] + (float)static_cast<const _Float16*>(base)[e];
   }
-  __device__ static __forceinline__ void st(void* base, int i, int idx, float v) {
-    static_cast<_Float16*>(base)[idx] = (_Float16)(v - (float)WD[i]);
+  __device__ static __forceinline__ void st(void* base, int i, uint32_t e, float v) {
+    const _Float16 h = (_Float16)(v - (float)WD[i]);
+    __builtin_nontemporal_store(__builtin_bit_cast(unsigned short, h), static_cast<unsigned short*>(base) + e);
+  }
+  __device__ static __forceinline__ void st_plain(void* base, int i, uint32_t e, float v) {
+    static_cast<_Float16*>(base)[e] = (_Float16)(v - (float)WD[i]);
   }
 };
 
@@ -87,23 +94,51 @@ __device__ __forceinline__ Geo make_geo(const CollideArgs& a, int x, int y) {
   return g;
 }
 
-__device__ __forceinline__ int rowoff(const CollideArgs& a, int x, int y) { return (x * a.ny + y) * a.nz; }
+constexpr uint32_t BRICK = Q * ZT;  // elements per 64-node brick
+
+// Element offset contributed by (x, y) (wave-uniform) and by z (per lane).
+__device__ __forceinline__ uint32_t rowpart(const CollideArgs& a, int x, int y) {
+  return ((uint32_t)x * (uint32_t)(a.zc * a.ny) + (uint32_t)y) * BRICK;
+}
+__device__ __forceinline__ uint32_t colpart(const CollideArgs& a, int z) {
+  return (uint32_t)(z >> 6) * (uint32_t)a.ny * BRICK + (uint32_t)(z & (ZT - 1));
+}
+
+// Column offsets of z and of its periodic neighbours z - 1 and z + 1.
+struct Col {
+  uint32_t c0, cm, cp;
+};
+__device__ __forceinline__ Col make_col(const CollideArgs& a, int z) {
+  const int zm = z == 0 ? a.nz - 1 : z - 1;
+  const int zp = z == a.nz - 1 ? 0 : z + 1;
+  return Col{colpart(a, z), colpart(a, zm), colpart(a, zp)};
+}
 
 // Pull of direction i into node (g.x, g.y, z) with the wall rules
 // (Eq. (3); halfway bounce-back or specular slip at the y walls).  Sources
-// outside the x range (inlet unknowns, outlet) return `unset`.
+// outside the x range (inlet unknowns, outlet) give `unset`.  The source plane,
+// row and z are chosen by selects (scalar for plane and row) and the load is
+// always issued from a valid address, so the 19 loads of a node form one
+// straight-line batch.  Opposite and mirrored directions share w_i.
 template <bool F16>
-__device__ __forceinline__ float pull_dir(const CollideArgs& a, const Geo& g, int i, int z, int zm, int zp,
-                                          float unset) {
+__device__ __forceinline__ float pull_dir(const CollideArgs& a, const Geo& g, int i, const Col& col, float unset) {
   const int cx = CX[i], cy = CY[i], cz = CZ[i];
-  const int zs = cz == 1 ? zm : (cz == -1 ? zp : z);
-  if (cy != 0 && g.yout[cy + 1]) {
-    if (a.ywall == LBM_Y_BOUNCEBACK) return Pop<F16>::ld(a.src[opp(i)], opp(i), rowoff(a, g.x, g.y) + z);
-    if (!g.xok[cx + 1]) return unset;
-    return Pop<F16>::ld(a.src[REFLY[i]], REFLY[i], rowoff(a, g.xs[cx + 1], g.y) + zs);
+  const uint32_t cs = cz == 1 ? col.cm : (cz == -1 ? col.cp : col.c0);
+  int plane = i, xsrc = g.xs[cx + 1], ysrc = g.ys[cy + 1];
+  uint32_t csrc = cs;
+  bool ok = g.xok[cx + 1];
+  if (cy != 0) {
+    const bool out = g.yout[cy + 1];
+    const bool bb = out && a.ywall == LBM_Y_BOUNCEBACK;
+    plane = out ? (bb ? opp(i) : REFLY[i]) : i;
+    xsrc = bb ? g.x : xsrc;
+    ysrc = out ? g.y : ysrc;
+    csrc = bb ? col.c0 : cs;
+    ok = bb ? true : ok;
   }
-  if (!g.xok[cx + 1]) return unset;
-  return Pop<F16>::ld(a.src[i], i, rowoff(a, g.xs[cx + 1], g.ys[cy + 1]) + zs);
+  const uint32_t row = rowpart(a, xsrc, ysrc) + (uint32_t)plane * ZT;
+  const float v = Pop<F16>::ld(a.src, i, row + csrc);
+  return ok ? v : unset;
 }
 
 // Regularised inlet populations (Sec. III.A, Eq. (26)-(31)): Zou-He density
@@ -304,29 +339,41 @@ __device__ __forceinline__ void collide(const CollideArgs& a, float f[Q], float 
   f[9] = f9 + R9;
 }
 
+// Node of the calling thread: block = 4 consecutive y rows of one (x, z-chunk),
+// blocks ordered like the bricks (y-groups fastest, then z-chunks, then x).
+struct Node {
+  int x, y, zci, base, gy, lane, z;
+  bool owned, active;
+};
+__device__ __forceinline__ Node decode(const CollideArgs& a) {
+  Node n;
+  const int L = blockIdx.x;
+  n.gy = L % a.yg;
+  const int rest = L / a.yg;
+  n.zci = rest % a.zc;
+  n.x = rest / a.zc;
+  n.lane = threadIdx.x & (ZT - 1);
+  n.base = min(YROWS * n.gy, a.ny - YROWS);
+  n.y = n.base + uni(threadIdx.x >> 6);
+  n.owned = n.y >= YROWS * n.gy;  // rows shared with the previous group (ragged ny) are helpers only
+  const int zraw = n.zci * ZT + n.lane;
+  n.active = zraw < a.nz;
+  n.z = n.active ? zraw : a.nz - 1;  // inactive lanes compute a valid node and store nothing
+  return n;
+}
+
 template <bool F16>
 __global__ __launch_bounds__(BLOCK) void collide_kernel(CollideArgs a) {
   __shared__ float lds_u2[2][2][ZT];
-  const int L = xcd_remap(blockIdx.x, a.nblocks);
-  const int zci = L % a.zc;
-  const int rest = L / a.zc;
-  const int gy = rest % a.yg;
-  const int x = rest / a.yg;
-  const int lane = threadIdx.x & (ZT - 1);
-  const int ty = uni(threadIdx.x >> 6);
-  const int base = min(YROWS * gy, a.ny - YROWS);
-  const int y = base + ty;
-  const bool owned = y >= YROWS * gy;  // rows shared with the previous group (ragged ny) are helpers only
-  const int zraw = zci * ZT + lane;
-  const bool active = zraw < a.nz;
-  const int z = active ? zraw : a.nz - 1;
-  const int zm = z == 0 ? a.nz - 1 : z - 1;
-  const int zp = z == a.nz - 1 ? 0 : z + 1;
+  const Node nd = decode(a);
+  const int x = nd.x, y = nd.y, z = nd.z, lane = nd.lane, base = nd.base, zci = nd.zci;
+  const bool owned = nd.owned, active = nd.active;
+  const Col col = make_col(a, z);
 
   const Geo g = make_geo(a, x, y);
   float f[Q];
 #pragma unroll
-  for (int i = 0; i < Q; ++i) f[i] = pull_dir<F16>(a, g, i, z, zm, zp, 0.f);
+  for (int i = 0; i < Q; ++i) f[i] = pull_dir<F16>(a, g, i, col, 0.f);
 
   const bool inflow = a.xbc == LBM_X_INFLOW;
   if (inflow && x == a.nx - 1) {  // convective outlet for c_x < 0
@@ -334,7 +381,7 @@ __global__ __launch_bounds__(BLOCK) void collide_kernel(CollideArgs a) {
 #pragma unroll
     for (int k = 0; k < 5; ++k) {
       const int i = OUT5[k];
-      const float up = pull_dir<F16>(a, g2, i, z, zm, zp, 0.f);
+      const float up = pull_dir<F16>(a, g2, i, col, 0.f);
       const int hidx = (k * a.ny + y) * a.nz + z;
       const float v = (a.hist_in[hidx] + a.u_conv * up) * a.inv_1pu;
       f[i] = v;
@@ -391,10 +438,10 @@ __global__ __launch_bounds__(BLOCK) void collide_kernel(CollideArgs a) {
 
   if (!(rho > 0.f && rho < 1e30f)) atomicOr(a.err, ERRBIT_NONFINITE);
 
-  const int n = rowoff(a, x, y) + z;
   if (active && owned) {
+    const uint32_t row = rowpart(a, x, y);
 #pragma unroll
-    for (int i = 0; i < Q; ++i) Pop<F16>::st(a.dst[i], i, n, f[i]);
+    for (int i = 0; i < Q; ++i) Pop<F16>::st(a.dst, i, row + (uint32_t)i * ZT + col.c0, f[i]);
   }
 
   if (a.stats_on) {
@@ -427,59 +474,63 @@ __global__ __launch_bounds__(BLOCK) void collide_kernel(CollideArgs a) {
 
 // Pull with the wall rules only (debug map); unset populations are -1.
 __global__ __launch_bounds__(BLOCK) void stream_only_kernel(CollideArgs a) {
-  const int L = blockIdx.x;
-  const int zci = L % a.zc;
-  const int rest = L / a.zc;
-  const int gy = rest % a.yg;
-  const int x = rest / a.yg;
-  const int lane = threadIdx.x & (ZT - 1);
-  const int ty = uni(threadIdx.x >> 6);
-  const int base = min(YROWS * gy, a.ny - YROWS);
-  const int y = base + ty;
-  const bool owned = y >= YROWS * gy;
-  const int z = zci * ZT + lane;
-  if (z >= a.nz || !owned) return;
-  const int zm = z == 0 ? a.nz - 1 : z - 1;
-  const int zp = z == a.nz - 1 ? 0 : z + 1;
-  const Geo g = make_geo(a, x, y);
-  const int n = rowoff(a, x, y) + z;
+  const Node nd = decode(a);
+  if (!nd.active || !nd.owned) return;
+  const Col col = make_col(a, nd.z);
+  const Geo g = make_geo(a, nd.x, nd.y);
+  const uint32_t row = rowpart(a, nd.x, nd.y);
 #pragma unroll
-  for (int i = 0; i < Q; ++i) Pop<false>::st(a.dst[i], i, n, pull_dir<false>(a, g, i, z, zm, zp, -1.f));
+  for (int i = 0; i < Q; ++i) Pop<false>::st_plain(a.dst, i, row + (uint32_t)i * ZT + col.c0, pull_dir<false>(a, g, i, col, -1.f));
 }
 
-struct PtrTable {
-  void* p[Q];
-};
-
+// f_i = f_eq_i(rho, u) + eps w_i pert_i from SoA node fields [.][N], N = (x ny + y) nz + z.
 template <bool F16>
-__global__ void init_kernel(PtrTable dstp, float* hist, const float* rho, const float* u, const float* pert,
-                            float eps, int nx, int ny, int nz, int N) {
-  const int n = blockIdx.x * blockDim.x + threadIdx.x;
-  if (n >= N) return;
+__global__ __launch_bounds__(BLOCK) void init_kernel(CollideArgs a, float* hist, const float* rho, const float* u,
+                                                     const float* pert, float eps) {
+  const Node nd = decode(a);
+  if (!nd.active || !nd.owned) return;
+  const int N = a.nx * a.ny * a.nz;
+  const int n = (nd.x * a.ny + nd.y) * a.nz + nd.z;
   const float r = rho ? rho[n] : 1.f;
   const float ux = u[n], uy = u[N + n], uz = u[2 * N + n];
   const float uu15 = 1.5f * (ux * ux + uy * uy + uz * uz);
-  const int z = n % nz, y = (n / nz) % ny, x = n / (nz * ny);
+  const uint32_t e0 = rowpart(a, nd.x, nd.y) + colpart(a, nd.z);
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
     const float cu = CX[i] * ux + CY[i] * uy + CZ[i] * uz;
     float v = (float)WD[i] * r * (1.f + 3.f * cu + 4.5f * cu * cu - uu15);
     if (pert) v += eps * (float)WD[i] * pert[(size_t)i * N + n];
-    Pop<F16>::st(dstp.p[i], i, n, v);
-    if (hist && x == nx - 1) {
+    Pop<F16>::st_plain(a.dst, i, e0 + (uint32_t)i * ZT, v);
+    if (hist && nd.x == a.nx - 1) {
 #pragma unroll
       for (int k = 0; k < 5; ++k)
-        if (OUT5[k] == i) hist[(k * ny + y) * nz + z] = v;
+        if (OUT5[k] == i) hist[(k * a.ny + nd.y) * a.nz + nd.z] = v;
     }
   }
 }
 
+// State (bricks) -> float SoA [19][N].
 template <bool F16>
-__global__ void export_kernel(PtrTable srcp, float* out, int N) {
-  const int n = blockIdx.x * blockDim.x + threadIdx.x;
-  if (n >= N) return;
+__global__ __launch_bounds__(BLOCK) void export_kernel(CollideArgs a, float* out) {
+  const Node nd = decode(a);
+  if (!nd.active || !nd.owned) return;
+  const size_t N = (size_t)a.nx * a.ny * a.nz;
+  const size_t n = ((size_t)nd.x * a.ny + nd.y) * a.nz + nd.z;
+  const uint32_t e0 = rowpart(a, nd.x, nd.y) + colpart(a, nd.z);
 #pragma unroll
-  for (int i = 0; i < Q; ++i) out[(size_t)i * N + n] = Pop<F16>::ld(srcp.p[i], i, n);
+  for (int i = 0; i < Q; ++i) out[(size_t)i * N + n] = Pop<F16>::ld(a.src, i, e0 + (uint32_t)i * ZT);
+}
+
+// Float SoA [19][N] -> state (bricks), rounded to the storage type.
+template <bool F16>
+__global__ __launch_bounds__(BLOCK) void import_kernel(CollideArgs a, const float* in) {
+  const Node nd = decode(a);
+  if (!nd.active || !nd.owned) return;
+  const size_t N = (size_t)a.nx * a.ny * a.nz;
+  const size_t n = ((size_t)nd.x * a.ny + nd.y) * a.nz + nd.z;
+  const uint32_t e0 = rowpart(a, nd.x, nd.y) + colpart(a, nd.z);
+#pragma unroll
+  for (int i = 0; i < Q; ++i) Pop<F16>::st_plain(a.dst, i, e0 + (uint32_t)i * ZT, in[(size_t)i * N + n]);
 }
 
 __global__ void copy_kernel(const float4* __restrict__ src, float4* __restrict__ dst, int64_t n4) {
@@ -491,11 +542,8 @@ const double kD[Q] = {19, 2394, 252, 10, 40, 10, 40, 10, 40, 36, 72, 12, 24, 4, 
 
 void fill_args(lbm_ctx* h, CollideArgs& a, int src, int dst) {
   const lbm_config& c = h->cfg;
-  const size_t es = c.storage == LBM_STORE_F16DEV ? 2 : 4;
-  for (int i = 0; i < Q; ++i) {
-    a.src[i] = static_cast<const char*>(h->f[src]) + (size_t)i * h->N * es;
-    a.dst[i] = static_cast<char*>(h->f[dst]) + (size_t)i * h->N * es;
-  }
+  a.src = h->f[src];
+  a.dst = h->f[dst];
   a.hist_in = h->hist[src];
   a.hist_out = h->hist[dst];
   a.u_in = h->stg_bound ? h->stg.u_in : nullptr;
@@ -552,34 +600,34 @@ hipError_t launch_stream_only(lbm_ctx* h, int src, int dst) {
   return hipGetLastError();
 }
 
-// The 19 per-direction base pointers of buffer `which`.
-static PtrTable dir_pointers(lbm_ctx* h, int which) {
-  const size_t es = h->cfg.storage == LBM_STORE_F16DEV ? 2 : 4;
-  PtrTable t;
-  for (int i = 0; i < Q; ++i) t.p[i] = static_cast<char*>(h->f[which]) + (size_t)i * h->N * es;
-  return t;
-}
-
 hipError_t launch_init(lbm_ctx* h, const float* rho, const float* u, const float* pert, float eps) {
-  const PtrTable t = dir_pointers(h, h->cur);
-  const int N = (int)h->N;
-  const int nb = (N + 255) / 256;
+  CollideArgs a;
+  fill_args(h, a, h->cur, h->cur);
   float* hist = h->cfg.xbc == LBM_X_INFLOW ? h->hist[h->cur] : nullptr;
   if (h->cfg.storage == LBM_STORE_F16DEV)
-    init_kernel<true><<<nb, 256, 0, h->stream>>>(t, hist, rho, u, pert, eps, h->cfg.nx, h->cfg.ny, h->cfg.nz, N);
+    init_kernel<true><<<h->nblocks, BLOCK, 0, h->stream>>>(a, hist, rho, u, pert, eps);
   else
-    init_kernel<false><<<nb, 256, 0, h->stream>>>(t, hist, rho, u, pert, eps, h->cfg.nx, h->cfg.ny, h->cfg.nz, N);
+    init_kernel<false><<<h->nblocks, BLOCK, 0, h->stream>>>(a, hist, rho, u, pert, eps);
   return hipGetLastError();
 }
 
 hipError_t launch_export(lbm_ctx* h, float* out) {
-  const PtrTable t = dir_pointers(h, h->cur);
-  const int N = (int)h->N;
-  const int nb = (N + 255) / 256;
+  CollideArgs a;
+  fill_args(h, a, h->cur, h->cur);
   if (h->cfg.storage == LBM_STORE_F16DEV)
-    export_kernel<true><<<nb, 256, 0, h->stream>>>(t, out, N);
+    export_kernel<true><<<h->nblocks, BLOCK, 0, h->stream>>>(a, out);
   else
-    export_kernel<false><<<nb, 256, 0, h->stream>>>(t, out, N);
+    export_kernel<false><<<h->nblocks, BLOCK, 0, h->stream>>>(a, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_import(lbm_ctx* h, const float* in) {
+  CollideArgs a;
+  fill_args(h, a, h->cur, h->cur);
+  if (h->cfg.storage == LBM_STORE_F16DEV)
+    import_kernel<true><<<h->nblocks, BLOCK, 0, h->stream>>>(a, in);
+  else
+    import_kernel<false><<<h->nblocks, BLOCK, 0, h->stream>>>(a, in);
   return hipGetLastError();
 }
 

@@ -21,8 +21,8 @@ constexpr int BLOCK = ZT * YROWS;
 
 // Arguments of the fused collide-stream kernel (passed by value).
 struct CollideArgs {
-  const void* src[Q];  // per-direction base of the state s_n
-  void* dst[Q];        // per-direction base of s_{n+1}
+  const void* src;  // state s_n (64-node bricks, see collide.hip)
+  void* dst;        // state s_{n+1}
   const float* hist_in;   // [5][ny][nz]
   float* hist_out;        // [5][ny][nz]
   const float* u_in;      // [3][ny][nz]
@@ -83,6 +83,7 @@ hipError_t launch_collide(lbm_ctx* h, int src, int dst);
 hipError_t launch_stream_only(lbm_ctx* h, int src, int dst);
 hipError_t launch_init(lbm_ctx* h, const float* rho, const float* u, const float* pert, float eps);
 hipError_t launch_export(lbm_ctx* h, float* out);
+hipError_t launch_import(lbm_ctx* h, const float* in);
 hipError_t launch_copy(const void* src, void* dst, int64_t bytes, hipStream_t s);
 // stg.hip
 hipError_t launch_stg_bind(lbm_ctx* h, const lbm_stg* s);

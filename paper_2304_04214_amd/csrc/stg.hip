@@ -65,34 +65,55 @@ __global__ void stg_bind_kernel(lbm_stg s, StgTables t, int ny, int nz) {
   }
 }
 
-// One wave per inlet row y, 64 spanwise nodes per wave, 4 rows per block.
+// One block per (inlet row y, 64 spanwise nodes); its four waves each sum a
+// quarter of the modes, and the partial sums are added in a fixed order.
 __global__ __launch_bounds__(256) void stg_fill_kernel(lbm_stg s, StgTables t, int ny, int nz, double time,
                                                        int* err) {
-  __shared__ float2 rowph[4][LBM_MAX_MODES];
+  __shared__ float2 rowph[LBM_MAX_MODES];
+  __shared__ float amp[3][LBM_MAX_MODES];
+  __shared__ float part[3][3][64];
   const int lane = threadIdx.x & 63;
-  const int w = threadIdx.x >> 6;
-  const int yr = blockIdx.y * 4 + w;
-  const int y = yr < ny ? yr : ny - 1;
-  const int z = blockIdx.x * 64 + lane;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int y = blockIdx.y;
+  const int zr = blockIdx.x * 64 + lane;
+  const int z = zr < nz ? zr : nz - 1;
   const int N = s.n_modes;
   // (y, t)-dependent phase of every mode, FP64 then reduced to [0, 2 pi)
-  for (int n = lane; n < N; n += 64) {
+  for (int n = threadIdx.x; n < N; n += 256) {
     const double ph = fmod(t.ky[n] * (y + 0.5) + s.omega[n] * time + s.phi[n], TWO_PI);
     double sn, cs;
     sincos(ph, &sn, &cs);
-    rowph[w][n] = make_float2((float)cs, (float)sn);
+    rowph[n] = make_float2((float)cs, (float)sn);
+    amp[0][n] = t.amp3[n];
+    amp[1][n] = t.amp3[N + n];
+    amp[2][n] = t.amp3[2 * N + n];
   }
   __syncthreads();
-  if (yr >= ny || z >= nz) return;
   float v0 = 0.f, v1 = 0.f, v2 = 0.f;
   const float2* tz = t.trigz + z;
-  for (int n = 0; n < N; ++n) {
-    const float2 a = rowph[w][n];
+  // wave w sums the contiguous mode range [n0, n1)
+  const int n0 = (N * w) >> 2, n1 = (N * (w + 1)) >> 2;
+#pragma unroll 8
+  for (int n = n0; n < n1; ++n) {
+    const float2 a = rowph[n];
     const float2 b = tz[(int64_t)n * nz];
     const float c = a.x * b.x - a.y * b.y;  // cos(alpha + beta)
-    v0 += t.amp3[n] * c;
-    v1 += t.amp3[N + n] * c;
-    v2 += t.amp3[2 * N + n] * c;
+    v0 += amp[0][n] * c;
+    v1 += amp[1][n] * c;
+    v2 += amp[2][n] * c;
+  }
+  if (w > 0) {
+    part[w - 1][0][lane] = v0;
+    part[w - 1][1][lane] = v1;
+    part[w - 1][2][lane] = v2;
+  }
+  __syncthreads();
+  if (w != 0 || zr >= nz) return;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    v0 += part[k][0][lane];
+    v1 += part[k][1][lane];
+    v2 += part[k][2][lane];
   }
   // Eq. (23): u' = a v' with the lower-triangular Cholesky factor; Eq. (22)
   const float a11 = t.chol[y], a21 = t.chol[ny + y], a22 = t.chol[2 * ny + y];
@@ -160,7 +181,7 @@ hipError_t launch_stg_bind(lbm_ctx* h, const lbm_stg* s) {
 
 hipError_t launch_stg_fill(lbm_ctx* h, double time) {
   const int ny = h->cfg.ny, nz = h->cfg.nz;
-  dim3 grid((nz + 63) / 64, (ny + 3) / 4);
+  dim3 grid((nz + 63) / 64, ny);
   stg_fill_kernel<<<grid, 256, 0, h->stream>>>(h->stg, h->tab, ny, nz, time, h->d_err);
   return hipGetLastError();
 }

@@ -42,7 +42,7 @@ def test_stream_index_map_bit_exact(ywall, xbc, shape):
     ch = Channel(nx, ny, nz, tau0=0.6, ywall=ywall, xbc=xbc, wall_model=False)
     codes = np.arange(19 * nx * ny * nz, dtype=np.float64).reshape(19, nx, ny, nz)
     assert codes.max() < 2 ** 24
-    ch.f[0].copy_(torch.as_tensor(codes, dtype=torch.float32))
+    ch.load_populations(codes)
     ch.stream_only()
     ch.sync()
     gpu = ch.populations().cpu().numpy().astype(np.float64)
@@ -100,7 +100,7 @@ def test_c1_oracle_config_50_steps():
     e20 = rel_linf(f_g, f20)
     c.ch.step(30)
     c.ch.sync()
-    st, f50, _, _ = O.run(c.ocfg, f20, h20, 20, 30, stg=c.stg_or)
+    st, f50, _ = O.run(c.ocfg, f20, h20, 20, 30, stg=c.stg_or)
     f_g, _ = c.gpu_state()
     e50 = rel_linf(f_g, f50)
     _say("  rel Linf 20 steps %.3e, 50 steps %.3e" % (e20, e50))
@@ -165,7 +165,9 @@ def test_mach_guard_is_reported():
 def test_nonfinite_density_is_reported():
     c = Case(4, 6, 8, ywall="slip", xbc="periodic", wall_model=False)
     c.ch.sync()
-    c.ch.f[0][3, 1, 2, 5] = float("nan")
+    f = c.ch.populations()
+    f[3, 1, 2, 5] = float("nan")
+    c.ch.load_populations(f)
     c.ch.step(1)
     with pytest.raises(A.LbmError) as e:
         c.ch.sync()
