@@ -184,12 +184,15 @@ lbm_status lbm_create(const lbm_config* cfg, void* f_a, void* f_b, float* hist_a
   }
   std::vector<int> none(cfg->nx, -1);
   if (hipMemcpy(h->d_plane_of_x, none.data(), sizeof(int) * cfg->nx, hipMemcpyHostToDevice) != hipSuccess ||
-      hipMemset(h->d_err, 0, sizeof(int)) != hipSuccess) {
+      hipMemset(h->d_err, 0, sizeof(int)) != hipSuccess || lbm::build_block_lists(h, none) != hipSuccess) {
     (void)hipFree(h->d_err);
     (void)hipFree(h->d_plane_of_x);
+    if (h->d_blist_int) (void)hipFree(h->d_blist_int);
+    if (h->d_blist_bnd) (void)hipFree(h->d_blist_bnd);
     delete h;
     return LBM_ERR_HIP;
   }
+  h->plane_of_x = none;
   *out = h;
   return LBM_OK;
 }
@@ -200,6 +203,8 @@ lbm_status lbm_destroy(lbm_handle h) {
   free_tables(h);
   if (h->d_stats) (void)hipFree(h->d_stats);
   if (h->d_plane_of_x) (void)hipFree(h->d_plane_of_x);
+  if (h->d_blist_int) (void)hipFree(h->d_blist_int);
+  if (h->d_blist_bnd) (void)hipFree(h->d_blist_bnd);
   if (h->d_err) (void)hipFree(h->d_err);
   for (hipEvent_t e : h->ev) (void)hipEventDestroy(e);
   delete h;
@@ -315,10 +320,16 @@ lbm_status lbm_stats(lbm_handle h, int32_t op, const int32_t* x_planes, int32_t 
       h->n_planes = n_planes;
       h->n_samples = 0;
       h->stats_on = 1;
+      h->plane_of_x = map;
+      HIPCHK(lbm::build_block_lists(h, h->plane_of_x));
       return LBM_OK;
     }
     case LBM_STATS_DETACH:
-      h->stats_on = 0;
+      if (h->stats_on) {
+        h->stats_on = 0;
+        HIPCHK(hipStreamSynchronize(h->stream));
+        HIPCHK(lbm::build_block_lists(h, h->plane_of_x));
+      }
       return LBM_OK;
     case LBM_STATS_RESET: {
       if (!h->d_stats) return LBM_ERR_STATE;

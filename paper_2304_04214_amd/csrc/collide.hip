@@ -17,9 +17,19 @@
 // scalar base + per-lane column offset.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
+#include <vector>
 
 #include "internal.h"
+
+#ifndef LBM_EXP_F16_NT
+#define LBM_EXP_F16_NT 1
+#endif
+#ifndef LBM_EXP_F32_NT
+#define LBM_EXP_F32_NT 1
+#endif
+
 
 namespace lbm {
 namespace {
@@ -29,31 +39,70 @@ __device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlan
 // Population storage: float, or half deviations h_i = f_i - w_i.
 template <bool F16>
 struct Pop;
+// Loads take a wave-uniform element offset `row` (scalar) and a per-lane byte
+// offset `cb`, so the address is scalar base + 32-bit vector offset.
 template <>
 struct Pop<false> {
-  __device__ static __forceinline__ float ld(const void* base, int, uint32_t e) {
-    return static_cast<const float*>(base)[e];
+  static constexpr uint32_t ES = 4;
+  using Raw = float;
+  __device__ static __forceinline__ Raw raw(const char* p, uint32_t off) {
+    return *reinterpret_cast<const float*>(p + off);
   }
-  __device__ static __forceinline__ void st(void* base, int, uint32_t e, float v) {
-    __builtin_nontemporal_store(v, static_cast<float*>(base) + e);  // streamed once, not re-read
+  __device__ static __forceinline__ float cvt(int, Raw r) { return r; }
+  // p: wave-uniform byte pointer; off: per-lane byte offset (+ a constant)
+  __device__ static __forceinline__ float ldp(const char* p, int, uint32_t off) {
+    return *reinterpret_cast<const float*>(p + off);
+  }
+  __device__ static __forceinline__ void stp(char* p, int, uint32_t off, float v) {
+#if LBM_EXP_F32_NT
+    __builtin_nontemporal_store(v, reinterpret_cast<float*>(p + off));  // streamed once, not re-read
+#else
+    *reinterpret_cast<float*>(p + off) = v;
+#endif
   }
   __device__ static __forceinline__ void st_plain(void* base, int, uint32_t e, float v) {
     static_cast<float*>(base)[e] = v;
   }
+  __device__ static __forceinline__ float ld_plain(const void* base, int, uint32_t e) {
+    return static_cast<const float*>(base)[e];
+  }
 };
 template <>
 struct Pop<true> {
-  __device__ static __forceinline__ float ld(const void* base, int i, uint32_t e) {
-    return (float)WD[i] + (float)static_cast<const _Float16*>(base)[e];
+  static constexpr uint32_t ES = 2;
+  using Raw = uint32_t;  // the 16-bit pattern of h_i
+  __device__ static __forceinline__ Raw raw(const char* p, uint32_t off) {
+    return *reinterpret_cast<const unsigned short*>(p + off);
   }
-  __device__ static __forceinline__ void st(void* base, int i, uint32_t e, float v) {
-    const _Float16 h = (_Float16)(v - (float)WD[i]);
-    __builtin_nontemporal_store(__builtin_bit_cast(unsigned short, h), static_cast<unsigned short*>(base) + e);
+  __device__ static __forceinline__ float cvt(int i, Raw r) {
+    return (float)WD[i] + (float)__builtin_bit_cast(_Float16, (unsigned short)r);
+  }
+  // f = w_i + h_i
+  __device__ static __forceinline__ float ldp(const char* p, int i, uint32_t off) {
+    return (float)WD[i] + (float)*reinterpret_cast<const _Float16*>(p + off);
+  }
+  // h_i = f - w_i rounded to nearest even half
+  __device__ static __forceinline__ void stp(char* p, int i, uint32_t off, float v) {
+    const uint32_t hb = __builtin_bit_cast(unsigned short, (_Float16)(v - (float)WD[i]));
+#if LBM_EXP_F16_NT
+    __builtin_nontemporal_store((unsigned short)hb, reinterpret_cast<unsigned short*>(p + off));
+#else
+    *reinterpret_cast<unsigned short*>(p + off) = (unsigned short)hb;
+#endif
   }
   __device__ static __forceinline__ void st_plain(void* base, int i, uint32_t e, float v) {
     static_cast<_Float16*>(base)[e] = (_Float16)(v - (float)WD[i]);
   }
+  __device__ static __forceinline__ float ld_plain(const void* base, int i, uint32_t e) {
+    return (float)WD[i] + (float)static_cast<const _Float16*>(base)[e];
+  }
 };
+
+// Byte pointer to the start of the (x, y) brick row of a buffer (wave-uniform).
+template <bool F16>
+__device__ __forceinline__ const char* row_ptr(const void* base, uint32_t rowp) {
+  return static_cast<const char*>(base) + (size_t)rowp * Pop<F16>::ES;
+}
 
 // Wave-uniform source rows of one node row (x, y).
 struct Geo {
@@ -104,14 +153,18 @@ __device__ __forceinline__ uint32_t colpart(const CollideArgs& a, int z) {
   return (uint32_t)(z >> 6) * (uint32_t)a.ny * BRICK + (uint32_t)(z & (ZT - 1));
 }
 
-// Column offsets of z and of its periodic neighbours z - 1 and z + 1.
+// Column offsets of z and of its periodic neighbours z - 1 and z + 1, in
+// elements and (times the element size) in bytes.
 struct Col {
-  uint32_t c0, cm, cp;
+  uint32_t c0, b0, bm, bp;
 };
+template <bool F16>
 __device__ __forceinline__ Col make_col(const CollideArgs& a, int z) {
   const int zm = z == 0 ? a.nz - 1 : z - 1;
   const int zp = z == a.nz - 1 ? 0 : z + 1;
-  return Col{colpart(a, z), colpart(a, zm), colpart(a, zp)};
+  constexpr uint32_t es = Pop<F16>::ES;
+  const uint32_t c0 = colpart(a, z);
+  return Col{c0, c0 * es, colpart(a, zm) * es, colpart(a, zp) * es};
 }
 
 // Pull of direction i into node (g.x, g.y, z) with the wall rules
@@ -123,7 +176,7 @@ __device__ __forceinline__ Col make_col(const CollideArgs& a, int z) {
 template <bool F16>
 __device__ __forceinline__ float pull_dir(const CollideArgs& a, const Geo& g, int i, const Col& col, float unset) {
   const int cx = CX[i], cy = CY[i], cz = CZ[i];
-  const uint32_t cs = cz == 1 ? col.cm : (cz == -1 ? col.cp : col.c0);
+  const uint32_t cs = cz == 1 ? col.bm : (cz == -1 ? col.bp : col.b0);
   int plane = i, xsrc = g.xs[cx + 1], ysrc = g.ys[cy + 1];
   uint32_t csrc = cs;
   bool ok = g.xok[cx + 1];
@@ -133,12 +186,70 @@ __device__ __forceinline__ float pull_dir(const CollideArgs& a, const Geo& g, in
     plane = out ? (bb ? opp(i) : REFLY[i]) : i;
     xsrc = bb ? g.x : xsrc;
     ysrc = out ? g.y : ysrc;
-    csrc = bb ? col.c0 : cs;
+    csrc = bb ? col.b0 : cs;
     ok = bb ? true : ok;
   }
-  const uint32_t row = rowpart(a, xsrc, ysrc) + (uint32_t)plane * ZT;
-  const float v = Pop<F16>::ld(a.src, i, row + csrc);
+  const char* p = row_ptr<F16>(a.src, rowpart(a, xsrc, ysrc) + (uint32_t)plane * ZT);
+  const float v = Pop<F16>::ldp(p, i, csrc);
   return ok ? v : unset;
+}
+
+// Whether the pulled source of direction i exists (false only for sources
+// outside the x range: inlet unknowns and the outlet's c_x < 0 directions).
+__device__ __forceinline__ bool pull_ok(const CollideArgs& a, const Geo& g, int i) {
+  const int cx = CX[i], cy = CY[i];
+  if (cy != 0 && g.yout[cy + 1] && a.ywall == LBM_Y_BOUNCEBACK) return true;
+  return g.xok[cx + 1];
+}
+
+// A row whose 3 x 3 source rows all lie inside the lattice: no wall, inlet or
+// outlet rule applies and the pulls are plain shifted loads.
+__device__ __forceinline__ bool interior(const Geo& g) {
+  return g.xok[0] && g.xok[2] && !g.yout[0] && !g.yout[2];
+}
+
+// Issue the 19 pull loads of node row g (raw storage values, no conversion),
+// so that they can be in flight while another row is being collided.
+template <bool F16>
+__device__ __forceinline__ void issue_pulls(const CollideArgs& a, const Geo& g, const Col& col,
+                                            typename Pop<F16>::Raw r[Q]) {
+  if (interior(g)) {
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+      const uint32_t cs = CZ[i] == 1 ? col.bm : (CZ[i] == -1 ? col.bp : col.b0);
+      r[i] = Pop<F16>::raw(row_ptr<F16>(a.src, rowpart(a, g.xs[CX[i] + 1], g.ys[CY[i] + 1]) + (uint32_t)i * ZT), cs);
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+      const int cx = CX[i], cy = CY[i], cz = CZ[i];
+      const uint32_t cs = cz == 1 ? col.bm : (cz == -1 ? col.bp : col.b0);
+      int plane = i, xsrc = g.xs[cx + 1], ysrc = g.ys[cy + 1];
+      uint32_t csrc = cs;
+      if (cy != 0) {
+        const bool out = g.yout[cy + 1];
+        const bool bb = out && a.ywall == LBM_Y_BOUNCEBACK;
+        plane = out ? (bb ? opp(i) : REFLY[i]) : i;
+        xsrc = bb ? g.x : xsrc;
+        ysrc = out ? g.y : ysrc;
+        csrc = bb ? col.b0 : cs;
+      }
+      r[i] = Pop<F16>::raw(row_ptr<F16>(a.src, rowpart(a, xsrc, ysrc) + (uint32_t)plane * ZT), csrc);
+    }
+  }
+}
+
+// Populations from the raw loads; sources outside the x range give 0.
+template <bool F16>
+__device__ __forceinline__ void convert_pulls(const CollideArgs& a, const Geo& g, const typename Pop<F16>::Raw r[Q],
+                                              float f[Q]) {
+  if (interior(g)) {
+#pragma unroll
+    for (int i = 0; i < Q; ++i) f[i] = Pop<F16>::cvt(i, r[i]);
+  } else {
+#pragma unroll
+    for (int i = 0; i < Q; ++i) f[i] = pull_ok(a, g, i) ? Pop<F16>::cvt(i, r[i]) : 0.f;
+  }
 }
 
 // Regularised inlet populations (Sec. III.A, Eq. (26)-(31)): Zou-He density
@@ -215,18 +326,35 @@ __device__ __forceinline__ void wall_force(const CollideArgs& a, float rho, floa
 // f* = f + M^-1 delta with delta_k = -s_k (m_k - m_eq_k) + (1 - s_k/2) F_k.
 // The moment transform uses the even/odd split of the basis over the
 // opposite-direction pairs (i, 18 - i).  Returns the force-corrected velocity.
-template <bool FORCE>
-__device__ __forceinline__ void collide(const CollideArgs& a, float f[Q], float rho, float jx, float jy, float jz,
-                                        float Fx, float Fy, float Fz, float& ux, float& uy, float& uz) {
-  float s[9], d[9];
+// Sums and differences over the opposite pairs (i, 18 - i); density and
+// momentum follow from them (Eq. (10)-(11)).
+struct Pairs {
+  float s[9], d[9], A, Bx;
+};
+__device__ __forceinline__ Pairs make_pairs(const float f[Q]) {
+  Pairs p;
 #pragma unroll
   for (int k = 0; k < 9; ++k) {
-    s[k] = f[k] + f[18 - k];
-    d[k] = f[k] - f[18 - k];
+    p.s[k] = f[k] + f[18 - k];
+    p.d[k] = f[k] - f[18 - k];
   }
+  p.A = p.s[0] + p.s[1] + p.s[3] + p.s[4] + p.s[5] + p.s[7];
+  p.Bx = p.s[2] + p.s[6] + p.s[8];
+  return p;
+}
+
+__device__ __forceinline__ float rcp_fast(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ float sqrt_fast(float x) { return __builtin_amdgcn_sqrtf(x); }
+
+template <bool FORCE>
+__device__ __forceinline__ void collide(const CollideArgs& a, float f[Q], const Pairs& pr, float rho, float jx,
+                                        float jy, float jz, float Fx, float Fy, float Fz, float& ux, float& uy,
+                                        float& uz) {
+  const float* s = pr.s;
+  const float* d = pr.d;
   const float f9 = f[9];
-  const float A = s[0] + s[1] + s[3] + s[4] + s[5] + s[7];
-  const float Bx = s[2] + s[6] + s[8];
+  const float A = pr.A;
+  const float Bx = pr.Bx;
   const float T04 = s[0] + s[4], T26 = s[2] + s[6], T1357 = s[1] + s[3] + s[5] + s[7];
   const float m1 = 8.f * A - 11.f * Bx - 30.f * f9;
   const float m2 = A - 4.f * Bx + 12.f * f9;
@@ -243,7 +371,7 @@ __device__ __forceinline__ void collide(const CollideArgs& a, float f[Q], float 
   const float m18 = (d[0] + d[4]) - (d[1] + d[3]);
 
   // Eq. (11): rho u = j + F/2;  Eq. (8) equilibria (with the readings of m2, m4,6,8)
-  const float ir = 1.f / rho;
+  const float ir = rcp_fast(rho);
   const float px = FORCE ? jx + 0.5f * Fx : jx;
   const float py = FORCE ? jy + 0.5f * Fy : jy;
   const float pz = FORCE ? jz + 0.5f * Fz : jz;
@@ -268,8 +396,8 @@ __device__ __forceinline__ void collide(const CollideArgs& a, float f[Q], float 
   const float pxx = (e9 + dc2) * (1.f / 3.f);
   const float pyy = 0.5f * (dc2 - pxx + e11), pzz = 0.5f * (dc2 - pxx - e11);
   const float q2 = pxx * pxx + pyy * pyy + pzz * pzz + 2.f * (e13 * e13 + e14 * e14 + e15 * e15);
-  const float tau = 0.5f * a.tau0 + 0.5f * sqrtf(a.tau0sq + a.smag * sqrtf(q2) * ir);
-  const float sv = 1.f / tau;
+  const float tau = 0.5f * a.tau0 + 0.5f * sqrt_fast(a.tau0sq + a.smag * sqrt_fast(q2) * ir);
+  const float sv = rcp_fast(tau);
   const float hv = 1.f - 0.5f * sv;
 
   // Guo forcing moments M Fbar = (1/rho) d m_eq/du . F
@@ -362,19 +490,12 @@ __device__ __forceinline__ Node decode(const CollideArgs& a) {
   return n;
 }
 
+// Boundary rules, wall model, collision, store and statistics of one node
+// whose pulled populations are in f (Algorithm 1 for one cell).
 template <bool F16>
-__global__ __launch_bounds__(BLOCK) void collide_kernel(CollideArgs a) {
-  __shared__ float lds_u2[2][2][ZT];
-  const Node nd = decode(a);
-  const int x = nd.x, y = nd.y, z = nd.z, lane = nd.lane, base = nd.base, zci = nd.zci;
-  const bool owned = nd.owned, active = nd.active;
-  const Col col = make_col(a, z);
-
-  const Geo g = make_geo(a, x, y);
-  float f[Q];
-#pragma unroll
-  for (int i = 0; i < Q; ++i) f[i] = pull_dir<F16>(a, g, i, col, 0.f);
-
+__device__ __forceinline__ void node_update(const CollideArgs& a, int x, int y, int z, int lane, int base, int zci,
+                                            bool owned, bool active, const Col& col, float f[Q],
+                                            float (*lds_u2)[2][ZT]) {
   const bool inflow = a.xbc == LBM_X_INFLOW;
   if (inflow && x == a.nx - 1) {  // convective outlet for c_x < 0
     const Geo g2 = make_geo(a, x - 1, y);
@@ -391,12 +512,11 @@ __global__ __launch_bounds__(BLOCK) void collide_kernel(CollideArgs a) {
   if (inflow && x == 0) inlet_regularize(a, y, z, f);
 
   // density and momentum before the force (Eq. (10)-(11))
-  float rho = 0.f;
-#pragma unroll
-  for (int i = 0; i < Q; ++i) rho += f[i];
-  const float jx = (f[3] + f[7] + f[10] + f[13] + f[17]) - (f[1] + f[5] + f[8] + f[11] + f[15]);
-  const float jy = (f[4] + f[11] + f[12] + f[13] + f[18]) - (f[0] + f[5] + f[6] + f[7] + f[14]);
-  const float jz = (f[14] + f[15] + f[16] + f[17] + f[18]) - (f[0] + f[1] + f[2] + f[3] + f[4]);
+  const Pairs pr = make_pairs(f);
+  const float rho = pr.A + pr.Bx + f[9];
+  const float jx = (pr.d[3] + pr.d[7]) - (pr.d[1] + pr.d[5] + pr.d[8]);
+  const float jy = pr.d[4] - (pr.d[0] + pr.d[5] + pr.d[6] + pr.d[7]);
+  const float jz = -(pr.d[0] + pr.d[1] + pr.d[2] + pr.d[3] + pr.d[4]);
 
   float Fx = 0.f, Fy = 0.f, Fz = 0.f;
   bool force = a.has_g != 0;
@@ -432,16 +552,16 @@ __global__ __launch_bounds__(BLOCK) void collide_kernel(CollideArgs a) {
 
   float ux, uy, uz;
   if (force)
-    collide<true>(a, f, rho, jx, jy, jz, Fx, Fy, Fz, ux, uy, uz);
+    collide<true>(a, f, pr, rho, jx, jy, jz, Fx, Fy, Fz, ux, uy, uz);
   else
-    collide<false>(a, f, rho, jx, jy, jz, 0.f, 0.f, 0.f, ux, uy, uz);
+    collide<false>(a, f, pr, rho, jx, jy, jz, 0.f, 0.f, 0.f, ux, uy, uz);
 
   if (!(rho > 0.f && rho < 1e30f)) atomicOr(a.err, ERRBIT_NONFINITE);
 
   if (active && owned) {
-    const uint32_t row = rowpart(a, x, y);
+    char* p = const_cast<char*>(row_ptr<F16>(a.dst, rowpart(a, x, y)));
 #pragma unroll
-    for (int i = 0; i < Q; ++i) Pop<F16>::st(a.dst, i, row + (uint32_t)i * ZT + col.c0, f[i]);
+    for (int i = 0; i < Q; ++i) Pop<F16>::stp(p + i * ZT * Pop<F16>::ES, i, col.b0, f[i]);
   }
 
   if (a.stats_on) {
@@ -472,11 +592,89 @@ __global__ __launch_bounds__(BLOCK) void collide_kernel(CollideArgs a) {
   }
 }
 
+// The collide-stream step runs as two kernels over disjoint block sets (a
+// block = 4 consecutive y rows of one (x, z-chunk)):
+//  * interior blocks, whose 3 x 3 source rows are all inside the lattice and
+//    which carry no statistics plane: a lean kernel with no boundary code, so
+//    it keeps few registers and many waves in flight to hide HBM latency;
+//  * boundary blocks (wall row groups, inlet and outlet planes, sampled
+//    statistics planes): the general kernel with every rule of Algorithm 1.
+// Both read s_n and write disjoint nodes of s_{n+1}.  Each walks a block list
+// (x, z-chunk, y-group) in memory order.  With FP32 storage every block goes
+// to the general kernel (see build_block_lists).
+__device__ __forceinline__ void block_coords(const CollideArgs& a, int e, int& x, int& zci, int& gy) {
+  gy = e % a.yg;
+  const int r = e / a.yg;
+  zci = r % a.zc;
+  x = r / a.zc;
+}
+
+template <bool F16, bool FORCE>
+__global__ __launch_bounds__(BLOCK) void collide_interior_kernel(CollideArgs a, const int* __restrict__ blist) {
+  int x, zci, gy;
+  block_coords(a, blist[blockIdx.x], x, zci, gy);
+  const int lane = threadIdx.x & (ZT - 1);
+  const int base = min(YROWS * gy, a.ny - YROWS);
+  const int y = base + uni(threadIdx.x >> 6);
+  const bool owned = y >= YROWS * gy;
+  const int zraw = zci * ZT + lane;
+  const bool active = zraw < a.nz;
+  const int z = active ? zraw : a.nz - 1;
+  const Col col = make_col<F16>(a, z);
+  const Geo g = make_geo(a, x, y);
+  typename Pop<F16>::Raw r[Q];
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    const uint32_t cs = CZ[i] == 1 ? col.bm : (CZ[i] == -1 ? col.bp : col.b0);
+    r[i] = Pop<F16>::raw(row_ptr<F16>(a.src, rowpart(a, g.xs[CX[i] + 1], g.ys[CY[i] + 1]) + (uint32_t)i * ZT), cs);
+  }
+  float f[Q];
+#pragma unroll
+  for (int i = 0; i < Q; ++i) f[i] = Pop<F16>::cvt(i, r[i]);
+  const Pairs pr = make_pairs(f);
+  const float rho = pr.A + pr.Bx + f[9];
+  const float jx = (pr.d[3] + pr.d[7]) - (pr.d[1] + pr.d[5] + pr.d[8]);
+  const float jy = pr.d[4] - (pr.d[0] + pr.d[5] + pr.d[6] + pr.d[7]);
+  const float jz = -(pr.d[0] + pr.d[1] + pr.d[2] + pr.d[3] + pr.d[4]);
+  float ux, uy, uz;
+  if (FORCE)
+    collide<true>(a, f, pr, rho, jx, jy, jz, rho * a.g[0], rho * a.g[1], rho * a.g[2], ux, uy, uz);
+  else
+    collide<false>(a, f, pr, rho, jx, jy, jz, 0.f, 0.f, 0.f, ux, uy, uz);
+  if (!(rho > 0.f && rho < 1e30f)) atomicOr(a.err, ERRBIT_NONFINITE);
+  if (active && owned) {
+    char* p = const_cast<char*>(row_ptr<F16>(a.dst, rowpart(a, x, y)));
+#pragma unroll
+    for (int i = 0; i < Q; ++i) Pop<F16>::stp(p + i * ZT * Pop<F16>::ES, i, col.b0, f[i]);
+  }
+}
+
+template <bool F16>
+__global__ __launch_bounds__(BLOCK) void collide_boundary_kernel(CollideArgs a, const int* __restrict__ blist) {
+  __shared__ float lds_u2[2][2][ZT];
+  int x, zci, gy;
+  block_coords(a, blist[blockIdx.x], x, zci, gy);
+  const int lane = threadIdx.x & (ZT - 1);
+  const int base = min(YROWS * gy, a.ny - YROWS);
+  const int y = base + uni(threadIdx.x >> 6);
+  const bool owned = y >= YROWS * gy;  // rows shared with the previous group (ragged ny) are helpers only
+  const int zraw = zci * ZT + lane;
+  const bool active = zraw < a.nz;
+  const int z = active ? zraw : a.nz - 1;  // inactive lanes compute a valid node and store nothing
+  const Col col = make_col<F16>(a, z);
+  const Geo g = make_geo(a, x, y);
+  typename Pop<F16>::Raw r[Q];
+  issue_pulls<F16>(a, g, col, r);
+  float f[Q];
+  convert_pulls<F16>(a, g, r, f);
+  node_update<F16>(a, x, y, z, lane, base, zci, owned, active, col, f, lds_u2);
+}
+
 // Pull with the wall rules only (debug map); unset populations are -1.
 __global__ __launch_bounds__(BLOCK) void stream_only_kernel(CollideArgs a) {
   const Node nd = decode(a);
   if (!nd.active || !nd.owned) return;
-  const Col col = make_col(a, nd.z);
+  const Col col = make_col<false>(a, nd.z);
   const Geo g = make_geo(a, nd.x, nd.y);
   const uint32_t row = rowpart(a, nd.x, nd.y);
 #pragma unroll
@@ -518,7 +716,7 @@ __global__ __launch_bounds__(BLOCK) void export_kernel(CollideArgs a, float* out
   const size_t n = ((size_t)nd.x * a.ny + nd.y) * a.nz + nd.z;
   const uint32_t e0 = rowpart(a, nd.x, nd.y) + colpart(a, nd.z);
 #pragma unroll
-  for (int i = 0; i < Q; ++i) out[(size_t)i * N + n] = Pop<F16>::ld(a.src, i, e0 + (uint32_t)i * ZT);
+  for (int i = 0; i < Q; ++i) out[(size_t)i * N + n] = Pop<F16>::ld_plain(a.src, i, e0 + (uint32_t)i * ZT);
 }
 
 // Float SoA [19][N] -> state (bricks), rounded to the storage type.
@@ -586,11 +784,66 @@ void fill_args(lbm_ctx* h, CollideArgs& a, int src, int dst) {
 hipError_t launch_collide(lbm_ctx* h, int src, int dst) {
   CollideArgs a;
   fill_args(h, a, src, dst);
-  if (h->cfg.storage == LBM_STORE_F16DEV)
-    collide_kernel<true><<<h->nblocks, BLOCK, 0, h->stream>>>(a);
-  else
-    collide_kernel<false><<<h->nblocks, BLOCK, 0, h->stream>>>(a);
+  const bool f16 = h->cfg.storage == LBM_STORE_F16DEV;
+  if (h->n_bnd > 0) {
+    if (f16)
+      collide_boundary_kernel<true><<<h->n_bnd, BLOCK, 0, h->stream>>>(a, h->d_blist_bnd);
+    else
+      collide_boundary_kernel<false><<<h->n_bnd, BLOCK, 0, h->stream>>>(a, h->d_blist_bnd);
+  }
+  if (h->n_int > 0) {
+    if (f16) {
+      if (a.has_g)
+        collide_interior_kernel<true, true><<<h->n_int, BLOCK, 0, h->stream>>>(a, h->d_blist_int);
+      else
+        collide_interior_kernel<true, false><<<h->n_int, BLOCK, 0, h->stream>>>(a, h->d_blist_int);
+    } else {
+      if (a.has_g)
+        collide_interior_kernel<false, true><<<h->n_int, BLOCK, 0, h->stream>>>(a, h->d_blist_int);
+      else
+        collide_interior_kernel<false, false><<<h->n_int, BLOCK, 0, h->stream>>>(a, h->d_blist_int);
+    }
+  }
   return hipGetLastError();
+}
+
+// Split the blocks (x, z-chunk, y-group) into interior and boundary lists,
+// both in memory order (see collide_interior_kernel / collide_boundary_kernel).
+hipError_t build_block_lists(lbm_ctx* h, const std::vector<int>& plane_of_x) {
+  const lbm_config& c = h->cfg;
+  std::vector<int> in, bd;
+  in.reserve((size_t)c.nx * h->zc * h->yg);
+  // FP32 storage is HBM-bound already with the general kernel's occupancy:
+  // one launch over all blocks.  FP16 storage moves half the bytes and needs
+  // the lean interior kernel's occupancy to hide latency.
+  const bool split = c.storage == LBM_STORE_F16DEV;
+  for (int x = 0; x < c.nx; ++x) {
+    const bool xb = (c.xbc == LBM_X_INFLOW && (x == 0 || x == c.nx - 1)) || (h->stats_on && plane_of_x[x] >= 0);
+    for (int zc = 0; zc < h->zc; ++zc)
+      for (int gy = 0; gy < h->yg; ++gy) {
+        const int base = std::min(YROWS * gy, c.ny - YROWS);
+        const bool yb = c.ywall != LBM_Y_PERIODIC && (base == 0 || base + YROWS - 1 == c.ny - 1);
+        const int e = (x * h->zc + zc) * h->yg + gy;
+        ((xb || yb || !split) ? bd : in).push_back(e);
+      }
+  }
+  hipError_t err;
+  for (int k = 0; k < 2; ++k) {
+    std::vector<int>& v = k == 0 ? in : bd;
+    int** d = k == 0 ? &h->d_blist_int : &h->d_blist_bnd;
+    int* cap = k == 0 ? &h->cap_int : &h->cap_bnd;
+    if (*cap < (int)v.size() || !*d) {
+      if (*d && (err = hipFree(*d)) != hipSuccess) return err;
+      *d = nullptr;
+      if ((err = hipMalloc(d, sizeof(int) * std::max<size_t>(v.size(), 1))) != hipSuccess) return err;
+      *cap = (int)std::max<size_t>(v.size(), 1);
+    }
+    if (!v.empty() && (err = hipMemcpy(*d, v.data(), sizeof(int) * v.size(), hipMemcpyHostToDevice)) != hipSuccess)
+      return err;
+  }
+  h->n_int = (int)in.size();
+  h->n_bnd = (int)bd.size();
+  return hipSuccess;
 }
 
 hipError_t launch_stream_only(lbm_ctx* h, int src, int dst) {

@@ -63,8 +63,12 @@ struct lbm_ctx {
   int zc = 0, yg = 0, nblocks = 0;
   int* d_err = nullptr;
   int* d_plane_of_x = nullptr;
+  int* d_blist_int = nullptr;  // interior / boundary collide block lists
+  int* d_blist_bnd = nullptr;
+  int n_int = 0, n_bnd = 0, cap_int = 0, cap_bnd = 0;
   double* d_stats = nullptr;
   int n_planes = 0;
+  std::vector<int> plane_of_x;  // host copy of d_plane_of_x
   int stats_on = 0;
   int64_t n_samples = 0;
   bool stg_bound = false;
@@ -80,6 +84,7 @@ struct lbm_ctx {
 namespace lbm {
 // collide.hip
 hipError_t launch_collide(lbm_ctx* h, int src, int dst);
+hipError_t build_block_lists(lbm_ctx* h, const std::vector<int>& plane_of_x);
 hipError_t launch_stream_only(lbm_ctx* h, int src, int dst);
 hipError_t launch_init(lbm_ctx* h, const float* rho, const float* u, const float* pert, float eps);
 hipError_t launch_export(lbm_ctx* h, float* out);
