@@ -69,7 +69,7 @@ def time_channel(name, storage, steps, warmup, device):
     ch.step(steps)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    k_ms, k_n = ch.kernel_timing(0)
+    k_ms, k_n, k_nodes = ch.kernel_timing(0)
     status = "ok"
     try:
         ch.sync()
@@ -78,8 +78,8 @@ def time_channel(name, storage, steps, warmup, device):
     ms = (t1 - t0) * 1e3 / steps
     kern_ms = k_ms / max(k_n, 1)
     res = dict(workload=name, storage=storage, shape=[nx, ny, nz], nodes=N, ms_per_step=ms,
-               mlups=N / (ms * 1e-3) / 1e6, kernel_ms=kern_ms, kernel_launches=k_n,
-               kernel_gbs=BYTES_PER_NODE[storage] * N / (kern_ms * 1e-3) / 1e9, status=status)
+               mlups=N / (ms * 1e-3) / 1e6, kernel_ms=kern_ms, kernel_launches=k_n, kernel_nodes=k_nodes,
+               kernel_gbs=BYTES_PER_NODE[storage] * k_nodes / (kern_ms * 1e-3) / 1e9, status=status)
     ch.close()
     del ch
     torch.cuda.empty_cache()
@@ -103,6 +103,21 @@ def copy_bandwidth(device, nbytes=2 << 30, reps=20):
     del a, b
     torch.cuda.empty_cache()
     return 2 * nbytes / (ms * 1e-3) / 1e9
+
+
+def measured_traffic(key):
+    """HBM bytes per launch of the dominant kernel from the committed rocprofv3
+    FETCH_SIZE / WRITE_SIZE record, or None when the kernel source changed since."""
+    import hashlib
+    rec = os.path.join(ROOT, "profiles", "collide_traffic_re1000_768x64x192.json")
+    try:
+        t = json.load(open(rec))
+        src = open(os.path.join(ROOT, t["kernel_source"]), "rb").read()
+        if hashlib.sha256(src).hexdigest() != t["kernel_source_sha256"]:
+            return None
+        return t[key]["traffic_bytes"]
+    except (OSError, KeyError, ValueError):
+        return None
 
 
 def cpu_baseline(target_s=15.0):
@@ -188,8 +203,9 @@ def main():
                                "slip walls + Reichardt wall model, convective outlet, 4 FP64 statistics planes",
                    "nodes": main_r["nodes"], "status": main_r["status"]},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                     "kernel": "collide_kernel<f32>", "kernel_ms": round(main_r["kernel_ms"], 5),
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic("c2:f32"),
+                     "kernel": "collide_general_kernel<f32> (all blocks)", "kernel_ms": round(main_r["kernel_ms"], 5),
+                     "kernel_nodes": main_r["kernel_nodes"],
                      "bytes_per_node": BYTES_PER_NODE["f32"], "copy_kernel_gbs": round(copy_gbs, 1),
                      "frac_of_copy": round(achieved / copy_gbs, 4)},
         "fp16dev": {"mlups": round(r16["mlups"], 1), "ms_per_step": round(r16["ms_per_step"], 5),

@@ -163,9 +163,14 @@ lbm_status stg_inlet_fill(lbm_handle h, const lbm_stg* stg, double t);
 /*
  * Advance nsteps time steps (Algorithm 1): for each step n -> n+1 the inlet
  * plane is filled for t = n+1 (when xbc = LBM_X_INFLOW), then one fused
- * pull-stream / boundary / wall-model / MRT-Smagorinsky collision kernel runs
- * over all nodes.  stg: bound when non-NULL; required (now or earlier) with
- * LBM_X_INFLOW.  Asynchronous on the handle's stream.
+ * pull-stream / boundary / wall-model / MRT-Smagorinsky collision runs over
+ * all nodes.  With LBM_STORE_F16DEV the interior blocks run in a lean kernel on
+ * the handle's stream, concurrently with the inlet plane and a general kernel
+ * for boundary blocks on an internal stream of default priority that the
+ * handle's stream joins; with LBM_STORE_F32 one general kernel covers all
+ * blocks.
+ * stg: bound when non-NULL; required (now or earlier) with LBM_X_INFLOW.
+ * Asynchronous on the handle's stream.
  */
 lbm_status lbm_step(lbm_handle h, const lbm_stg* stg, int32_t nsteps);
 
@@ -202,10 +207,15 @@ lbm_status lbm_stats(lbm_handle h, int32_t op, const int32_t* x_planes, int32_t 
 lbm_status lbm_sync(lbm_handle h);
 const char* lbm_status_str(lbm_status s);
 
-/* When enabled, every collide-stream launch is bracketed by HIP events on
-   the handle's stream; *total_ms and *launches report the summed kernel time
-   since the last reset (reading synchronises).  enable = 2 resets. */
-lbm_status lbm_kernel_timing(lbm_handle h, int32_t enable, double* total_ms, int64_t* launches);
+/* When enabled, every launch of the dominant collide-stream kernel (with
+   LBM_STORE_F32 the single kernel over all nodes, with LBM_STORE_F16DEV the
+   interior kernel over nodes away from walls, inlet, outlet and statistics
+   planes) is bracketed by HIP events on the handle's stream; *total_ms and
+   *launches report the summed kernel time since the last reset, and
+   *nodes_per_launch the nodes one launch updates (reading synchronises).
+   enable = 2 resets. */
+lbm_status lbm_kernel_timing(lbm_handle h, int32_t enable, double* total_ms, int64_t* launches,
+                             int64_t* nodes_per_launch);
 
 /* Plain device copy kernel (bandwidth calibration): dst[0:bytes) = src[0:bytes),
    bytes a multiple of 16, both 16-byte aligned. */

@@ -68,7 +68,7 @@ def lib():
             "lbm_state_elems": [P, P],
             "lbm_stats": [P, I32, P, I32, P, P],
             "lbm_sync": [P],
-            "lbm_kernel_timing": [P, I32, P, P],
+            "lbm_kernel_timing": [P, I32, P, P, P],
             "lbm_copy_probe": [P, P, I64, P],
         }
         for name, args in sig.items():

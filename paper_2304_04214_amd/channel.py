@@ -216,10 +216,13 @@ class Channel:
 
     # ---- timing ----
     def kernel_timing(self, enable):
+        """(summed ms, launches, nodes per launch) of the timed interior collide kernel."""
         ms = C.c_double()
         n = C.c_int64()
-        A.check(A.lib().lbm_kernel_timing(self._h, int(enable), C.byref(ms), C.byref(n)), "lbm_kernel_timing")
-        return ms.value, n.value
+        nodes = C.c_int64()
+        A.check(A.lib().lbm_kernel_timing(self._h, int(enable), C.byref(ms), C.byref(n), C.byref(nodes)),
+                "lbm_kernel_timing")
+        return ms.value, n.value, nodes.value
 
 
 def copy_probe(src, dst):

@@ -83,8 +83,13 @@ void free_tables(lbm_ctx* h) {
   t = lbm::StgTables();
 }
 
-hipError_t collide_launch(lbm_ctx* h, int src, int dst) {
-  if (!h->timing) return lbm::launch_collide(h, src, dst);
+// The timed collide launch (the interior kernel with FP16 storage, the
+// single general kernel with FP32 storage), bracketed by events when enabled.
+hipError_t timed_launch(lbm_ctx* h, int src, int dst) {
+  auto launch = [&]() {
+    return h->split ? lbm::launch_interior(h, src, dst, h->stream) : lbm::launch_boundary(h, src, dst, h->stream);
+  };
+  if (!h->timing) return launch();
   const size_t need = 2 * (size_t)(h->ev_used + 1);
   while (h->ev.size() < need) {
     hipEvent_t e;
@@ -94,11 +99,32 @@ hipError_t collide_launch(lbm_ctx* h, int src, int dst) {
   }
   hipError_t r = hipEventRecord(h->ev[2 * h->ev_used], h->stream);
   if (r != hipSuccess) return r;
-  r = lbm::launch_collide(h, src, dst);
+  r = launch();
   if (r != hipSuccess) return r;
   r = hipEventRecord(h->ev[2 * h->ev_used + 1], h->stream);
   if (r != hipSuccess) return r;
   ++h->ev_used;
+  return hipSuccess;
+}
+
+void destroy_streams(lbm_ctx* h) {
+  if (h->side) (void)hipStreamDestroy(h->side);
+  if (h->ev_fork) (void)hipEventDestroy(h->ev_fork);
+  for (int k = 0; k < 2; ++k) {
+    if (h->ev_int[k]) (void)hipEventDestroy(h->ev_int[k]);
+    if (h->ev_bnd[k]) (void)hipEventDestroy(h->ev_bnd[k]);
+  }
+  h->side = nullptr;
+}
+
+hipError_t create_streams(lbm_ctx* h) {
+  hipError_t e = hipStreamCreateWithFlags(&h->side, hipStreamNonBlocking);  // default priority
+  if (e != hipSuccess) return e;
+  if ((e = hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming)) != hipSuccess) return e;
+  for (int k = 0; k < 2; ++k) {
+    if ((e = hipEventCreateWithFlags(&h->ev_int[k], hipEventDisableTiming)) != hipSuccess) return e;
+    if ((e = hipEventCreateWithFlags(&h->ev_bnd[k], hipEventDisableTiming)) != hipSuccess) return e;
+  }
   return hipSuccess;
 }
 
@@ -167,6 +193,7 @@ lbm_status lbm_create(const lbm_config* cfg, void* f_a, void* f_b, float* hist_a
   h->N = (int64_t)cfg->nx * cfg->ny * cfg->nz;
   h->zc = (cfg->nz + lbm::ZT - 1) / lbm::ZT;
   h->yg = (cfg->ny + lbm::YROWS - 1) / lbm::YROWS;
+  h->split = cfg->storage == LBM_STORE_F16DEV;
   const int64_t nb = (int64_t)cfg->nx * h->yg * h->zc;
   if (nb >= (int64_t(1) << 31)) {
     delete h;
@@ -193,6 +220,15 @@ lbm_status lbm_create(const lbm_config* cfg, void* f_a, void* f_b, float* hist_a
     return LBM_ERR_HIP;
   }
   h->plane_of_x = none;
+  if (create_streams(h) != hipSuccess) {
+    destroy_streams(h);
+    (void)hipFree(h->d_err);
+    (void)hipFree(h->d_plane_of_x);
+    (void)hipFree(h->d_blist_int);
+    (void)hipFree(h->d_blist_bnd);
+    delete h;
+    return LBM_ERR_HIP;
+  }
   *out = h;
   return LBM_OK;
 }
@@ -207,6 +243,7 @@ lbm_status lbm_destroy(lbm_handle h) {
   if (h->d_blist_bnd) (void)hipFree(h->d_blist_bnd);
   if (h->d_err) (void)hipFree(h->d_err);
   for (hipEvent_t e : h->ev) (void)hipEventDestroy(e);
+  destroy_streams(h);
   delete h;
   return LBM_OK;
 }
@@ -252,7 +289,7 @@ lbm_status stg_inlet_fill(lbm_handle h, const lbm_stg* stg, double t) {
     if (st != LBM_OK) return st;
   }
   if (!h->stg_bound) return LBM_ERR_STATE;
-  HIPCHK(lbm::launch_stg_fill(h, t));
+  HIPCHK(lbm::launch_stg_fill(h, t, h->stream));
   return LBM_OK;
 }
 
@@ -264,13 +301,38 @@ lbm_status lbm_step(lbm_handle h, const lbm_stg* stg, int32_t nsteps) {
   }
   const bool inflow = h->cfg.xbc == LBM_X_INFLOW;
   if (inflow && !h->stg_bound) return LBM_ERR_STATE;
+  if (nsteps == 0) return LBM_OK;
+  if (!h->split) {
+    for (int32_t n = 0; n < nsteps; ++n) {
+      if (inflow) HIPCHK(lbm::launch_stg_fill(h, (double)(h->time + 1), h->stream));
+      HIPCHK(timed_launch(h, h->cur, 1 - h->cur));
+      h->cur = 1 - h->cur;
+      ++h->time;
+      if (h->stats_on) ++h->n_samples;
+    }
+    return LBM_OK;
+  }
+  // Step n: the side stream fills the inlet plane and runs the boundary
+  // blocks while the caller's stream runs the interior blocks.  Both read s_n
+  // and write disjoint nodes of s_{n+1}; step n+1 on either stream waits for
+  // step n on the other (ping-pong events), and the caller's stream joins the
+  // side stream at the end.
+  HIPCHK(hipEventRecord(h->ev_fork, h->stream));
+  HIPCHK(hipStreamWaitEvent(h->side, h->ev_fork, 0));
   for (int32_t n = 0; n < nsteps; ++n) {
-    if (inflow) HIPCHK(lbm::launch_stg_fill(h, (double)(h->time + 1)));
-    HIPCHK(collide_launch(h, h->cur, 1 - h->cur));
-    h->cur = 1 - h->cur;
+    const int src = h->cur, dst = 1 - h->cur;
+    if (n > 0) HIPCHK(hipStreamWaitEvent(h->side, h->ev_int[(n - 1) & 1], 0));
+    if (inflow) HIPCHK(lbm::launch_stg_fill(h, (double)(h->time + 1), h->side));
+    HIPCHK(lbm::launch_boundary(h, src, dst, h->side));
+    HIPCHK(hipEventRecord(h->ev_bnd[n & 1], h->side));
+    if (n > 0) HIPCHK(hipStreamWaitEvent(h->stream, h->ev_bnd[(n - 1) & 1], 0));
+    HIPCHK(timed_launch(h, src, dst));
+    HIPCHK(hipEventRecord(h->ev_int[n & 1], h->stream));
+    h->cur = dst;
     ++h->time;
     if (h->stats_on) ++h->n_samples;
   }
+  HIPCHK(hipStreamWaitEvent(h->stream, h->ev_bnd[(nsteps - 1) & 1], 0));
   return LBM_OK;
 }
 
@@ -368,11 +430,13 @@ lbm_status lbm_sync(lbm_handle h) {
   return take_error(h);
 }
 
-lbm_status lbm_kernel_timing(lbm_handle h, int32_t enable, double* total_ms, int64_t* launches) {
+lbm_status lbm_kernel_timing(lbm_handle h, int32_t enable, double* total_ms, int64_t* launches,
+                              int64_t* nodes_per_launch) {
   if (!h) return LBM_ERR_ARG;
   HIPCHK(harvest_timing(h));
   if (total_ms) *total_ms = h->timed_ms;
   if (launches) *launches = h->timed_launches;
+  if (nodes_per_launch) *nodes_per_launch = h->split ? h->int_nodes : h->N;
   if (enable == 2) {
     h->timed_ms = 0.0;
     h->timed_launches = 0;

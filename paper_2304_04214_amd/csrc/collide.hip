@@ -600,8 +600,7 @@ __device__ __forceinline__ void node_update(const CollideArgs& a, int x, int y, 
 //  * boundary blocks (wall row groups, inlet and outlet planes, sampled
 //    statistics planes): the general kernel with every rule of Algorithm 1.
 // Both read s_n and write disjoint nodes of s_{n+1}.  Each walks a block list
-// (x, z-chunk, y-group) in memory order.  With FP32 storage every block goes
-// to the general kernel (see build_block_lists).
+// (x, z-chunk, y-group) in memory order.
 __device__ __forceinline__ void block_coords(const CollideArgs& a, int e, int& x, int& zci, int& gy) {
   gy = e % a.yg;
   const int r = e / a.yg;
@@ -611,8 +610,10 @@ __device__ __forceinline__ void block_coords(const CollideArgs& a, int e, int& x
 
 template <bool F16, bool FORCE>
 __global__ __launch_bounds__(BLOCK) void collide_interior_kernel(CollideArgs a, const int* __restrict__ blist) {
+  const int e = blist[blockIdx.x];
+  if (e < 0) return;  // padding of the XCD-ordered list
   int x, zci, gy;
-  block_coords(a, blist[blockIdx.x], x, zci, gy);
+  block_coords(a, e, x, zci, gy);
   const int lane = threadIdx.x & (ZT - 1);
   const int base = min(YROWS * gy, a.ny - YROWS);
   const int y = base + uni(threadIdx.x >> 6);
@@ -650,10 +651,12 @@ __global__ __launch_bounds__(BLOCK) void collide_interior_kernel(CollideArgs a, 
 }
 
 template <bool F16>
-__global__ __launch_bounds__(BLOCK) void collide_boundary_kernel(CollideArgs a, const int* __restrict__ blist) {
+__global__ __launch_bounds__(BLOCK) void collide_general_kernel(CollideArgs a, const int* __restrict__ blist) {
   __shared__ float lds_u2[2][2][ZT];
+  const int e = blist[blockIdx.x];
+  if (e < 0) return;  // padding of the XCD-ordered list (whole block: no barrier is skipped by part of it)
   int x, zci, gy;
-  block_coords(a, blist[blockIdx.x], x, zci, gy);
+  block_coords(a, e, x, zci, gy);
   const int lane = threadIdx.x & (ZT - 1);
   const int base = min(YROWS * gy, a.ny - YROWS);
   const int y = base + uni(threadIdx.x >> 6);
@@ -781,52 +784,83 @@ void fill_args(lbm_ctx* h, CollideArgs& a, int src, int dst) {
 
 }  // namespace
 
-hipError_t launch_collide(lbm_ctx* h, int src, int dst) {
+hipError_t launch_boundary(lbm_ctx* h, int src, int dst, hipStream_t stream) {
+  if (h->n_bnd == 0) return hipSuccess;
   CollideArgs a;
   fill_args(h, a, src, dst);
-  const bool f16 = h->cfg.storage == LBM_STORE_F16DEV;
-  if (h->n_bnd > 0) {
-    if (f16)
-      collide_boundary_kernel<true><<<h->n_bnd, BLOCK, 0, h->stream>>>(a, h->d_blist_bnd);
+  if (h->cfg.storage == LBM_STORE_F16DEV)
+    collide_general_kernel<true><<<h->n_bnd, BLOCK, 0, stream>>>(a, h->d_blist_bnd);
+  else
+    collide_general_kernel<false><<<h->n_bnd, BLOCK, 0, stream>>>(a, h->d_blist_bnd);
+  return hipGetLastError();
+}
+
+hipError_t launch_interior(lbm_ctx* h, int src, int dst, hipStream_t stream) {
+  if (h->n_int == 0) return hipSuccess;
+  CollideArgs a;
+  fill_args(h, a, src, dst);
+  if (h->cfg.storage == LBM_STORE_F16DEV) {
+    if (a.has_g)
+      collide_interior_kernel<true, true><<<h->n_int, BLOCK, 0, stream>>>(a, h->d_blist_int);
     else
-      collide_boundary_kernel<false><<<h->n_bnd, BLOCK, 0, h->stream>>>(a, h->d_blist_bnd);
-  }
-  if (h->n_int > 0) {
-    if (f16) {
-      if (a.has_g)
-        collide_interior_kernel<true, true><<<h->n_int, BLOCK, 0, h->stream>>>(a, h->d_blist_int);
-      else
-        collide_interior_kernel<true, false><<<h->n_int, BLOCK, 0, h->stream>>>(a, h->d_blist_int);
-    } else {
-      if (a.has_g)
-        collide_interior_kernel<false, true><<<h->n_int, BLOCK, 0, h->stream>>>(a, h->d_blist_int);
-      else
-        collide_interior_kernel<false, false><<<h->n_int, BLOCK, 0, h->stream>>>(a, h->d_blist_int);
-    }
+      collide_interior_kernel<true, false><<<h->n_int, BLOCK, 0, stream>>>(a, h->d_blist_int);
+  } else {
+    if (a.has_g)
+      collide_interior_kernel<false, true><<<h->n_int, BLOCK, 0, stream>>>(a, h->d_blist_int);
+    else
+      collide_interior_kernel<false, false><<<h->n_int, BLOCK, 0, stream>>>(a, h->d_blist_int);
   }
   return hipGetLastError();
 }
 
+// Arrange a list of blocks for dispatch.  Blocks are handed to the 8 XCDs
+// round-robin (block b runs on XCD b mod 8), and each XCD has its own L2.
+// The only cache lines two blocks share are the edge lines of the +-1 z
+// shifts between z-neighbouring bricks of one (x, y-group) column, so every
+// column is given to one XCD and its z-chunks run back to back there.
+// Columns go to XCDs in turn; queues are padded with -1 (empty block).
+std::vector<int> xcd_order(const std::vector<int>& entries, int zc) {
+  constexpr int NX = 8;
+  std::vector<std::vector<int>> q(NX);
+  const size_t ncol = entries.size() / zc;
+  for (size_t c = 0; c < ncol; ++c)
+    for (int k = 0; k < zc; ++k) q[c % NX].push_back(entries[c * zc + k]);
+  size_t len = 0;
+  for (auto& v : q) len = std::max(len, v.size());
+  std::vector<int> out(len * NX, -1);
+  for (int k = 0; k < NX; ++k)
+    for (size_t j = 0; j < q[k].size(); ++j) out[j * NX + k] = q[k][j];
+  return out;
+}
+
 // Split the blocks (x, z-chunk, y-group) into interior and boundary lists,
-// both in memory order (see collide_interior_kernel / collide_boundary_kernel).
+// each ordered by xcd_order (see collide_interior_kernel / collide_general_kernel).
 hipError_t build_block_lists(lbm_ctx* h, const std::vector<int>& plane_of_x) {
   const lbm_config& c = h->cfg;
   std::vector<int> in, bd;
   in.reserve((size_t)c.nx * h->zc * h->yg);
-  // FP32 storage is HBM-bound already with the general kernel's occupancy:
-  // one launch over all blocks.  FP16 storage moves half the bytes and needs
-  // the lean interior kernel's occupancy to hide latency.
-  const bool split = c.storage == LBM_STORE_F16DEV;
+  int64_t int_nodes = 0;
+  const bool split = h->split;
+  // columns (x, y-group) in memory order, each with its zc z-chunks
   for (int x = 0; x < c.nx; ++x) {
     const bool xb = (c.xbc == LBM_X_INFLOW && (x == 0 || x == c.nx - 1)) || (h->stats_on && plane_of_x[x] >= 0);
-    for (int zc = 0; zc < h->zc; ++zc)
-      for (int gy = 0; gy < h->yg; ++gy) {
-        const int base = std::min(YROWS * gy, c.ny - YROWS);
-        const bool yb = c.ywall != LBM_Y_PERIODIC && (base == 0 || base + YROWS - 1 == c.ny - 1);
+    for (int gy = 0; gy < h->yg; ++gy) {
+      const int base = std::min(YROWS * gy, c.ny - YROWS);
+      const bool yb = c.ywall != LBM_Y_PERIODIC && (base == 0 || base + YROWS - 1 == c.ny - 1);
+      const bool interior_block = split && !xb && !yb;
+      for (int zc = 0; zc < h->zc; ++zc) {
         const int e = (x * h->zc + zc) * h->yg + gy;
-        ((xb || yb || !split) ? bd : in).push_back(e);
+        (interior_block ? in : bd).push_back(e);
+        if (interior_block) {
+          const int owned_rows = YROWS - (YROWS * gy - base);
+          const int lanes = std::min(ZT, c.nz - ZT * zc);
+          int_nodes += (int64_t)owned_rows * lanes;
+        }
       }
+    }
   }
+  in = xcd_order(in, h->zc);
+  bd = xcd_order(bd, h->zc);
   hipError_t err;
   for (int k = 0; k < 2; ++k) {
     std::vector<int>& v = k == 0 ? in : bd;
@@ -843,6 +877,7 @@ hipError_t build_block_lists(lbm_ctx* h, const std::vector<int>& plane_of_x) {
   }
   h->n_int = (int)in.size();
   h->n_bnd = (int)bd.size();
+  h->int_nodes = int_nodes;
   return hipSuccess;
 }
 

@@ -53,7 +53,9 @@ struct StgTables {
 
 struct lbm_ctx {
   lbm_config cfg{};
-  hipStream_t stream = nullptr;
+  hipStream_t stream = nullptr;  // caller's stream: every call's work is ordered on it
+  hipStream_t side = nullptr;    // inlet plane + boundary blocks, concurrent with the interior kernel
+  hipEvent_t ev_fork = nullptr, ev_int[2] = {nullptr, nullptr}, ev_bnd[2] = {nullptr, nullptr};
   int device = 0;
   void* f[2] = {nullptr, nullptr};
   float* hist[2] = {nullptr, nullptr};
@@ -66,6 +68,11 @@ struct lbm_ctx {
   int* d_blist_int = nullptr;  // interior / boundary collide block lists
   int* d_blist_bnd = nullptr;
   int n_int = 0, n_bnd = 0, cap_int = 0, cap_bnd = 0;
+  int64_t int_nodes = 0;  // nodes updated by one interior launch
+  // FP16 storage: interior blocks in a lean kernel, boundary blocks (and the
+  // inlet plane) concurrently on the side stream.  FP32 storage is HBM-bound
+  // with the general kernel alone: one launch over all blocks.
+  bool split = false;
   double* d_stats = nullptr;
   int n_planes = 0;
   std::vector<int> plane_of_x;  // host copy of d_plane_of_x
@@ -83,7 +90,8 @@ struct lbm_ctx {
 
 namespace lbm {
 // collide.hip
-hipError_t launch_collide(lbm_ctx* h, int src, int dst);
+hipError_t launch_boundary(lbm_ctx* h, int src, int dst, hipStream_t stream);
+hipError_t launch_interior(lbm_ctx* h, int src, int dst, hipStream_t stream);
 hipError_t build_block_lists(lbm_ctx* h, const std::vector<int>& plane_of_x);
 hipError_t launch_stream_only(lbm_ctx* h, int src, int dst);
 hipError_t launch_init(lbm_ctx* h, const float* rho, const float* u, const float* pert, float eps);
@@ -92,6 +100,6 @@ hipError_t launch_import(lbm_ctx* h, const float* in);
 hipError_t launch_copy(const void* src, void* dst, int64_t bytes, hipStream_t s);
 // stg.hip
 hipError_t launch_stg_bind(lbm_ctx* h, const lbm_stg* s);
-hipError_t launch_stg_fill(lbm_ctx* h, double t);
+hipError_t launch_stg_fill(lbm_ctx* h, double t, hipStream_t stream);
 hipError_t launch_inflow_reichardt(lbm_ctx* h, double u_tau, double* u_rans);
 }  // namespace lbm

@@ -179,10 +179,10 @@ hipError_t launch_stg_bind(lbm_ctx* h, const lbm_stg* s) {
   return hipGetLastError();
 }
 
-hipError_t launch_stg_fill(lbm_ctx* h, double time) {
+hipError_t launch_stg_fill(lbm_ctx* h, double time, hipStream_t stream) {
   const int ny = h->cfg.ny, nz = h->cfg.nz;
   dim3 grid((nz + 63) / 64, ny);
-  stg_fill_kernel<<<grid, 256, 0, h->stream>>>(h->stg, h->tab, ny, nz, time, h->d_err);
+  stg_fill_kernel<<<grid, 256, 0, stream>>>(h->stg, h->tab, ny, nz, time, h->d_err);
   return hipGetLastError();
 }
 
