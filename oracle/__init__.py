@@ -9,7 +9,9 @@ Parity status per function (see the pins in ``tests/test_oracle_*.py``):
 every function below is pinned by a closed form, an identity or a printed
 value of the paper, except the whole-system step at turbulent sizes, whose
 agreement with anything but the HIP path is unpinned by the paper (it gives no
-worked example); its parts are pinned one by one.
+worked example); its parts are pinned one by one.  The adjoint step is pinned
+by the definition of an adjoint: its inner products with random directions
+equal central finite differences of the forward step (tests/test_oracle_adjoint.py).
 """
 import ctypes as C
 import os
@@ -87,6 +89,8 @@ def lib():
             "oracle_init": (I, [P, P, P, P, D, P, P]),
             "oracle_stream_only": (I, [P, P, P]),
             "oracle_step": (I, [P, P, D, P, P, P, P, P, I, P]),
+            "oracle_step_uin": (I, [P, P, P, P, P, P, P, I, P]),
+            "oracle_adjoint_step": (I, [P, P, D, P, P, P, P, P, P, I, P, P, P, P, P, P]),
             "oracle_step_nodes": (I, [P, P, D, P, P, C.c_int64, P, P, P]),
             "oracle_macro": (None, [P, P, P, P]),
             "oracle_run": (I, [P, P, D, I, P, P, P, I, P]),
@@ -271,6 +275,79 @@ def step(cfg, f, hist, t_next, stg=None, planes=None, acc=None):
                            _p(_d(f)), _p(out), _p(None if hist is None else _d(hist)), _p(hist_out),
                            _p(pl), 0 if pl is None else len(pl), _p(acc))
     return st, out, hist_out
+
+
+def step_uin(cfg, f, hist, uin, planes=None, acc=None):
+    """One step with the inlet velocity plane uin[3,ny,nz] given; returns (status, f_new, hist_new)."""
+    out = np.empty(shape(cfg))
+    hist_out = hist.copy() if hist is not None else None
+    pl = None if planes is None else np.ascontiguousarray(planes, dtype=np.int32)
+    st = lib().oracle_step_uin(C.byref(cfg), _p(None if uin is None else _d(uin)), _p(_d(f)), _p(out),
+                               _p(None if hist is None else _d(hist)), _p(hist_out),
+                               _p(pl), 0 if pl is None else len(pl), _p(acc))
+    return st, out, hist_out
+
+
+def adjoint_step(cfg, f, hist, t_next, lam_next, eta_next=None, stg=None, uin=None, planes=None, coef=None,
+                 want_amp=False):
+    """Adjoint of step(f, hist, t_next): returns dict(status, lam, eta, g_uin, g_cs, g_amp).
+
+    lam_next = dL/ds_{n+1}, eta_next = dL/dhist_{n+1}, coef[p, y, 9] = dL/d(each
+    statistics sum of this step) or None.  uin, when given, replaces the STG plane.
+    """
+    ny, nz = cfg.ny, cfg.nz
+    lam = np.zeros(shape(cfg))
+    open_ = cfg.xbc == 1
+    eta = np.zeros((5, ny, nz)) if open_ else None
+    if open_ and eta_next is None:
+        eta_next = np.zeros((5, ny, nz))
+    g_uin = np.zeros((3, ny, nz)) if open_ else None
+    g_cs = np.zeros(1)
+    g_amp = np.zeros(len(stg.amp_bin)) if (want_amp and stg is not None) else None
+    pl = None if planes is None else np.ascontiguousarray(planes, dtype=np.int32)
+    st = lib().oracle_adjoint_step(
+        C.byref(cfg), _ref(stg.c if stg is not None else None), float(t_next), _p(None if uin is None else _d(uin)),
+        _p(_d(f)), _p(None if hist is None else _d(hist)), _p(_d(lam_next)),
+        _p(None if eta_next is None else _d(eta_next)), _p(pl), 0 if pl is None else len(pl),
+        _p(None if coef is None else _d(coef)), _p(lam), _p(eta), _p(g_uin), _p(g_cs), _p(g_amp))
+    return dict(status=st, lam=lam, eta=eta, g_uin=g_uin, g_cs=float(g_cs[0]), g_amp=g_amp)
+
+
+def gradient_run(cfg, stg, f0, hist0, t0, nsteps, planes, coef, sample_from=1, want_states=False):
+    """Loss gradient over nsteps steps from (f0, hist0) at time t0 by the adjoint.
+
+    The loss depends on the statistics sums acc accumulated over the steps
+    n = sample_from..nsteps (step n produces the state at time t0 + n);
+    coef[p, y, 9] = dL/dacc.  Returns dict(g_amp, g_cs, lam0, acc): the gradient
+    with respect to the amplitude scalings s_b and C_s, dL/df0, and acc.
+    All forward states are kept in memory (small lattices only).
+    """
+    open_ = cfg.xbc == 1
+    states = [(_d(f0).copy(), None if hist0 is None else _d(hist0).copy())]
+    acc = np.zeros((len(planes), cfg.ny, 9))
+    for n in range(1, nsteps + 1):
+        f, h = states[-1]
+        st, f1, h1 = step(cfg, f, h, t0 + n, stg=stg if open_ else None, planes=planes,
+                          acc=acc if n >= sample_from else None)
+        assert st == OK, st
+        states.append((f1, h1))
+    lam = np.zeros(shape(cfg))
+    eta = np.zeros((5, cfg.ny, cfg.nz)) if open_ else None
+    g_amp = np.zeros(len(stg.amp_bin)) if (open_ and stg is not None) else None
+    g_cs = 0.0
+    for n in range(nsteps, 0, -1):
+        f, h = states[n - 1]
+        r = adjoint_step(cfg, f, h, t0 + n, lam, eta, stg=stg if open_ else None, planes=planes,
+                         coef=coef if n >= sample_from else None, want_amp=g_amp is not None)
+        assert r["status"] == OK, r["status"]
+        lam, eta = r["lam"], r["eta"]
+        g_cs += r["g_cs"]
+        if g_amp is not None:
+            g_amp += r["g_amp"]
+    out = dict(g_amp=g_amp, g_cs=g_cs, lam0=lam, acc=acc)
+    if want_states:
+        out["states"] = states
+    return out
 
 
 def run(cfg, f, hist, t0, nsteps, stg=None, planes=None, acc=None):

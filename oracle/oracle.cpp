@@ -182,6 +182,78 @@ int g_mutation = 0;
 
 inline double val(double x) { return x; }
 
+/*
+ * Forward-mode dual numbers with K derivative slots: v + sum_k d_k e_k,
+ * e_k e_l = 0.  Every template below is written for a generic real type, so
+ * evaluating it on Duals gives the exact local Jacobian of that step
+ * (used by the adjoint).
+ */
+template <int K>
+struct Dual {
+  double v;
+  double d[K];
+  Dual() : v(0.0) { std::memset(d, 0, sizeof(d)); }
+  Dual(double x) : v(x) { std::memset(d, 0, sizeof(d)); }  // NOLINT: constants promote
+  static Dual seed(double x, int k) {
+    Dual r(x);
+    r.d[k] = 1.0;
+    return r;
+  }
+};
+template <int K>
+double val(const Dual<K>& x) { return x.v; }
+template <int K>
+Dual<K> chain(const Dual<K>& a, double fa, double dfa) { /* g(a) with g = fa, g' = dfa */
+  Dual<K> r;
+  r.v = fa;
+  for (int k = 0; k < K; ++k) r.d[k] = dfa * a.d[k];
+  return r;
+}
+template <int K>
+Dual<K> operator+(const Dual<K>& a, const Dual<K>& b) {
+  Dual<K> r;
+  r.v = a.v + b.v;
+  for (int k = 0; k < K; ++k) r.d[k] = a.d[k] + b.d[k];
+  return r;
+}
+template <int K>
+Dual<K> operator-(const Dual<K>& a, const Dual<K>& b) {
+  Dual<K> r;
+  r.v = a.v - b.v;
+  for (int k = 0; k < K; ++k) r.d[k] = a.d[k] - b.d[k];
+  return r;
+}
+template <int K>
+Dual<K> operator-(const Dual<K>& a) { return chain(a, -a.v, -1.0); }
+template <int K>
+Dual<K> operator*(const Dual<K>& a, const Dual<K>& b) {
+  Dual<K> r;
+  r.v = a.v * b.v;
+  for (int k = 0; k < K; ++k) r.d[k] = a.d[k] * b.v + a.v * b.d[k];
+  return r;
+}
+template <int K>
+Dual<K> operator/(const Dual<K>& a, const Dual<K>& b) {
+  Dual<K> r;
+  r.v = a.v / b.v;
+  for (int k = 0; k < K; ++k) r.d[k] = (a.d[k] - r.v * b.d[k]) / b.v;
+  return r;
+}
+template <int K> Dual<K> operator+(const Dual<K>& a, double b) { return a + Dual<K>(b); }
+template <int K> Dual<K> operator+(double a, const Dual<K>& b) { return Dual<K>(a) + b; }
+template <int K> Dual<K> operator-(const Dual<K>& a, double b) { return a - Dual<K>(b); }
+template <int K> Dual<K> operator-(double a, const Dual<K>& b) { return Dual<K>(a) - b; }
+template <int K> Dual<K> operator*(const Dual<K>& a, double b) { return chain(a, a.v * b, b); }
+template <int K> Dual<K> operator*(double a, const Dual<K>& b) { return chain(b, a * b.v, a); }
+template <int K> Dual<K> operator/(const Dual<K>& a, double b) { return chain(a, a.v / b, 1.0 / b); }
+template <int K> Dual<K> operator/(double a, const Dual<K>& b) { return Dual<K>(a) / b; }
+template <int K> bool operator==(const Dual<K>& a, double b) { return a.v == b; }
+template <int K> Dual<K> sqrt(const Dual<K>& a) { const double r = std::sqrt(a.v); return chain(a, r, 0.5 / r); }
+template <int K> Dual<K> exp(const Dual<K>& a) { const double e = std::exp(a.v); return chain(a, e, e); }
+template <int K> Dual<K> log(const Dual<K>& a) { return chain(a, std::log(a.v), 1.0 / a.v); }
+template <int K> Dual<K> log1p(const Dual<K>& a) { return chain(a, std::log1p(a.v), 1.0 / (1.0 + a.v)); }
+template <int K> Dual<K> expm1(const Dual<K>& a) { return chain(a, std::expm1(a.v), std::exp(a.v)); }
+
 /* ---- Sec. III.A, Eq. (27): second-order equilibrium ---- */
 template <class R>
 void feq_poly(const R& rho, const R u[3], R out[19]) {
@@ -234,10 +306,10 @@ void guo_populations(const R u[3], const R F[3], R out[19]) {
 }
 
 /* ---- Sec. II.B, Eq. (13)-(15): Smagorinsky relaxation time (reading R5) ---- */
-template <class R>
-R tau_eff_of(const R& Qhalf, const R& rho, double tau0, double cs_smag) {
+template <class R, class C>
+R tau_eff_of(const R& Qhalf, const R& rho, double tau0, const C& cs_smag) {
   using std::sqrt;
-  const double csmag = cs_smag * cs_smag;
+  const C csmag = cs_smag * cs_smag;
   return 0.5 * tau0 + 0.5 * sqrt(tau0 * tau0 + 18.0 * std::sqrt(2.0) * csmag * Qhalf / rho);
 }
 
@@ -255,7 +327,8 @@ R safe_norm(const R& s2) {
  * out: post-collision populations.  u_out (optional): rho u = sum f c + F/2.
  */
 template <class R>
-void collide(const oracle_cfg& cfg, const R f[19], const R F[3], R out[19], R* tau_out, R u_out[3]) {
+void collide(const oracle_cfg& cfg, const R f[19], const R F[3], const R& cs_smag, R out[19], R* tau_out,
+             R u_out[3]) {
   using std::sqrt;
   const Tables& t = T();
   R rho = 0.0 * f[0], j[3] = {0.0 * f[0], 0.0 * f[0], 0.0 * f[0]};
@@ -286,7 +359,7 @@ void collide(const oracle_cfg& cfg, const R f[19], const R F[3], R out[19], R* t
   for (int a = 0; a < 3; ++a)
     for (int b = 0; b < 3; ++b) q2 = q2 + Pn[a][b] * Pn[a][b];
   R Qhalf = safe_norm(q2);
-  R tau = tau_eff_of(Qhalf, rho, cfg.tau0, cfg.cs_smag);
+  R tau = tau_eff_of(Qhalf, rho, cfg.tau0, cs_smag);
   if (tau_out) *tau_out = tau;
   R S[19];
   for (int k = 0; k < 19; ++k) S[k] = cfg.s[k] + 0.0 * f[0];
@@ -479,8 +552,12 @@ struct Ctx {
 
 const int OUT5[5] = {1, 5, 8, 11, 15}; /* directions with c_x < 0, outlet history order */
 
-/* Sec. II.A, Eq. (3): pull streaming with the wall rules (Sec. II.C, IV.A). */
-bool pulled(const Ctx& c, int i, int x, int y, int z, double* v) {
+/*
+ * Sec. II.A, Eq. (3): pull streaming with the wall rules (Sec. II.C, IV.A).
+ * Flat index of the post-collision value that population i of node (x, y, z)
+ * takes, or -1 when there is none (outside the x range of an open channel).
+ */
+long long pull_src(const Ctx& c, int i, int x, int y, int z) {
   const oracle_cfg& cf = *c.cfg;
   const Tables& t = T();
   int xs = x - C[i][0], ys = y - C[i][1];
@@ -490,52 +567,87 @@ bool pulled(const Ctx& c, int i, int x, int y, int z, double* v) {
     if (cf.ywall == 0) {
       ys = (ys % c.ny + c.ny) % c.ny;
     } else if (cf.ywall == 1) { /* halfway bounce-back: the population that left towards the wall */
-      *v = c.f[c.at(t.opp[i], x, y, z)];
-      return true;
+      return (long long)c.at(t.opp[i], x, y, z);
     } else { /* specular reflection at the halfway wall */
-      if (xs < 0 || xs >= c.nx) return false;
-      *v = c.f[c.at(t.refl_y[i], xs, y, zs)];
-      return true;
+      if (xs < 0 || xs >= c.nx) return -1;
+      return (long long)c.at(t.refl_y[i], xs, y, zs);
     }
   }
-  if (xs < 0 || xs >= c.nx) return false;
-  *v = c.f[c.at(i, xs, ys, zs)];
+  if (xs < 0 || xs >= c.nx) return -1;
+  return (long long)c.at(i, xs, ys, zs);
+}
+
+bool pulled(const Ctx& c, int i, int x, int y, int z, double* v) {
+  const long long k = pull_src(c, i, x, y, z);
+  if (k < 0) return false;
+  *v = c.f[k];
   return true;
 }
 
-/* Post-streaming, post-boundary populations of one node (Algorithm 1 inlet branch). */
-void post_boundary(const Ctx& c, int x, int y, int z, double fo[19], double hist_new[5], bool* is_outlet) {
+/*
+ * Inputs of one node's boundary rules, gathered from the state: the pulled
+ * populations, and at the outlet the history plane and the pulled values of
+ * the node upstream; at the inlet the prescribed velocity.
+ */
+struct NodeIn {
+  double pv[19];
+  double hist[5], up[5], uin[3];
+  bool outlet, inlet;
+};
+
+void gather_inputs(const Ctx& c, int x, int y, int z, NodeIn* in) {
   const oracle_cfg& cf = *c.cfg;
   for (int i = 0; i < 19; ++i) {
     double v = 0.0;
-    fo[i] = pulled(c, i, x, y, z, &v) ? v : 0.0;
+    in->pv[i] = pulled(c, i, x, y, z, &v) ? v : 0.0;
   }
-  *is_outlet = false;
-  if (cf.xbc == 1 && x == c.nx - 1) { /* convective outlet (R13) */
-    *is_outlet = true;
+  in->outlet = (cf.xbc == 1 && x == c.nx - 1);
+  in->inlet = (cf.xbc == 1 && x == 0);
+  for (int k = 0; k < 5; ++k) in->hist[k] = in->up[k] = 0.0;
+  for (int a = 0; a < 3; ++a) in->uin[a] = 0.0;
+  if (in->outlet)
+    for (int k = 0; k < 5; ++k) {
+      double up = 0.0;
+      pulled(c, OUT5[k], x - 1, y, z, &up);
+      in->up[k] = up;
+      in->hist[k] = c.hist[((size_t)k * c.ny + y) * c.nz + z];
+    }
+  if (in->inlet)
+    for (int a = 0; a < 3; ++a) in->uin[a] = c.uin[((size_t)a * c.ny + y) * c.nz + z];
+}
+
+/* Post-streaming, post-boundary populations of one node (Algorithm 1 inlet branch). */
+template <class R>
+void boundary_rules(const oracle_cfg& cf, bool outlet, bool inlet, const R pv[19], const R hist[5], const R up[5],
+                    const R uin[3], R fo[19], R hist_new[5]) {
+  for (int i = 0; i < 19; ++i) fo[i] = pv[i];
+  if (outlet) { /* convective outlet (R13) */
     for (int k = 0; k < 5; ++k) {
       const int i = OUT5[k];
-      double up = 0.0;
-      pulled(c, i, x - 1, y, z, &up);
-      const double prev = c.hist[((size_t)k * c.ny + y) * c.nz + z];
-      fo[i] = (prev + cf.u_conv * up) / (1.0 + cf.u_conv);
+      fo[i] = (hist[k] + cf.u_conv * up[k]) / (1.0 + cf.u_conv);
       hist_new[k] = fo[i];
     }
   }
-  if (cf.xbc == 1 && x == 0) { /* STG inlet, Algorithm 1 steps 6-7 */
-    double u[3];
-    for (int a = 0; a < 3; ++a) u[a] = c.uin[((size_t)a * c.ny + y) * c.nz + z];
-    double out[19];
-    inlet_regularize(fo, u, out, (double*)nullptr);
+  if (inlet) { /* STG inlet, Algorithm 1 steps 6-7 */
+    R out[19];
+    inlet_regularize(fo, uin, out, (R*)nullptr);
     for (int i = 0; i < 19; ++i) fo[i] = out[i];
   }
 }
 
-void pre_force_velocity(const double f[19], double* rho, double u[3]) {
-  double r = 0, j[3] = {0, 0, 0};
+void post_boundary(const Ctx& c, int x, int y, int z, double fo[19], double hist_new[5], bool* is_outlet) {
+  NodeIn in;
+  gather_inputs(c, x, y, z, &in);
+  boundary_rules(*c.cfg, in.outlet, in.inlet, in.pv, in.hist, in.up, in.uin, fo, hist_new);
+  *is_outlet = in.outlet;
+}
+
+template <class R>
+void pre_force_velocity(const R f[19], R* rho, R u[3]) {
+  R r = 0.0 * f[0], j[3] = {0.0 * f[0], 0.0 * f[0], 0.0 * f[0]};
   for (int i = 0; i < 19; ++i) {
-    r += f[i];
-    for (int a = 0; a < 3; ++a) j[a] += f[i] * C[i][a];
+    r = r + f[i];
+    for (int a = 0; a < 3; ++a) j[a] = j[a] + f[i] * C[i][a];
   }
   *rho = r;
   for (int a = 0; a < 3; ++a) u[a] = j[a] / r;
@@ -545,29 +657,50 @@ bool is_wall_cell(const oracle_cfg& cf, int y) {
   return cf.wall_model == 1 && cf.ywall != 0 && (y == 0 || y == cf.ny - 1);
 }
 
+/*
+ * Algorithm 1 steps 8-14 for one node from its post-boundary populations f
+ * (and, in a first off-wall cell, those of the next row, f2): wall force,
+ * F = rho g + F_w, collision.  out: post-collision populations; u_stat: the
+ * force-corrected velocity.  Returns the wall solve's status.
+ */
+template <class R>
+int node_core(const oracle_cfg& cf, int y, const R f[19], const R f2[19], const R& cs_smag, R out[19],
+              R u_stat[3]) {
+  R rho, uw[3];
+  pre_force_velocity(f, &rho, uw);
+  R F[3] = {rho * cf.g[0], rho * cf.g[1], rho * cf.g[2]}; /* R9 */
+  int st = OR_OK;
+  if (is_wall_cell(cf, y)) { /* Algorithm 1 steps 9-14 */
+    const int top = (y == cf.ny - 1);
+    R rho2, u2[3];
+    pre_force_velocity(f2, &rho2, u2);
+    R Fw[3];
+    st = wall_force(cf, rho, uw, u2, top, Fw, (R*)nullptr);
+    for (int a = 0; a < 3; ++a) F[a] = F[a] + Fw[a];
+  }
+  R tau;
+  collide(cf, f, F, cs_smag, out, &tau, u_stat);
+  return st;
+}
+
+int wall_neighbour_row(const oracle_cfg& cf, int y) { return (y == cf.ny - 1) ? y - 1 : y + 1; }
+
 /* One node of Algorithm 1: boundaries, wall branch, stream-collide.  Returns status. */
 int node_update(const Ctx& c, int x, int y, int z, double out[19], double hist_new[5], bool* is_outlet,
                 double u_stat[3]) {
   const oracle_cfg& cf = *c.cfg;
-  double f[19];
+  double f[19], f2[19];
   post_boundary(c, x, y, z, f, hist_new, is_outlet);
-  double rho, uw[3];
-  pre_force_velocity(f, &rho, uw);
-  double F[3] = {rho * cf.g[0], rho * cf.g[1], rho * cf.g[2]}; /* R9 */
-  int st = OR_OK;
-  if (is_wall_cell(cf, y)) { /* Algorithm 1 steps 9-14 */
-    const int top = (y == cf.ny - 1);
-    const int y2 = top ? y - 1 : y + 1;
-    double f2[19], h2[5], rho2, u2[3];
+  if (is_wall_cell(cf, y)) {
+    double h2[5];
     bool o2;
-    post_boundary(c, x, y2, z, f2, h2, &o2);
-    pre_force_velocity(f2, &rho2, u2);
-    double Fw[3];
-    st = wall_force(cf, rho, uw, u2, top, Fw, (double*)nullptr);
-    for (int a = 0; a < 3; ++a) F[a] += Fw[a];
+    post_boundary(c, x, wall_neighbour_row(cf, y), z, f2, h2, &o2);
+  } else {
+    for (int i = 0; i < 19; ++i) f2[i] = 0.0;
   }
-  double tau;
-  collide(cf, f, F, out, &tau, u_stat);
+  int st = node_core(cf, y, f, f2, cf.cs_smag, out, u_stat);
+  double rho = 0.0;
+  for (int i = 0; i < 19; ++i) rho += f[i];
   if (!(rho > 0.0) || !std::isfinite(rho)) st = OR_ERR_NONFINITE;
   for (int i = 0; i < 19; ++i)
     if (!std::isfinite(out[i])) st = OR_ERR_NONFINITE;
@@ -611,7 +744,7 @@ void oracle_guo(const double* u, const double* F, double* out) { guo_populations
 
 void oracle_collide_node(const oracle_cfg* cfg, const double* f, const double* F, double* out, double* tau_eff,
                          double* u) {
-  collide(*cfg, f, F, out, tau_eff, u);
+  collide(*cfg, f, F, cfg->cs_smag, out, tau_eff, u);
 }
 
 double oracle_tau_eff(double Qhalf, double rho, double tau0, double cs_smag) {
@@ -694,24 +827,16 @@ int oracle_stream_only(const oracle_cfg* cfg, const double* fin, double* fout) {
 }
 
 /*
- * One full step s_n -> s_{n+1} (Algorithm 1).  t_next is the STG time of the
- * new state.  hist_in/hist_out: outlet history (may not alias).  Statistics:
- * for each x in planes[], acc[p][y][0..8] += sum over z of
- * (u, v, w, uu, vv, ww, uv, uw, vw) with the force-corrected velocity.
+ * One full step s_n -> s_{n+1} (Algorithm 1) with the inlet velocity plane
+ * given (uin [3][ny][nz], used when xbc = 1).  hist_in/hist_out: outlet
+ * history (may not alias).  Statistics: for each x in planes[],
+ * acc[p][y][0..8] += sum over z of (u, v, w, uu, vv, ww, uv, uw, vw) with the
+ * force-corrected velocity.
  */
-int oracle_step(const oracle_cfg* cfg, const oracle_stg* stg, double t_next, const double* fin, double* fout,
-                const double* hist_in, double* hist_out, const int32_t* planes, int32_t n_planes, double* acc) {
-  if (!cfg_ok(cfg) || !fin || !fout) return OR_ERR_ARG;
-  if (cfg->xbc == 1 && (!stg || !hist_in || !hist_out)) return OR_ERR_ARG;
+int step_core(const oracle_cfg* cfg, const double* uin, const double* fin, double* fout, const double* hist_in,
+              double* hist_out, const int32_t* planes, int32_t n_planes, double* acc) {
   const int nx = cfg->nx, ny = cfg->ny, nz = cfg->nz;
-  std::vector<double> uin;
-  int st_all = OR_OK;
-  if (cfg->xbc == 1) {
-    uin.resize((size_t)3 * ny * nz);
-    int st = stg_plane(*cfg, *stg, t_next, uin.data(), nullptr);
-    if (st != OR_OK) st_all = st;
-  }
-  Ctx c{cfg, fin, hist_in, uin.empty() ? nullptr : uin.data(), (size_t)nx * ny * nz, nx, ny, nz};
+  Ctx c{cfg, fin, hist_in, uin, (size_t)nx * ny * nz, nx, ny, nz};
   std::vector<int> plane_of(nx, -1);
   for (int p = 0; p < n_planes; ++p)
     if (planes[p] >= 0 && planes[p] < nx) plane_of[planes[p]] = p;
@@ -746,6 +871,162 @@ int oracle_step(const oracle_cfg* cfg, const oracle_stg* stg, double t_next, con
         st_err = st_local;
       }
     }
+  return st_err;
+}
+
+int oracle_step(const oracle_cfg* cfg, const oracle_stg* stg, double t_next, const double* fin, double* fout,
+                const double* hist_in, double* hist_out, const int32_t* planes, int32_t n_planes, double* acc) {
+  if (!cfg_ok(cfg) || !fin || !fout) return OR_ERR_ARG;
+  if (cfg->xbc == 1 && (!stg || !hist_in || !hist_out)) return OR_ERR_ARG;
+  std::vector<double> uin;
+  int st_all = OR_OK;
+  if (cfg->xbc == 1) {
+    uin.resize((size_t)3 * cfg->ny * cfg->nz);
+    st_all = stg_plane(*cfg, *stg, t_next, uin.data(), nullptr);
+  }
+  int st = step_core(cfg, uin.empty() ? nullptr : uin.data(), fin, fout, hist_in, hist_out, planes, n_planes, acc);
+  return st != OR_OK ? st : st_all;
+}
+
+/* The same step with the inlet velocity plane given instead of generated. */
+int oracle_step_uin(const oracle_cfg* cfg, const double* uin, const double* fin, double* fout,
+                    const double* hist_in, double* hist_out, const int32_t* planes, int32_t n_planes, double* acc) {
+  if (!cfg_ok(cfg) || !fin || !fout) return OR_ERR_ARG;
+  if (cfg->xbc == 1 && (!uin || !hist_in || !hist_out)) return OR_ERR_ARG;
+  return step_core(cfg, uin, fin, fout, hist_in, hist_out, planes, n_planes, acc);
+}
+
+/*
+ * Discrete adjoint of one step s_n -> s_{n+1} (the transpose of the step's
+ * linearisation).  Given the loss sensitivities to the step's outputs --
+ * lam_next = dL/ds_{n+1} [19][N], eta_next = dL/dhist_{n+1} [5][ny][nz] and
+ * the statistics weights coef [n_planes][ny][9] (dL/d of each accumulated sum
+ * of this step, NULL when the step is not sampled) -- it returns
+ * lam_prev = dL/ds_n, eta_prev = dL/dhist_n, g_uin = dL/du_in(t_next)
+ * [3][ny][nz] (overwritten) and adds dL/dC_s to *g_cs and, with STG inputs,
+ * dL/ds_b = sum over the bin's rows of g_uin . (a v') to g_amp[b].
+ *
+ * Method: every node's update is split into its boundary rules (pulled
+ * populations, outlet history and upstream values, inlet velocity -> the
+ * post-boundary populations) and its core (post-boundary populations of the
+ * node and, in a first off-wall cell, of the next row, and C_s -> the new
+ * populations and velocity).  The local Jacobians of both come from dual
+ * numbers; pass 1 pulls the output sensitivities back to the post-boundary
+ * populations of every node, pass 2 pulls those back through the boundary
+ * rules and adds them to the source of every pulled value.
+ */
+int oracle_adjoint_step(const oracle_cfg* cfg, const oracle_stg* stg, double t_next, const double* uin_given,
+                        const double* s_n, const double* hist_n, const double* lam_next, const double* eta_next,
+                        const int32_t* planes, int32_t n_planes, const double* coef, double* lam_prev,
+                        double* eta_prev, double* g_uin, double* g_cs, double* g_amp) {
+  if (!cfg_ok(cfg) || !s_n || !lam_next || !lam_prev) return OR_ERR_ARG;
+  const int nx = cfg->nx, ny = cfg->ny, nz = cfg->nz;
+  const bool open = cfg->xbc == 1;
+  if (open && (!hist_n || !eta_next || !eta_prev || (!uin_given && !stg))) return OR_ERR_ARG;
+  if (g_amp && !stg) return OR_ERR_ARG;
+  const size_t N = (size_t)nx * ny * nz, P = (size_t)ny * nz;
+  std::vector<double> uin, fluct;
+  int st_all = OR_OK;
+  if (open) {
+    uin.resize(3 * P);
+    if (stg) {
+      fluct.resize(3 * P);
+      st_all = stg_plane(*cfg, *stg, t_next, uin.data(), fluct.data());
+    }
+    if (uin_given) std::memcpy(uin.data(), uin_given, 3 * P * sizeof(double));
+  }
+  Ctx c{cfg, s_n, hist_n, open ? uin.data() : nullptr, N, nx, ny, nz};
+  std::vector<int> plane_of(nx, -1);
+  for (int p = 0; p < n_planes; ++p)
+    if (planes && planes[p] >= 0 && planes[p] < nx) plane_of[planes[p]] = p;
+
+  /* pass 1: dL/d(post-boundary populations) of every node, and dL/dC_s */
+  typedef Dual<39> D1;
+  std::vector<double> G(19 * N, 0.0), gcs_x(nx, 0.0);
+  int st_err = OR_OK;
+#pragma omp parallel for schedule(static)
+  for (int x = 0; x < nx; ++x) {
+    for (int y = 0; y < ny; ++y)
+      for (int z = 0; z < nz; ++z) {
+        double fo[19], f2[19], hn[5];
+        bool is_out;
+        post_boundary(c, x, y, z, fo, hn, &is_out);
+        const bool wall = is_wall_cell(*cfg, y);
+        const int y2 = wall ? wall_neighbour_row(*cfg, y) : y;
+        if (wall) {
+          double h2[5];
+          bool o2;
+          post_boundary(c, x, y2, z, f2, h2, &o2);
+        }
+        D1 fd[19], f2d[19], out[19], u[3];
+        for (int i = 0; i < 19; ++i) {
+          fd[i] = D1::seed(fo[i], i);
+          f2d[i] = wall ? D1::seed(f2[i], 19 + i) : D1(0.0);
+        }
+        const D1 cs = D1::seed(cfg->cs_smag, 38);
+        int st = node_core(*cfg, y, fd, f2d, cs, out, u);
+        if (st != OR_OK) {
+#pragma omp critical
+          st_err = st;
+        }
+        D1 J(0.0);
+        for (int i = 0; i < 19; ++i) J = J + lam_next[c.at(i, x, y, z)] * out[i];
+        if (coef && plane_of[x] >= 0) {
+          const double* A = coef + ((size_t)plane_of[x] * ny + y) * 9;
+          const D1 prod[9] = {u[0], u[1], u[2], u[0] * u[0], u[1] * u[1], u[2] * u[2],
+                              u[0] * u[1], u[0] * u[2], u[1] * u[2]};
+          for (int k = 0; k < 9; ++k) J = J + A[k] * prod[k];
+        }
+        for (int i = 0; i < 19; ++i) G[c.at(i, x, y, z)] += J.d[i];
+        if (wall && g_mutation != 8)
+          for (int i = 0; i < 19; ++i) G[c.at(i, x, y2, z)] += J.d[19 + i];
+        gcs_x[x] += J.d[38];
+        if (is_out && g_mutation != 9)
+          for (int k = 0; k < 5; ++k) G[c.at(OUT5[k], x, y, z)] += eta_next[(size_t)k * P + (size_t)y * nz + z];
+      }
+  }
+  if (g_cs)
+    for (int x = 0; x < nx; ++x) *g_cs += gcs_x[x];
+
+  /* pass 2: through the boundary rules to the pulled sources, history and inlet velocity */
+  typedef Dual<32> D2;
+  std::memset(lam_prev, 0, 19 * N * sizeof(double));
+  if (open) std::memset(eta_prev, 0, 5 * P * sizeof(double));
+  std::vector<double> gu(open ? 3 * P : 0, 0.0);
+  for (int x = 0; x < nx; ++x)
+    for (int y = 0; y < ny; ++y)
+      for (int z = 0; z < nz; ++z) {
+        NodeIn in;
+        gather_inputs(c, x, y, z, &in);
+        D2 pv[19], hist[5], up[5], ui[3], fo[19], hn[5];
+        for (int i = 0; i < 19; ++i) pv[i] = D2::seed(in.pv[i], i);
+        for (int k = 0; k < 5; ++k) {
+          hist[k] = D2::seed(in.hist[k], 19 + k);
+          up[k] = D2::seed(in.up[k], 24 + k);
+        }
+        for (int a = 0; a < 3; ++a) ui[a] = D2::seed(in.uin[a], 29 + a);
+        boundary_rules(*cfg, in.outlet, in.inlet, pv, hist, up, ui, fo, hn);
+        D2 J(0.0);
+        for (int i = 0; i < 19; ++i) J = J + G[c.at(i, x, y, z)] * fo[i];
+        for (int i = 0; i < 19; ++i) {
+          const long long k = pull_src(c, i, x, y, z);
+          if (k >= 0) lam_prev[k] += J.d[i];
+        }
+        if (in.outlet)
+          for (int k = 0; k < 5; ++k) {
+            eta_prev[(size_t)k * P + (size_t)y * nz + z] += J.d[19 + k];
+            const long long s = pull_src(c, OUT5[k], x - 1, y, z);
+            if (s >= 0 && g_mutation != 10) lam_prev[s] += J.d[24 + k];
+          }
+        if (in.inlet)
+          for (int a = 0; a < 3; ++a) gu[(size_t)a * P + (size_t)y * nz + z] += J.d[29 + a];
+      }
+  if (open && g_uin) std::memcpy(g_uin, gu.data(), 3 * P * sizeof(double));
+  if (open && g_amp && !fluct.empty())
+    for (int y = 0; y < ny; ++y)
+      for (int z = 0; z < nz; ++z)
+        for (int a = 0; a < 3; ++a)
+          g_amp[stg->bin_of_y[y]] += gu[(size_t)a * P + (size_t)y * nz + z] * fluct[(size_t)a * P + (size_t)y * nz + z];
   return st_err != OR_OK ? st_err : st_all;
 }
 
