@@ -203,6 +203,51 @@ lbm_status lbm_import_f32(lbm_handle h, const float* in);
 lbm_status lbm_stats(lbm_handle h, int32_t op, const int32_t* x_planes, int32_t n_planes, double* host_out,
                      int64_t* n_samples);
 
+/* Set the Smagorinsky constant C_s (C_smag = C_s^2, Sec. II.B, Eq. (13)-(15))
+   used by later steps and adjoint steps; cs_smag >= 0. */
+lbm_status lbm_set_cs_smag(lbm_handle h, double cs_smag);
+
+/*
+ * Discrete adjoint of one step n -> n+1: the transpose of the step's
+ * linearisation (the step of Algorithm 1 with the rules of Sec. II-III), for
+ * gradients of a loss L of the plane statistics with respect to the STG
+ * amplitude scalings s_b (Sec. III.A, Eq. (22)) and C_s (Sec. II.B, Eq. (14)).
+ *  s_n      device buffer of the post-collision state at time n (storage type
+ *           and brick layout of the handle), 256-byte aligned;
+ *  hist_n   device float [5][ny][nz], its outlet history (LBM_X_INFLOW);
+ *  t_next   n + 1, the STG time of the step (the inlet plane is recomputed);
+ *  lam_next dL/ds_{n+1}: device float bricks (lbm_state_elems() elements,
+ *           256-byte aligned; padding nodes are neither read nor written);
+ *  eta_next dL/dhist_{n+1}: device float [5][ny][nz] (LBM_X_INFLOW);
+ *  lam_prev (written) dL/ds_n, float bricks, must not alias lam_next;
+ *  eta_prev (written) dL/dhist_n (LBM_X_INFLOW), must not alias eta_next;
+ *  coef     device float [n_planes][ny][9]: dL/d(the sums over z of u, v, w,
+ *           uu, vv, ww, uv, uw, vw that step n -> n+1 adds at the attached
+ *           statistics planes, see lbm_stats), or NULL when the step is not
+ *           sampled;
+ *  g_uin    (written, optional) dL/du_in(t_next), device float [3][ny][nz];
+ *  grad     (accumulated, optional) device double [n_bins + 1]:
+ *           grad[b] += dL/ds_b for the bins of the bound STG inputs (n_bins = 0
+ *           with LBM_X_PERIODIC), grad[n_bins] += dL/dC_s (FP64, fixed-order
+ *           sums: the result does not depend on scheduling).
+ * Chaining calls backwards from lam = eta = 0, with the states of the forward
+ * run, gives the gradient of a loss of the accumulated statistics.  The wall
+ * law's u_tau is differentiated at its root.  Uses the handle's configuration
+ * (C_s, rates, STG tables) and statistics planes; the handle's own state is
+ * neither read nor changed.  Overwrites the bound stg->u_in (and stg->fluct)
+ * with the plane at t_next.  Errors: LBM_ERR_ARG (NULL or aliasing
+ * buffers), LBM_ERR_SHAPE (alignment), LBM_ERR_STATE (LBM_X_INFLOW without
+ * bound STG inputs, coef without statistics planes).  Asynchronous on the
+ * handle's stream.
+ */
+lbm_status lbm_adjoint_step(lbm_handle h, const lbm_stg* stg, const void* s_n, const float* hist_n, double t_next,
+                            const float* lam_next, const float* eta_next, float* lam_prev, float* eta_prev,
+                            const float* coef, float* g_uin, double* grad);
+
+/* Float brick field (an adjoint field lam) <-> float SoA [19][N], device buffers. */
+lbm_status lbm_field_export(lbm_handle h, const float* bricks, float* soa);
+lbm_status lbm_field_import(lbm_handle h, const float* soa, float* bricks);
+
 /* Wait for the handle's stream; return and clear any latched device error. */
 lbm_status lbm_sync(lbm_handle h);
 const char* lbm_status_str(lbm_status s);

@@ -187,6 +187,12 @@ class Channel:
         A.check(A.lib().lbm_import_f32(self._h, _ptr(f)), "lbm_import_f32")
         self._keep_import = f
 
+    def point_state(self, f_a, f_b, hist_a, hist_b, time):
+        """Point the handle at caller buffers (no copy): the state is in f_a / hist_a at `time`,
+        the next step writes f_b / hist_b."""
+        A.check(A.lib().lbm_set_state(self._h, _ptr(f_a), _ptr(f_b), _ptr(hist_a), _ptr(hist_b), int(time)),
+                "lbm_set_state")
+
     def set_state(self, f_cur, hist_cur, time):
         """Restore a state (checkpoint): copies into the buffers and sets the time index."""
         self.f[0].copy_(f_cur)
@@ -213,6 +219,38 @@ class Channel:
         A.check(A.lib().lbm_stats(self._h, A.STATS_READ, None, 0, out.ctypes.data_as(C.c_void_p), C.byref(n)),
                 "lbm_stats read")
         return out, n.value
+
+    # ---- adjoint ----
+    def set_cs_smag(self, cs):
+        A.check(A.lib().lbm_set_cs_smag(self._h, float(cs)), "lbm_set_cs_smag")
+        self.cfg.cs_smag = float(cs)
+
+    def new_field(self):
+        """A zeroed float brick field (an adjoint lam), shape (nx, zc, ny, 19, 64)."""
+        return torch.zeros((self.nx, self.zc, self.ny, 19, 64), dtype=torch.float32, device=self.device)
+
+    def field_export(self, bricks):
+        out = torch.empty((19, self.nx, self.ny, self.nz), dtype=torch.float32, device=self.device)
+        A.check(A.lib().lbm_field_export(self._h, _ptr(bricks), _ptr(out)), "lbm_field_export")
+        return out
+
+    def field_import(self, soa, bricks=None):
+        soa = _dev(soa, torch.float32, self.device).reshape(19, self.N)
+        bricks = self.new_field() if bricks is None else bricks
+        A.check(A.lib().lbm_field_import(self._h, _ptr(soa), _ptr(bricks)), "lbm_field_import")
+        self._keep_import = soa
+        return bricks
+
+    def adjoint_step(self, s_n, hist_n, t_next, lam_next, lam_prev, eta_next=None, eta_prev=None, coef=None,
+                     g_uin=None, grad=None):
+        """lam_prev = dL/ds_n (and eta_prev = dL/dhist_n) from lam_next = dL/ds_{n+1}; grad (device
+        float64 [n_bins + 1]) += (dL/ds_b..., dL/dC_s).  coef: [n_planes, ny, 9] statistics weights."""
+        coef = None if coef is None else _dev(coef, torch.float32, self.device)
+        st = A.lib().lbm_adjoint_step(self._h, self._stg_arg(), _ptr(s_n), _ptr(hist_n), float(t_next),
+                                      _ptr(lam_next), _ptr(eta_next), _ptr(lam_prev), _ptr(eta_prev), _ptr(coef),
+                                      _ptr(g_uin), _ptr(grad))
+        A.check(st, "lbm_adjoint_step")
+        self._keep_coef = coef
 
     # ---- timing ----
     def kernel_timing(self, enable):

@@ -1,0 +1,555 @@
+// Discrete adjoint of the fused collide-stream step (the transpose of the
+// linearised Algorithm 1 step of Xue, Yao, Davidson, arXiv 2304.04214), for
+// gradients of statistics losses with respect to the STG amplitude scalings
+// s_b (Sec. III.A, Eq. (22)-(25)) and the Smagorinsky constant C_s
+// (Sec. II.B, Eq. (13)-(15)).
+//
+// Formulation.  Node X of step n -> n+1 pulls 19 values of s_n (Eq. (3) with
+// the wall rules), applies its boundary rules, the wall force and the
+// collision.  Every element of s_n is pulled by at most one node, so the
+// adjoint of the pull is a scatter to the same addresses, with no conflicts:
+// a thread recomputes its node's forward step from s_n, pulls
+// lam_{n+1}(X) back through the collision, the wall force and the boundary
+// rules to its 19 pulled values, and stores each at the address it was pulled
+// from.  Couplings between nodes beyond the pull:
+//  * wall model: a first off-wall cell reads the velocity of the next row;
+//    its sensitivity goes back to that row through LDS (the block holds both);
+//  * convective outlet: the outlet node at x = nx-1 reads the pulled values of
+//    the node at nx-2.  The outlet plane runs first; it stores dL/dhist_n,
+//    and the nodes at nx-2 add U_c times it to their c_x < 0 values.
+// Elements of s_n that no node pulls (the x = 0 and x = nx-1 planes of an open
+// channel) get zero from a fill that runs before the scatter.
+//
+// The Newton solve for u_tau is differentiated through its converged root
+// (implicit function theorem), not through the truncated iteration.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+
+#include "internal.h"
+#include "stream.h"
+
+namespace lbm {
+namespace {
+
+// Moments (M v)_k of a population vector in the Appendix A.1 basis, from its
+// opposite-pair sums and differences.
+__device__ __forceinline__ void moments(const float v[Q], float m[Q]) {
+  const Pairs p = make_pairs(v);
+  const float* s = p.s;
+  const float* d = p.d;
+  const float T04 = s[0] + s[4], T26 = s[2] + s[6], T1357 = s[1] + s[3] + s[5] + s[7];
+  m[0] = p.A + p.Bx + v[9];
+  m[1] = 8.f * p.A - 11.f * p.Bx - 30.f * v[9];
+  m[2] = p.A - 4.f * p.Bx + 12.f * v[9];
+  m[3] = (d[3] + d[7]) - (d[1] + d[5] + d[8]);
+  m[4] = (d[3] + d[7]) - (d[1] + d[5]) + 4.f * d[8];
+  m[5] = d[4] - (d[0] + d[5] + d[6] + d[7]);
+  m[6] = d[4] - (d[0] + d[5] + d[7]) + 4.f * d[6];
+  m[7] = -(d[0] + d[1] + d[2] + d[3] + d[4]);
+  m[8] = 4.f * d[2] - (d[0] + d[1] + d[3] + d[4]);
+  m[9] = 2.f * (s[8] - T04) + T1357 - T26;
+  m[10] = -2.f * T04 + T1357 + 2.f * T26 - 4.f * s[8];
+  m[11] = (s[5] + s[6] + s[7]) - (s[1] + s[2] + s[3]);
+  m[12] = (s[5] + s[7] - 2.f * s[6]) - (s[1] + s[3] - 2.f * s[2]);
+  m[13] = s[5] - s[7];
+  m[14] = s[0] - s[4];
+  m[15] = s[1] - s[3];
+  m[16] = (d[1] + d[7]) - (d[3] + d[5]);
+  m[17] = (d[4] + d[5] + d[7]) - d[0];
+  m[18] = (d[0] + d[4]) - (d[1] + d[3]);
+}
+
+// g += M^T nu, assembled per opposite pair (the transpose of moments()).
+__device__ __forceinline__ void add_mt(float g[Q], const float nu[Q]) {
+  const float P = nu[0] + 8.f * nu[1] + nu[2], Qx = nu[0] - 11.f * nu[1] - 4.f * nu[2];
+  const float b910 = nu[9] + nu[10], c1112 = nu[11] + nu[12];
+  const float h = 2.f * nu[10] - nu[9], kk = 2.f * nu[12] - nu[11];
+  float E[9], O[9];
+  E[0] = P - 2.f * b910 + nu[14];
+  E[4] = P - 2.f * b910 - nu[14];
+  E[1] = P + b910 - c1112 + nu[15];
+  E[3] = P + b910 - c1112 - nu[15];
+  E[5] = P + b910 + c1112 + nu[13];
+  E[7] = P + b910 + c1112 - nu[13];
+  E[2] = Qx + h + kk;
+  E[6] = Qx + h - kk;
+  E[8] = Qx + 2.f * nu[9] - 4.f * nu[10];
+  const float B34 = nu[3] + nu[4], B56 = nu[5] + nu[6], B78 = nu[7] + nu[8];
+  O[0] = -B56 - B78 - nu[17] + nu[18];
+  O[4] = B56 - B78 + nu[17] + nu[18];
+  O[1] = -B34 - B78 + nu[16] - nu[18];
+  O[3] = B34 - B78 - nu[16] - nu[18];
+  O[5] = -B34 - B56 - nu[16] + nu[17];
+  O[7] = B34 - B56 + nu[16] + nu[17];
+  O[2] = 4.f * nu[8] - nu[7];
+  O[6] = 4.f * nu[6] - nu[5];
+  O[8] = 4.f * nu[4] - nu[3];
+#pragma unroll
+  for (int k = 0; k < 9; ++k) {
+    g[k] += E[k] + O[k];
+    g[18 - k] += E[k] - O[k];
+  }
+  g[9] += nu[0] - 30.f * nu[1] + 12.f * nu[2];
+}
+
+// Adjoint of the regularised inlet (inlet_regularize): gb holds dL/d(inlet
+// populations) on entry and dL/d(pulled populations) on return (zero for
+// c_x > 0, which the rule does not read); ub receives dL/du_in.
+__device__ __forceinline__ void inlet_adjoint(float rin, float ux, float uy, float uz, float gb[Q], float& ubx,
+                                              float& uby, float& ubz) {
+  // dL/dPi_neq
+  float Pxx = 0.f, Pyy = 0.f, Pzz = 0.f, Pxy = 0.f, Pyz = 0.f, Pxz = 0.f;
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    const float c = 4.5f * (float)WD[i] * gb[i];
+    Pxx += (CX[i] * CX[i] - 1.f / 3.f) * c;
+    Pyy += (CY[i] * CY[i] - 1.f / 3.f) * c;
+    Pzz += (CZ[i] * CZ[i] - 1.f / 3.f) * c;
+    Pxy += (2 * CX[i] * CY[i]) * c;
+    Pyz += (2 * CY[i] * CZ[i]) * c;
+    Pxz += (2 * CX[i] * CZ[i]) * c;
+  }
+  const float uu15 = 1.5f * (ux * ux + uy * uy + uz * uz);
+  const float i1u = 1.f / (1.f - ux);
+  float rb = 0.f;
+  ubx = uby = ubz = 0.f;
+  float fb[Q];
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    // dL/df_neq_i (c_x <= 0 only enter Pi_neq, the c_x < 0 ones twice)
+    float feqb = gb[i];
+    fb[i] = 0.f;
+    if (CX[i] <= 0) {
+      const float fnb = (CX[i] * CX[i] - 1.f / 3.f) * Pxx + (CY[i] * CY[i] - 1.f / 3.f) * Pyy +
+                        (CZ[i] * CZ[i] - 1.f / 3.f) * Pzz + (CX[i] * CY[i]) * Pxy + (CY[i] * CZ[i]) * Pyz +
+                        (CX[i] * CZ[i]) * Pxz;
+      const float mult = CX[i] == 0 ? 1.f : 2.f;
+      fb[i] = mult * fnb;
+      feqb -= mult * fnb;
+    }
+    // f_eq_i = w_i rin (1 + 3 cu + 4.5 cu^2 - 1.5 uu)
+    const float cu = CX[i] * ux + CY[i] * uy + CZ[i] * uz;
+    const float wr = (float)WD[i] * feqb;
+    rb += wr * (1.f + 3.f * cu + 4.5f * cu * cu - uu15);
+    const float t = wr * rin * (3.f + 9.f * cu);
+    ubx += t * CX[i] - wr * rin * 3.f * ux;
+    uby += t * CY[i] - wr * rin * 3.f * uy;
+    ubz += t * CZ[i] - wr * rin * 3.f * uz;
+  }
+  // rin = (rho_0 + 2 rho_-) / (1 - u_x)
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    if (CX[i] == 0) fb[i] += rb * i1u;
+    if (CX[i] == -1) fb[i] += 2.f * rb * i1u;
+    gb[i] = fb[i];
+  }
+  ubx += rb * rin * i1u;
+}
+
+// One thread per node; a block is 4 consecutive y rows of one (x, z-chunk),
+// entries first .. first + gridDim.x - 1 in memory order.
+template <bool F16>
+__global__ __launch_bounds__(BLOCK) void adjoint_kernel(AdjointArgs A) {
+  __shared__ float lds_u2[2][2][ZT];  // forward: (u_x, u_z) of rows 1 and ny-2
+  __shared__ float lds_g2[2][2][ZT];  // reverse: dL/d(u_x, u_z) of those rows, from the wall rows
+  __shared__ double lds_cs[YROWS];
+  const CollideArgs& a = A.c;
+  const int e = A.first + (int)blockIdx.x;
+  int x, zci, gy;
+  block_coords(a, e, x, zci, gy);
+  const int lane = threadIdx.x & (ZT - 1);
+  const int w = uni(threadIdx.x >> 6);
+  const int base = min(YROWS * gy, a.ny - YROWS);
+  const int y = base + w;
+  // The block that scatters a row must hold every term of its adjoint: with
+  // the wall model, row ny-2 receives the top wall row's sensitivity, so it
+  // belongs to the top block even where ragged ny puts it in another group.
+  bool own = y >= YROWS * gy;
+  if (a.wall_model && y == a.ny - 2) own = base == a.ny - YROWS;
+  const int zraw = zci * ZT + lane;
+  const bool active = zraw < a.nz;
+  const int z = active ? zraw : a.nz - 1;  // inactive lanes compute a valid node and store nothing
+  const bool mine = own && active;
+  const Col col = make_col<F16>(a, z);
+  const Geo g = make_geo(a, x, y);
+  typename Pop<F16>::Raw r[Q];
+  issue_pulls<F16>(a, g, col, r);
+  const uint32_t erow = rowpart(a, x, y) + col.c0;
+  float lam[Q];
+#pragma unroll
+  for (int i = 0; i < Q; ++i) lam[i] = A.lam_next[erow + (uint32_t)i * ZT];
+  float f[Q];
+  convert_pulls<F16>(a, g, r, f);
+
+  // ---- forward recompute: boundary rules ----
+  const bool inflow = a.xbc == LBM_X_INFLOW;
+  const bool outlet = inflow && x == a.nx - 1, inlet = inflow && x == 0;
+  if (outlet) {
+    const Geo g2 = make_geo(a, x - 1, y);
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+      const int i = OUT5[k];
+      const float up = pull_dir<F16>(a, g2, i, col, 0.f);
+      f[i] = (a.hist_in[(k * a.ny + y) * a.nz + z] + a.u_conv * up) * a.inv_1pu;
+    }
+  }
+  float rin = 0.f;
+  if (inlet) rin = inlet_regularize(a, y, z, f);
+
+  // ---- forward recompute: density, momentum, wall force ----
+  const Pairs pr = make_pairs(f);
+  const float rho = pr.A + pr.Bx + f[9];
+  const float jx = (pr.d[3] + pr.d[7]) - (pr.d[1] + pr.d[5] + pr.d[8]);
+  const float jy = pr.d[4] - (pr.d[0] + pr.d[5] + pr.d[6] + pr.d[7]);
+  const float jz = -(pr.d[0] + pr.d[1] + pr.d[2] + pr.d[3] + pr.d[4]);
+  const float iw = 1.f / rho;  // pre-force velocities j / rho of the wall model
+  float Fx = rho * a.g[0], Fy = rho * a.g[1], Fz = rho * a.g[2];
+  const bool bot = base == 0, top = base == a.ny - YROWS;
+  const bool wblock = a.wall_model && (bot || top);  // block-uniform
+  const bool wrow = wblock && ((bot && y == 0) || (top && y == a.ny - 1));
+  const bool nrow = wblock && ((bot && y == 1) || (top && y == a.ny - 2));
+  const int wslot = (bot && y <= 1) ? 0 : 1;
+  bool wact = false;
+  float wex = 0.f, wez = 0.f, witn = 0.f, wtw = 0.f, wut = 1.f, wdg = 1.f, wsg = 0.f;
+  if (wblock) {
+    if (nrow) {
+      lds_u2[wslot][0][lane] = jx * iw;
+      lds_u2[wslot][1][lane] = jz * iw;
+    }
+    __syncthreads();
+    if (wrow) {
+      const float u2x = lds_u2[wslot][0][lane], u2z = lds_u2[wslot][1][lane];
+      const float tn2 = u2x * u2x + u2z * u2z;
+      if (tn2 > 0.f) {
+        witn = 1.f / sqrtf(tn2);
+        wex = u2x * witn;
+        wez = u2z * witn;
+        const float uhat = jx * iw * wex + jz * iw * wez;
+        if (uhat != 0.f) {
+          wact = true;
+          wut = newton_utau(a, fabsf(uhat));
+          wsg = uhat > 0.f ? 1.f : -1.f;
+          wtw = -wsg * rho * wut * wut;
+          Fx += wtw * wex;
+          Fz += wtw * wez;
+          const float yp = a.y_wall * wut * a.inv_nu0;
+          float up, dup;
+          reichardt(a, yp, up, dup);
+          wdg = up + yp * dup;  // d(u_tau u+)/du_tau at the root
+        }
+      }
+    }
+  }
+
+  // ---- forward recompute: collision quantities (as in collide()) ----
+  float ml[Q];
+  {
+    float mf[Q];
+    moments(f, mf);
+#pragma unroll
+    for (int k = 0; k < Q; ++k) ml[k] = mf[k];  // forward moments, replaced by those of lambda below
+  }
+  const float ir = rcp_fast(rho);
+  const float px = jx + 0.5f * Fx, py = jy + 0.5f * Fy, pz = jz + 0.5f * Fz;
+  const float ux = px * ir, uy = py * ir, uz = pz * ir;
+  const float uxx = ux * ux, uyy = uy * uy, uzz = uz * uz, uu = uxx + uyy + uzz;
+  const float e1 = ml[1] - rho * (19.f * uu - 11.f);
+  const float q9 = rho * (2.f * uxx - uyy - uzz);
+  const float q11 = rho * (uyy - uzz);
+  const float e9 = ml[9] - q9;
+  const float e11 = ml[11] - q11;
+  const float e13 = ml[13] - px * uy, e14 = ml[14] - py * uz, e15 = ml[15] - px * uz;
+  const float dc2 = e1 * (1.f / 19.f);
+  const float pxx = (e9 + dc2) * (1.f / 3.f);
+  const float pyy = 0.5f * (dc2 - pxx + e11), pzz = 0.5f * (dc2 - pxx - e11);
+  const float q2 = pxx * pxx + pyy * pyy + pzz * pzz + 2.f * (e13 * e13 + e14 * e14 + e15 * e15);
+  const float Qh = sqrt_fast(q2);
+  const float rr = sqrt_fast(a.tau0sq + a.smag * Qh * ir);
+  const float tau = 0.5f * a.tau0 + 0.5f * rr;
+  const float sv = rcp_fast(tau);
+  const float hv = 1.f - 0.5f * sv;
+  const float uF = ux * Fx + uy * Fy + uz * Fz;
+  const float F9 = 2.f * (2.f * ux * Fx - uy * Fy - uz * Fz);
+  const float F11 = 2.f * (uy * Fy - uz * Fz);
+  const float F13 = ux * Fy + uy * Fx, F14 = uy * Fz + uz * Fy, F15 = ux * Fz + uz * Fx;
+
+  // ---- reverse: collision ----
+  moments(lam, ml);  // (M lambda)_k; delta_k / D_k enters f*, so mu_k = (M lambda)_k / D_k
+  float nu[Q];       // dL/dm (moment-space cotangent of the pre-collision populations)
+  float Fb1, Fb2, Fb4, Fb6, Fb8, Fb10, Fb12;
+  nu[1] = -a.rs[1] * ml[1];
+  Fb1 = a.rf[1] * ml[1];
+  nu[2] = -a.rs[2] * ml[2];
+  Fb2 = a.rf[2] * ml[2];
+  nu[4] = -a.rs[4] * ml[4];
+  Fb4 = a.rf[4] * ml[4];
+  nu[6] = -a.rs[6] * ml[6];
+  Fb6 = a.rf[6] * ml[6];
+  nu[8] = -a.rs[8] * ml[8];
+  Fb8 = a.rf[8] * ml[8];
+  nu[10] = -a.rs[10] * ml[10];
+  Fb10 = a.rf[10] * ml[10];
+  nu[12] = -a.rs[12] * ml[12];
+  Fb12 = a.rf[12] * ml[12];
+  nu[16] = -a.rs[16] * ml[16];
+  nu[17] = -a.rs[17] * ml[17];
+  nu[18] = -a.rs[18] * ml[18];
+  const float mu9 = ml[9] * (1.f / 36.f), mu11 = ml[11] * (1.f / 12.f);
+  const float mu13 = 0.25f * ml[13], mu14 = 0.25f * ml[14], mu15 = 0.25f * ml[15];
+  nu[9] = -sv * mu9;
+  nu[11] = -sv * mu11;
+  nu[13] = -sv * mu13;
+  nu[14] = -sv * mu14;
+  nu[15] = -sv * mu15;
+  const float Fb9 = hv * mu9, Fb11 = hv * mu11, Fb13 = hv * mu13, Fb14 = hv * mu14, Fb15 = hv * mu15;
+  // viscous rate 1/tau_eff -> tau_eff -> Q^(1/2), rho and C_s
+  const float svb = -(mu9 * (e9 + 0.5f * F9) + mu11 * (e11 + 0.5f * F11) + mu13 * (e13 + 0.5f * F13) +
+                      mu14 * (e14 + 0.5f * F14) + mu15 * (e15 + 0.5f * F15));
+  const float taub = -svb * sv * sv;
+  const float Xb = taub * 0.25f * rcp_fast(rr);
+  const float Qhb = Xb * a.smag * ir;
+  float rhob = -Xb * a.smag * Qh * ir * ir;
+  const float csb = Xb * Qh * ir * A.dsmag;
+  const float q2b = Qh > 0.f ? 0.5f * Qhb * rcp_fast(Qh) : 0.f;
+  {
+    const float pxxb = 2.f * q2b * pxx, pyyb = 2.f * q2b * pyy, pzzb = 2.f * q2b * pzz;
+    nu[13] += 4.f * q2b * e13;
+    nu[14] += 4.f * q2b * e14;
+    nu[15] += 4.f * q2b * e15;
+    const float Pt = pxxb - 0.5f * (pyyb + pzzb);
+    const float dc2b = 0.5f * (pyyb + pzzb) + Pt * (1.f / 3.f);
+    nu[11] += 0.5f * (pyyb - pzzb);
+    nu[9] += Pt * (1.f / 3.f);
+    nu[1] += dc2b * (1.f / 19.f);
+  }
+  // equilibrium moments as functions of rho and p = rho u (e_k = m_k - m_eq_k)
+  const float q9b = -nu[9] + 0.5f * nu[10], q11b = -nu[11] + 0.5f * nu[12];
+  float pxb = -38.f * ux * nu[1] + 11.f * ux * nu[2] + (2.f / 3.f) * nu[4] + 4.f * ux * q9b - uy * nu[13] -
+              uz * nu[15];
+  float pyb = -38.f * uy * nu[1] + 11.f * uy * nu[2] + (2.f / 3.f) * nu[6] - 2.f * uy * q9b + 2.f * uy * q11b -
+              ux * nu[13] - uz * nu[14];
+  float pzb = -38.f * uz * nu[1] + 11.f * uz * nu[2] + (2.f / 3.f) * nu[8] - 2.f * uz * q9b - 2.f * uz * q11b -
+              uy * nu[14] - ux * nu[15];
+  rhob += (19.f * uu + 11.f) * nu[1] - (3.f + 5.5f * uu) * nu[2] - (2.f * uxx - uyy - uzz) * q9b -
+          (uyy - uzz) * q11b + ux * uy * nu[13] + uy * uz * nu[14] + ux * uz * nu[15];
+  // Guo force moments F_k(u, F); the conserved moments 3, 5, 7 gain F itself
+  const float uFb = 38.f * Fb1 - 11.f * Fb2;
+  const float A9 = Fb9 - 0.5f * Fb10, A11 = Fb11 - 0.5f * Fb12;
+  float uxb = uFb * Fx + 4.f * A9 * Fx + Fb13 * Fy + Fb15 * Fz;
+  float uyb = uFb * Fy - 2.f * A9 * Fy + 2.f * A11 * Fy + Fb13 * Fx + Fb14 * Fz;
+  float uzb = uFb * Fz - 2.f * A9 * Fz - 2.f * A11 * Fz + Fb14 * Fy + Fb15 * Fx;
+  float Fxb = uFb * ux - (2.f / 3.f) * Fb4 + 4.f * A9 * ux + Fb13 * uy + Fb15 * uz + 0.1f * ml[3];
+  float Fyb = uFb * uy - (2.f / 3.f) * Fb6 - 2.f * A9 * uy + 2.f * A11 * uy + Fb13 * ux + Fb14 * uz + 0.1f * ml[5];
+  float Fzb = uFb * uz - (2.f / 3.f) * Fb8 - 2.f * A9 * uz - 2.f * A11 * uz + Fb14 * uy + Fb15 * ux + 0.1f * ml[7];
+  // statistics source: d/du of sum_k coef_k (u, v, w, uu, vv, ww, uv, uw, vw)
+  if (A.coef) {
+    const int p = a.plane_of_x[x];
+    if (p >= 0) {
+      const float* c = A.coef + ((size_t)p * a.ny + y) * 9;
+      uxb += c[0] + 2.f * c[3] * ux + c[6] * uy + c[7] * uz;
+      uyb += c[1] + 2.f * c[4] * uy + c[6] * ux + c[8] * uz;
+      uzb += c[2] + 2.f * c[5] * uz + c[7] * ux + c[8] * uy;
+    }
+  }
+  // u = p / rho, p = j + F / 2, F = rho g + F_w
+  pxb += uxb * ir;
+  pyb += uyb * ir;
+  pzb += uzb * ir;
+  rhob -= (uxb * ux + uyb * uy + uzb * uz) * ir;
+  float jxb = pxb, jyb = pyb, jzb = pzb;
+  Fxb += 0.5f * pxb;
+  Fyb += 0.5f * pyb;
+  Fzb += 0.5f * pzb;
+  rhob += Fxb * a.g[0] + Fyb * a.g[1] + Fzb * a.g[2];
+
+  // ---- reverse: wall force F_w = -sign(u_hat) rho u_tau^2 e ----
+  if (wblock) {
+    float u2xb = 0.f, u2zb = 0.f;
+    if (wact) {
+      const float twb = Fxb * wex + Fzb * wez;
+      float exb = wtw * Fxb, ezb = wtw * Fzb;
+      rhob += twb * wtw * iw;
+      const float utb = twb * 2.f * wtw / wut;
+      const float uhb = wsg * utb / wdg;  // u_tau(|u_hat|): du_tau/d|u_hat| = 1 / wdg
+      const float uwx = jx * iw, uwz = jz * iw;
+      exb += uhb * uwx;
+      ezb += uhb * uwz;
+      const float uwxb = uhb * wex, uwzb = uhb * wez;
+      jxb += uwxb * iw;
+      jzb += uwzb * iw;
+      rhob -= (uwxb * uwx + uwzb * uwz) * iw;
+      const float ed = wex * exb + wez * ezb;  // e = t / |t|
+      u2xb = (exb - wex * ed) * witn;
+      u2zb = (ezb - wez * ed) * witn;
+    }
+    if (wrow) {
+      lds_g2[wslot][0][lane] = u2xb;
+      lds_g2[wslot][1][lane] = u2zb;
+    }
+    __syncthreads();
+    if (nrow) {  // this row's pre-force velocity fed the wall row's base vector
+      const float gx = lds_g2[wslot][0][lane], gz = lds_g2[wslot][1][lane];
+      jxb += gx * iw;
+      jzb += gz * iw;
+      rhob -= (gx * jx + gz * jz) * iw * iw;
+    }
+  }
+
+  // ---- dL/d(post-boundary populations) = lambda + M^T nu ----
+  nu[0] = rhob;
+  nu[3] = jxb;
+  nu[5] = jyb;
+  nu[7] = jzb;
+  add_mt(lam, nu);
+  float* gb = lam;
+
+  // ---- reverse: boundary rules ----
+  if (outlet) {
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+      const int i = OUT5[k];
+      const int hidx = (k * a.ny + y) * a.nz + z;
+      const float v = (gb[i] + A.eta_next[hidx]) * a.inv_1pu;  // hist_{n+1} holds these populations
+      if (mine) A.eta_prev[hidx] = v;
+      gb[i] = 0.f;
+    }
+  }
+  if (inflow && x == a.nx - 2) {  // values read by the outlet node through its upstream term
+#pragma unroll
+    for (int k = 0; k < 5; ++k) gb[OUT5[k]] += a.u_conv * A.eta_prev[(k * a.ny + y) * a.nz + z];
+  }
+  if (inlet) {
+    const int pl = a.ny * a.nz, o = y * a.nz + z;
+    const float uix = a.u_in[o], uiy = a.u_in[pl + o], uiz = a.u_in[2 * pl + o];
+    float ubx, uby, ubz;
+    inlet_adjoint(rin, uix, uiy, uiz, gb, ubx, uby, ubz);
+    if (mine) {
+      A.g_uin[o] = ubx;
+      A.g_uin[pl + o] = uby;
+      A.g_uin[2 * pl + o] = ubz;
+    }
+  }
+
+  // ---- scatter to the addresses the pulls read ----
+  if (mine) {
+    const Col cl = make_col<false>(a, z);
+    char* base_l = reinterpret_cast<char*>(A.lam_prev);
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+      const int cx = CX[i], cy = CY[i], cz = CZ[i];
+      uint32_t cs = cz == 1 ? cl.bm : (cz == -1 ? cl.bp : cl.b0);
+      int plane = i, xsrc = g.xs[cx + 1], ysrc = g.ys[cy + 1];
+      if (cy != 0) {
+        const bool out = g.yout[cy + 1];
+        const bool bb = out && a.ywall == LBM_Y_BOUNCEBACK;
+        plane = out ? (bb ? opp(i) : REFLY[i]) : i;
+        xsrc = bb ? g.x : xsrc;
+        ysrc = out ? g.y : ysrc;
+        cs = bb ? cl.b0 : cs;
+      }
+      if (pull_ok(a, g, i))
+        *reinterpret_cast<float*>(base_l + (size_t)(rowpart(a, xsrc, ysrc) + (uint32_t)plane * ZT) * 4u + cs) = gb[i];
+    }
+  }
+
+  // ---- dL/dC_s of the block (fixed-order FP64 reduction) ----
+  double c = mine ? (double)csb : 0.0;
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) c += __shfl_xor(c, off, ZT);
+  if (lane == 0) lds_cs[w] = c;
+  __syncthreads();
+  if (threadIdx.x == 0) A.cs_part[e] = ((lds_cs[0] + lds_cs[1]) + lds_cs[2]) + lds_cs[3];
+}
+
+// Zero fill of float elements [begin, end).
+__global__ void zero_kernel(float* p, int64_t n) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += stride) p[k] = 0.f;
+}
+
+// Row sums over z and components of g_uin . fluct (FP64, fixed order).
+__global__ __launch_bounds__(256) void amp_rows_kernel(const float* g_uin, const float* fluct, double* rowsum, int ny,
+                                                       int nz) {
+  __shared__ double part[256];
+  const int y = blockIdx.x;
+  double s = 0.0;
+  for (int k = threadIdx.x; k < 3 * nz; k += 256) {
+    const int c = k / nz, z = k - c * nz;
+    const size_t o = ((size_t)c * ny + y) * nz + z;
+    s += (double)g_uin[o] * (double)fluct[o];
+  }
+  part[threadIdx.x] = s;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h) part[threadIdx.x] += part[threadIdx.x + h];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) rowsum[y] = part[0];
+}
+
+// grad[b] += sum of the bin's row sums (rows in order); grad[n_bins] += sum of
+// the per-block dL/dC_s (fixed-order tree).
+__global__ __launch_bounds__(256) void adjoint_finalize_kernel(const double* cs_part, int nblocks,
+                                                               const double* rowsum, const int* bin_of_y, int ny,
+                                                               int n_bins, double* grad) {
+  __shared__ double part[256];
+  double s = 0.0;
+  for (int k = threadIdx.x; k < nblocks; k += 256) s += cs_part[k];
+  part[threadIdx.x] = s;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h) part[threadIdx.x] += part[threadIdx.x + h];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    grad[n_bins] += part[0];
+    if (rowsum)
+      for (int y = 0; y < ny; ++y) {
+        int b = bin_of_y[y];
+        b = b < 0 ? 0 : (b >= n_bins ? n_bins - 1 : b);  // clamped like the STG binding
+        grad[b] += rowsum[y];
+      }
+  }
+}
+
+}  // namespace
+
+// Edge-plane fill (open channel), the outlet plane, then the rest.
+hipError_t launch_adjoint(lbm_ctx* h, const AdjointArgs& args, int storage_f16) {
+  const lbm_config& c = h->cfg;
+  const int per_x = h->zc * h->yg;
+  AdjointArgs A = args;
+  auto run = [&](int first, int count) {
+    A.first = first;
+    if (count <= 0) return;
+    if (storage_f16)
+      adjoint_kernel<true><<<count, BLOCK, 0, h->stream>>>(A);
+    else
+      adjoint_kernel<false><<<count, BLOCK, 0, h->stream>>>(A);
+  };
+  if (c.xbc == LBM_X_INFLOW) {
+    const int64_t plane = (int64_t)h->zc * c.ny * BRICK;  // elements of one x plane (zc * ny bricks)
+    zero_kernel<<<(unsigned)std::min<int64_t>((plane + 255) / 256, 4096), 256, 0, h->stream>>>(A.lam_prev, plane);
+    zero_kernel<<<(unsigned)std::min<int64_t>((plane + 255) / 256, 4096), 256, 0, h->stream>>>(
+        A.lam_prev + (int64_t)(c.nx - 1) * plane, plane);
+    run((c.nx - 1) * per_x, per_x);
+    run(0, (c.nx - 1) * per_x);
+  } else {
+    run(0, h->nblocks);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_adjoint_reduce(lbm_ctx* h, const float* g_uin, const float* fluct, double* grad) {
+  const int ny = h->cfg.ny, nz = h->cfg.nz;
+  const bool bins = g_uin && fluct && h->stg_bound;
+  if (bins) amp_rows_kernel<<<ny, 256, 0, h->stream>>>(g_uin, fluct, h->d_rowsum, ny, nz);
+  adjoint_finalize_kernel<<<1, 256, 0, h->stream>>>(h->d_cs_part, h->nblocks, bins ? h->d_rowsum : nullptr,
+                                                    bins ? h->stg.bin_of_y : nullptr, ny,
+                                                    bins ? h->stg.n_bins : 0, grad);
+  return hipGetLastError();
+}
+
+}  // namespace lbm

@@ -1,6 +1,7 @@
 // C ABI of the library: argument checking, handle state, launch sequencing.
 #include <hip/hip_runtime.h>
 
+#include <cmath>
 #include <cstdint>
 #include <cstring>
 #include <new>
@@ -242,6 +243,10 @@ lbm_status lbm_destroy(lbm_handle h) {
   if (h->d_blist_int) (void)hipFree(h->d_blist_int);
   if (h->d_blist_bnd) (void)hipFree(h->d_blist_bnd);
   if (h->d_err) (void)hipFree(h->d_err);
+  if (h->d_cs_part) (void)hipFree(h->d_cs_part);
+  if (h->d_rowsum) (void)hipFree(h->d_rowsum);
+  if (h->d_fluct) (void)hipFree(h->d_fluct);
+  if (h->d_guin) (void)hipFree(h->d_guin);
   for (hipEvent_t e : h->ev) (void)hipEventDestroy(e);
   destroy_streams(h);
   delete h;
@@ -422,6 +427,70 @@ lbm_status lbm_stats(lbm_handle h, int32_t op, const int32_t* x_planes, int32_t 
     default:
       return LBM_ERR_ARG;
   }
+}
+
+lbm_status lbm_set_cs_smag(lbm_handle h, double cs_smag) {
+  if (!h || !(cs_smag >= 0.0)) return LBM_ERR_ARG;
+  h->cfg.cs_smag = cs_smag;
+  return LBM_OK;
+}
+
+lbm_status lbm_adjoint_step(lbm_handle h, const lbm_stg* stg, const void* s_n, const float* hist_n, double t_next,
+                            const float* lam_next, const float* eta_next, float* lam_prev, float* eta_prev,
+                            const float* coef, float* g_uin, double* grad) {
+  if (!h || !s_n || !lam_next || !lam_prev || lam_next == lam_prev) return LBM_ERR_ARG;
+  if (!aligned256(s_n) || !aligned256(lam_next) || !aligned256(lam_prev)) return LBM_ERR_SHAPE;
+  const bool inflow = h->cfg.xbc == LBM_X_INFLOW;
+  if (inflow && (!hist_n || !eta_next || !eta_prev || eta_next == eta_prev)) return LBM_ERR_ARG;
+  if (stg) {
+    lbm_status st = bind_stg(h, stg);
+    if (st != LBM_OK) return st;
+  }
+  if (inflow && !h->stg_bound) return LBM_ERR_STATE;
+  if (coef && h->n_planes < 1) return LBM_ERR_STATE;
+  const size_t plane = (size_t)3 * h->cfg.ny * h->cfg.nz;
+  if (!h->d_cs_part) HIPCHK(hipMalloc(&h->d_cs_part, sizeof(double) * h->nblocks));
+  if (!h->d_rowsum) HIPCHK(hipMalloc(&h->d_rowsum, sizeof(double) * h->cfg.ny));
+  if (inflow && !h->stg.fluct && !h->d_fluct) HIPCHK(hipMalloc(&h->d_fluct, sizeof(float) * plane));
+  if (inflow && !g_uin && !h->d_guin) HIPCHK(hipMalloc(&h->d_guin, sizeof(float) * plane));
+  lbm::AdjointArgs A;
+  lbm::fill_args(h, A.c, h->cur, h->cur);
+  A.c.src = s_n;
+  A.c.dst = nullptr;
+  A.c.hist_in = inflow ? hist_n : nullptr;
+  A.c.hist_out = nullptr;
+  A.c.stats = nullptr;
+  A.c.stats_on = 0;
+  A.c.u_in = inflow ? h->stg.u_in : nullptr;
+  A.lam_next = lam_next;
+  A.lam_prev = lam_prev;
+  A.eta_next = inflow ? eta_next : nullptr;
+  A.eta_prev = inflow ? eta_prev : nullptr;
+  A.coef = coef;
+  A.g_uin = inflow ? (g_uin ? g_uin : h->d_guin) : nullptr;
+  A.cs_part = h->d_cs_part;
+  A.dsmag = (float)(36.0 * std::sqrt(2.0) * h->cfg.cs_smag);  // d(18 sqrt(2) C_s^2)/dC_s
+  A.first = 0;
+  float* fluct = nullptr;
+  if (inflow) {
+    fluct = h->stg.fluct ? h->stg.fluct : h->d_fluct;
+    HIPCHK(lbm::launch_stg_fill(h, t_next, h->stream, fluct));
+  }
+  HIPCHK(lbm::launch_adjoint(h, A, h->cfg.storage == LBM_STORE_F16DEV));
+  if (grad) HIPCHK(lbm::launch_adjoint_reduce(h, inflow ? A.g_uin : nullptr, fluct, grad));
+  return LBM_OK;
+}
+
+lbm_status lbm_field_export(lbm_handle h, const float* bricks, float* soa) {
+  if (!h || !bricks || !soa) return LBM_ERR_ARG;
+  HIPCHK(lbm::launch_field_export(h, bricks, soa));
+  return LBM_OK;
+}
+
+lbm_status lbm_field_import(lbm_handle h, const float* soa, float* bricks) {
+  if (!h || !bricks || !soa) return LBM_ERR_ARG;
+  HIPCHK(lbm::launch_field_import(h, soa, bricks));
+  return LBM_OK;
 }
 
 lbm_status lbm_sync(lbm_handle h) {

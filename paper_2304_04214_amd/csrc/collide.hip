@@ -22,275 +22,12 @@
 #include <vector>
 
 #include "internal.h"
+#include "stream.h"
 
-#ifndef LBM_EXP_F16_NT
-#define LBM_EXP_F16_NT 1
-#endif
-#ifndef LBM_EXP_F32_NT
-#define LBM_EXP_F32_NT 1
-#endif
 
 
 namespace lbm {
 namespace {
-
-__device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
-
-// Population storage: float, or half deviations h_i = f_i - w_i.
-template <bool F16>
-struct Pop;
-// Loads take a wave-uniform element offset `row` (scalar) and a per-lane byte
-// offset `cb`, so the address is scalar base + 32-bit vector offset.
-template <>
-struct Pop<false> {
-  static constexpr uint32_t ES = 4;
-  using Raw = float;
-  __device__ static __forceinline__ Raw raw(const char* p, uint32_t off) {
-    return *reinterpret_cast<const float*>(p + off);
-  }
-  __device__ static __forceinline__ float cvt(int, Raw r) { return r; }
-  // p: wave-uniform byte pointer; off: per-lane byte offset (+ a constant)
-  __device__ static __forceinline__ float ldp(const char* p, int, uint32_t off) {
-    return *reinterpret_cast<const float*>(p + off);
-  }
-  __device__ static __forceinline__ void stp(char* p, int, uint32_t off, float v) {
-#if LBM_EXP_F32_NT
-    __builtin_nontemporal_store(v, reinterpret_cast<float*>(p + off));  // streamed once, not re-read
-#else
-    *reinterpret_cast<float*>(p + off) = v;
-#endif
-  }
-  __device__ static __forceinline__ void st_plain(void* base, int, uint32_t e, float v) {
-    static_cast<float*>(base)[e] = v;
-  }
-  __device__ static __forceinline__ float ld_plain(const void* base, int, uint32_t e) {
-    return static_cast<const float*>(base)[e];
-  }
-};
-template <>
-struct Pop<true> {
-  static constexpr uint32_t ES = 2;
-  using Raw = uint32_t;  // the 16-bit pattern of h_i
-  __device__ static __forceinline__ Raw raw(const char* p, uint32_t off) {
-    return *reinterpret_cast<const unsigned short*>(p + off);
-  }
-  __device__ static __forceinline__ float cvt(int i, Raw r) {
-    return (float)WD[i] + (float)__builtin_bit_cast(_Float16, (unsigned short)r);
-  }
-  // f = w_i + h_i
-  __device__ static __forceinline__ float ldp(const char* p, int i, uint32_t off) {
-    return (float)WD[i] + (float)*reinterpret_cast<const _Float16*>(p + off);
-  }
-  // h_i = f - w_i rounded to nearest even half
-  __device__ static __forceinline__ void stp(char* p, int i, uint32_t off, float v) {
-    const uint32_t hb = __builtin_bit_cast(unsigned short, (_Float16)(v - (float)WD[i]));
-#if LBM_EXP_F16_NT
-    __builtin_nontemporal_store((unsigned short)hb, reinterpret_cast<unsigned short*>(p + off));
-#else
-    *reinterpret_cast<unsigned short*>(p + off) = (unsigned short)hb;
-#endif
-  }
-  __device__ static __forceinline__ void st_plain(void* base, int i, uint32_t e, float v) {
-    static_cast<_Float16*>(base)[e] = (_Float16)(v - (float)WD[i]);
-  }
-  __device__ static __forceinline__ float ld_plain(const void* base, int i, uint32_t e) {
-    return (float)WD[i] + (float)static_cast<const _Float16*>(base)[e];
-  }
-};
-
-// Byte pointer to the start of the (x, y) brick row of a buffer (wave-uniform).
-template <bool F16>
-__device__ __forceinline__ const char* row_ptr(const void* base, uint32_t rowp) {
-  return static_cast<const char*>(base) + (size_t)rowp * Pop<F16>::ES;
-}
-
-// Wave-uniform source rows of one node row (x, y).
-struct Geo {
-  int x, y;
-  int xs[3];
-  bool xok[3];  // index c_x + 1: source x = x - c_x and whether it lies in the lattice
-  int ys[3];
-  bool yout[3];  // index c_y + 1: source y and whether it lies beyond a wall
-};
-
-__device__ __forceinline__ Geo make_geo(const CollideArgs& a, int x, int y) {
-  Geo g;
-  g.x = x;
-  g.y = y;
-#pragma unroll
-  for (int c = -1; c <= 1; ++c) {
-    int s = x - c;
-    bool ok = true;
-    if (a.xbc == LBM_X_PERIODIC) {
-      s = s < 0 ? s + a.nx : (s >= a.nx ? s - a.nx : s);
-    } else {
-      ok = s >= 0 && s < a.nx;
-      s = s < 0 ? 0 : (s >= a.nx ? a.nx - 1 : s);
-    }
-    g.xs[c + 1] = s;
-    g.xok[c + 1] = ok;
-    int t = y - c;
-    bool out = t < 0 || t >= a.ny;
-    if (a.ywall == LBM_Y_PERIODIC) {
-      t = t < 0 ? t + a.ny : (t >= a.ny ? t - a.ny : t);
-      out = false;
-    } else {
-      t = t < 0 ? 0 : (t >= a.ny ? a.ny - 1 : t);
-    }
-    g.ys[c + 1] = t;
-    g.yout[c + 1] = out;
-  }
-  return g;
-}
-
-constexpr uint32_t BRICK = Q * ZT;  // elements per 64-node brick
-
-// Element offset contributed by (x, y) (wave-uniform) and by z (per lane).
-__device__ __forceinline__ uint32_t rowpart(const CollideArgs& a, int x, int y) {
-  return ((uint32_t)x * (uint32_t)(a.zc * a.ny) + (uint32_t)y) * BRICK;
-}
-__device__ __forceinline__ uint32_t colpart(const CollideArgs& a, int z) {
-  return (uint32_t)(z >> 6) * (uint32_t)a.ny * BRICK + (uint32_t)(z & (ZT - 1));
-}
-
-// Column offsets of z and of its periodic neighbours z - 1 and z + 1, in
-// elements and (times the element size) in bytes.
-struct Col {
-  uint32_t c0, b0, bm, bp;
-};
-template <bool F16>
-__device__ __forceinline__ Col make_col(const CollideArgs& a, int z) {
-  const int zm = z == 0 ? a.nz - 1 : z - 1;
-  const int zp = z == a.nz - 1 ? 0 : z + 1;
-  constexpr uint32_t es = Pop<F16>::ES;
-  const uint32_t c0 = colpart(a, z);
-  return Col{c0, c0 * es, colpart(a, zm) * es, colpart(a, zp) * es};
-}
-
-// Pull of direction i into node (g.x, g.y, z) with the wall rules
-// (Eq. (3); halfway bounce-back or specular slip at the y walls).  Sources
-// outside the x range (inlet unknowns, outlet) give `unset`.  The source plane,
-// row and z are chosen by selects (scalar for plane and row) and the load is
-// always issued from a valid address, so the 19 loads of a node form one
-// straight-line batch.  Opposite and mirrored directions share w_i.
-template <bool F16>
-__device__ __forceinline__ float pull_dir(const CollideArgs& a, const Geo& g, int i, const Col& col, float unset) {
-  const int cx = CX[i], cy = CY[i], cz = CZ[i];
-  const uint32_t cs = cz == 1 ? col.bm : (cz == -1 ? col.bp : col.b0);
-  int plane = i, xsrc = g.xs[cx + 1], ysrc = g.ys[cy + 1];
-  uint32_t csrc = cs;
-  bool ok = g.xok[cx + 1];
-  if (cy != 0) {
-    const bool out = g.yout[cy + 1];
-    const bool bb = out && a.ywall == LBM_Y_BOUNCEBACK;
-    plane = out ? (bb ? opp(i) : REFLY[i]) : i;
-    xsrc = bb ? g.x : xsrc;
-    ysrc = out ? g.y : ysrc;
-    csrc = bb ? col.b0 : cs;
-    ok = bb ? true : ok;
-  }
-  const char* p = row_ptr<F16>(a.src, rowpart(a, xsrc, ysrc) + (uint32_t)plane * ZT);
-  const float v = Pop<F16>::ldp(p, i, csrc);
-  return ok ? v : unset;
-}
-
-// Whether the pulled source of direction i exists (false only for sources
-// outside the x range: inlet unknowns and the outlet's c_x < 0 directions).
-__device__ __forceinline__ bool pull_ok(const CollideArgs& a, const Geo& g, int i) {
-  const int cx = CX[i], cy = CY[i];
-  if (cy != 0 && g.yout[cy + 1] && a.ywall == LBM_Y_BOUNCEBACK) return true;
-  return g.xok[cx + 1];
-}
-
-// A row whose 3 x 3 source rows all lie inside the lattice: no wall, inlet or
-// outlet rule applies and the pulls are plain shifted loads.
-__device__ __forceinline__ bool interior(const Geo& g) {
-  return g.xok[0] && g.xok[2] && !g.yout[0] && !g.yout[2];
-}
-
-// Issue the 19 pull loads of node row g (raw storage values, no conversion),
-// so that they can be in flight while another row is being collided.
-template <bool F16>
-__device__ __forceinline__ void issue_pulls(const CollideArgs& a, const Geo& g, const Col& col,
-                                            typename Pop<F16>::Raw r[Q]) {
-  if (interior(g)) {
-#pragma unroll
-    for (int i = 0; i < Q; ++i) {
-      const uint32_t cs = CZ[i] == 1 ? col.bm : (CZ[i] == -1 ? col.bp : col.b0);
-      r[i] = Pop<F16>::raw(row_ptr<F16>(a.src, rowpart(a, g.xs[CX[i] + 1], g.ys[CY[i] + 1]) + (uint32_t)i * ZT), cs);
-    }
-  } else {
-#pragma unroll
-    for (int i = 0; i < Q; ++i) {
-      const int cx = CX[i], cy = CY[i], cz = CZ[i];
-      const uint32_t cs = cz == 1 ? col.bm : (cz == -1 ? col.bp : col.b0);
-      int plane = i, xsrc = g.xs[cx + 1], ysrc = g.ys[cy + 1];
-      uint32_t csrc = cs;
-      if (cy != 0) {
-        const bool out = g.yout[cy + 1];
-        const bool bb = out && a.ywall == LBM_Y_BOUNCEBACK;
-        plane = out ? (bb ? opp(i) : REFLY[i]) : i;
-        xsrc = bb ? g.x : xsrc;
-        ysrc = out ? g.y : ysrc;
-        csrc = bb ? col.b0 : cs;
-      }
-      r[i] = Pop<F16>::raw(row_ptr<F16>(a.src, rowpart(a, xsrc, ysrc) + (uint32_t)plane * ZT), csrc);
-    }
-  }
-}
-
-// Populations from the raw loads; sources outside the x range give 0.
-template <bool F16>
-__device__ __forceinline__ void convert_pulls(const CollideArgs& a, const Geo& g, const typename Pop<F16>::Raw r[Q],
-                                              float f[Q]) {
-  if (interior(g)) {
-#pragma unroll
-    for (int i = 0; i < Q; ++i) f[i] = Pop<F16>::cvt(i, r[i]);
-  } else {
-#pragma unroll
-    for (int i = 0; i < Q; ++i) f[i] = pull_ok(a, g, i) ? Pop<F16>::cvt(i, r[i]) : 0.f;
-  }
-}
-
-// Regularised inlet populations (Sec. III.A, Eq. (26)-(31)): Zou-He density
-// from the known c_x <= 0 populations, second-order equilibrium at u_in, and
-// the non-equilibrium part rebuilt from Pi_neq with the unknown c_x > 0
-// non-equilibrium populations taken equal to their opposites.
-__device__ __forceinline__ void inlet_regularize(const CollideArgs& a, int y, int z, float f[Q]) {
-  const int pl = a.ny * a.nz, o = y * a.nz + z;
-  const float ux = a.u_in[o], uy = a.u_in[pl + o], uz = a.u_in[2 * pl + o];
-  float rho0 = 0.f, rhom = 0.f;
-#pragma unroll
-  for (int i = 0; i < Q; ++i) {
-    if (CX[i] == 0) rho0 += f[i];
-    if (CX[i] == -1) rhom += f[i];
-  }
-  const float rin = (rho0 + 2.f * rhom) / (1.f - ux);
-  const float uu15 = 1.5f * (ux * ux + uy * uy + uz * uz);
-  float feq[Q];
-  float pxx = 0.f, pyy = 0.f, pzz = 0.f, pxy = 0.f, pyz = 0.f, pxz = 0.f;
-#pragma unroll
-  for (int i = 0; i < Q; ++i) {
-    const float cu = CX[i] * ux + CY[i] * uy + CZ[i] * uz;
-    feq[i] = (float)WD[i] * rin * (1.f + 3.f * cu + 4.5f * cu * cu - uu15);
-    if (CX[i] <= 0) {
-      const float fn = (CX[i] == 0 ? 1.f : 2.f) * (f[i] - feq[i]);
-      pxx += (CX[i] * CX[i] - 1.f / 3.f) * fn;
-      pyy += (CY[i] * CY[i] - 1.f / 3.f) * fn;
-      pzz += (CZ[i] * CZ[i] - 1.f / 3.f) * fn;
-      pxy += (CX[i] * CY[i]) * fn;
-      pyz += (CY[i] * CZ[i]) * fn;
-      pxz += (CX[i] * CZ[i]) * fn;
-    }
-  }
-  const float tr3 = (pxx + pyy + pzz) * (1.f / 3.f);
-#pragma unroll
-  for (int i = 0; i < Q; ++i) {
-    const float cpc = CX[i] * CX[i] * pxx + CY[i] * CY[i] * pyy + CZ[i] * CZ[i] * pzz +
-                      2.f * (CX[i] * CY[i] * pxy + CY[i] * CZ[i] * pyz + CX[i] * CZ[i] * pxz);
-    f[i] = feq[i] + 4.5f * (float)WD[i] * (cpc - tr3);
-  }
-}
 
 // Reichardt wall force of a first off-wall cell (Sec. II.C, Eq. (16)-(21)):
 // base vector from the tangential part of u_2, projected speed u_hat, u_tau
@@ -306,16 +43,7 @@ __device__ __forceinline__ void wall_force(const CollideArgs& a, float rho, floa
   const float ex = u2x * itn, ez = u2z * itn;
   const float uhat = uwx * ex + uwz * ez;
   if (uhat == 0.f) return;
-  const float ua = fabsf(uhat);
-  float ut = sqrtf(a.nu0 * ua / a.y_wall);
-  for (int it = 0; it < a.newton_iters; ++it) {
-    const float yp = a.y_wall * ut * a.inv_nu0;
-    const float e1 = expf(yp * (-1.f / 11.f)), e3 = expf(yp * (-1.f / 3.f));
-    const float up = log1pf(a.kappa * yp) * a.inv_kappa - a.b_reich * (expm1f(yp * (-1.f / 11.f)) + yp * (1.f / 11.f) * e3);
-    const float dup = 1.f / (1.f + a.kappa * yp) +
-                      a.b_reich * ((e1 - e3) * (1.f / 11.f) + yp * (1.f / 33.f) * e3);
-    ut -= (ut * up - ua) / (up + yp * dup);
-  }
+  const float ut = newton_utau(a, fabsf(uhat));
   const float tw = (uhat > 0.f ? -1.f : 1.f) * rho * ut * ut;
   fx = tw * ex;
   fz = tw * ez;
@@ -326,26 +54,6 @@ __device__ __forceinline__ void wall_force(const CollideArgs& a, float rho, floa
 // f* = f + M^-1 delta with delta_k = -s_k (m_k - m_eq_k) + (1 - s_k/2) F_k.
 // The moment transform uses the even/odd split of the basis over the
 // opposite-direction pairs (i, 18 - i).  Returns the force-corrected velocity.
-// Sums and differences over the opposite pairs (i, 18 - i); density and
-// momentum follow from them (Eq. (10)-(11)).
-struct Pairs {
-  float s[9], d[9], A, Bx;
-};
-__device__ __forceinline__ Pairs make_pairs(const float f[Q]) {
-  Pairs p;
-#pragma unroll
-  for (int k = 0; k < 9; ++k) {
-    p.s[k] = f[k] + f[18 - k];
-    p.d[k] = f[k] - f[18 - k];
-  }
-  p.A = p.s[0] + p.s[1] + p.s[3] + p.s[4] + p.s[5] + p.s[7];
-  p.Bx = p.s[2] + p.s[6] + p.s[8];
-  return p;
-}
-
-__device__ __forceinline__ float rcp_fast(float x) { return __builtin_amdgcn_rcpf(x); }
-__device__ __forceinline__ float sqrt_fast(float x) { return __builtin_amdgcn_sqrtf(x); }
-
 template <bool FORCE>
 __device__ __forceinline__ void collide(const CollideArgs& a, float f[Q], const Pairs& pr, float rho, float jx,
                                         float jy, float jz, float Fx, float Fy, float Fz, float& ux, float& uy,
@@ -601,12 +309,6 @@ __device__ __forceinline__ void node_update(const CollideArgs& a, int x, int y, 
 //    statistics planes): the general kernel with every rule of Algorithm 1.
 // Both read s_n and write disjoint nodes of s_{n+1}.  Each walks a block list
 // (x, z-chunk, y-group) in memory order.
-__device__ __forceinline__ void block_coords(const CollideArgs& a, int e, int& x, int& zci, int& gy) {
-  gy = e % a.yg;
-  const int r = e / a.yg;
-  zci = r % a.zc;
-  x = r / a.zc;
-}
 
 template <bool F16, bool FORCE>
 __global__ __launch_bounds__(BLOCK) void collide_interior_kernel(CollideArgs a, const int* __restrict__ blist) {
@@ -739,8 +441,9 @@ __global__ void copy_kernel(const float4* __restrict__ src, float4* __restrict__
   for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n4; k += stride) dst[k] = src[k];
 }
 
-const double kD[Q] = {19, 2394, 252, 10, 40, 10, 40, 10, 40, 36, 72, 12, 24, 4, 4, 4, 8, 8, 8};
+}  // namespace
 
+// Kernel arguments of a launch reading buffer src and writing buffer dst.
 void fill_args(lbm_ctx* h, CollideArgs& a, int src, int dst) {
   const lbm_config& c = h->cfg;
   a.src = h->f[src];
@@ -777,12 +480,11 @@ void fill_args(lbm_ctx* h, CollideArgs& a, int src, int dst) {
   a.u_conv = (float)c.u_conv;
   a.inv_1pu = (float)(1.0 / (1.0 + c.u_conv));
   for (int k = 0; k < Q; ++k) {
-    a.rs[k] = (float)(c.s[k] / kD[k]);
-    a.rf[k] = (float)((1.0 - 0.5 * c.s[k]) / kD[k]);
+    a.rs[k] = (float)(c.s[k] / DNORM[k]);
+    a.rf[k] = (float)((1.0 - 0.5 * c.s[k]) / DNORM[k]);
   }
 }
 
-}  // namespace
 
 hipError_t launch_boundary(lbm_ctx* h, int src, int dst, hipStream_t stream) {
   if (h->n_bnd == 0) return hipSuccess;
@@ -916,6 +618,23 @@ hipError_t launch_import(lbm_ctx* h, const float* in) {
     import_kernel<true><<<h->nblocks, BLOCK, 0, h->stream>>>(a, in);
   else
     import_kernel<false><<<h->nblocks, BLOCK, 0, h->stream>>>(a, in);
+  return hipGetLastError();
+}
+
+// Float bricks <-> float SoA [19][N] for adjoint fields (always FP32).
+hipError_t launch_field_export(lbm_ctx* h, const float* bricks, float* soa) {
+  CollideArgs a;
+  fill_args(h, a, h->cur, h->cur);
+  a.src = bricks;
+  export_kernel<false><<<h->nblocks, BLOCK, 0, h->stream>>>(a, soa);
+  return hipGetLastError();
+}
+
+hipError_t launch_field_import(lbm_ctx* h, const float* soa, float* bricks) {
+  CollideArgs a;
+  fill_args(h, a, h->cur, h->cur);
+  a.dst = bricks;
+  import_kernel<false><<<h->nblocks, BLOCK, 0, h->stream>>>(a, soa);
   return hipGetLastError();
 }
 

@@ -38,6 +38,22 @@ struct CollideArgs {
   float rs[Q], rf[Q];  // s_k / D_k and (1 - s_k/2) / D_k for the fixed-rate moments
 };
 
+// Arguments of the adjoint kernels (passed by value).  c holds the forward
+// arguments with src = s_n, hist_in = its outlet history and u_in = the inlet
+// plane at t_{n+1}; dst, hist_out and stats are unused.
+struct AdjointArgs {
+  CollideArgs c;
+  const float* lam_next;  // dL/ds_{n+1}, float bricks
+  float* lam_prev;        // dL/ds_n, float bricks
+  const float* eta_next;  // dL/dhist_{n+1} [5][ny][nz]
+  float* eta_prev;        // dL/dhist_n [5][ny][nz]
+  const float* coef;      // [n_planes][ny][9] statistics weights, or null
+  float* g_uin;           // dL/du_in [3][ny][nz]
+  double* cs_part;        // [nblocks] per-block dL/dC_s
+  float dsmag;            // d(18 sqrt(2) C_s^2)/dC_s
+  int first;              // block entry of blockIdx.x = 0
+};
+
 struct StgTables {
   int n_modes = 0;
   int cap_trigz = 0, cap_amp3 = 0, cap_ky = 0, cap_chol = 0, cap_sb = 0, cap_urans = 0;
@@ -81,6 +97,11 @@ struct lbm_ctx {
   bool stg_bound = false;
   lbm_stg stg{};
   lbm::StgTables tab;
+  // adjoint scratch (allocated on the first adjoint step)
+  double* d_cs_part = nullptr;  // [nblocks]
+  double* d_rowsum = nullptr;   // [ny]
+  float* d_fluct = nullptr;     // [3][ny][nz], when the bound STG inputs have no fluct buffer
+  float* d_guin = nullptr;      // [3][ny][nz], when the caller passes no g_uin
   int timing = 0;
   std::vector<hipEvent_t> ev;  // pairs (start, stop) of timed launches
   int64_t ev_used = 0;
@@ -98,8 +119,14 @@ hipError_t launch_init(lbm_ctx* h, const float* rho, const float* u, const float
 hipError_t launch_export(lbm_ctx* h, float* out);
 hipError_t launch_import(lbm_ctx* h, const float* in);
 hipError_t launch_copy(const void* src, void* dst, int64_t bytes, hipStream_t s);
+void fill_args(lbm_ctx* h, CollideArgs& a, int src, int dst);
+hipError_t launch_field_export(lbm_ctx* h, const float* bricks, float* soa);
+hipError_t launch_field_import(lbm_ctx* h, const float* soa, float* bricks);
+// adjoint.hip
+hipError_t launch_adjoint(lbm_ctx* h, const AdjointArgs& args, int storage_f16);
+hipError_t launch_adjoint_reduce(lbm_ctx* h, const float* g_uin, const float* fluct, double* grad);
 // stg.hip
 hipError_t launch_stg_bind(lbm_ctx* h, const lbm_stg* s);
-hipError_t launch_stg_fill(lbm_ctx* h, double t, hipStream_t stream);
+hipError_t launch_stg_fill(lbm_ctx* h, double t, hipStream_t stream, float* fluct = nullptr);
 hipError_t launch_inflow_reichardt(lbm_ctx* h, double u_tau, double* u_rans);
 }  // namespace lbm

@@ -179,10 +179,13 @@ hipError_t launch_stg_bind(lbm_ctx* h, const lbm_stg* s) {
   return hipGetLastError();
 }
 
-hipError_t launch_stg_fill(lbm_ctx* h, double time, hipStream_t stream) {
+// fluct, when given, replaces the bound output of the fluctuation a v'.
+hipError_t launch_stg_fill(lbm_ctx* h, double time, hipStream_t stream, float* fluct) {
   const int ny = h->cfg.ny, nz = h->cfg.nz;
   dim3 grid((nz + 63) / 64, ny);
-  stg_fill_kernel<<<grid, 256, 0, stream>>>(h->stg, h->tab, ny, nz, time, h->d_err);
+  lbm_stg s = h->stg;
+  if (fluct) s.fluct = fluct;
+  stg_fill_kernel<<<grid, 256, 0, stream>>>(s, h->tab, ny, nz, time, h->d_err);
   return hipGetLastError();
 }
 
