@@ -7,8 +7,10 @@ outlet / regularised inlet / Reichardt wall model / MRT-Smagorinsky collision
 
 Workload (default): the Re_tau = 1000 channel shape 768 x 64 x 192 (x, y, z),
 FP32 populations, N = 200 STG modes, synthetic inputs.  Also timed: the same
-lattice with FP16-deviation storage, and the Re_tau = 5200 shape
-1536 x 128 x 384 in both storages.
+lattice with FP16-deviation storage, the Re_tau = 5200 shape
+1536 x 128 x 384 in both storages, and the discrete adjoint on the
+256 x 64 x 64 channel (gradient of a mean-profile loss over 400 steps with
+checkpoints every 20 steps).
 
 Prints ONE JSON line.
 """
@@ -82,6 +84,70 @@ def time_channel(name, storage, steps, warmup, device):
                kernel_gbs=BYTES_PER_NODE[storage] * k_nodes / (kern_ms * 1e-3) / 1e9, status=status)
     ch.close()
     del ch
+    torch.cuda.empty_cache()
+    return res
+
+
+ADJ_BYTES_PER_NODE = 228  # s_n read + lam_{n+1} read + lam_n written, 19 floats each
+
+
+def time_adjoint(device, steps=400, segment=20, warmup=20):
+    """Gradient of the mean-profile loss at x = 4 delta over `steps` steps on the
+    256 x 64 x 64 channel (FP32) w.r.t. 64 amplitude scalings and C_s: forward with
+    checkpoints, then the checkpointed adjoint sweep (recompute included)."""
+    import torch
+    from paper_2304_04214_amd.adjoint import StatsGradient, mean_profile_loss
+    from paper_2304_04214_amd import synthetic as S
+    ch, (nx, ny, nz) = make_channel("c4", "f32", device)
+    w = S.WORKLOADS["c4"]
+    N = nx * ny * nz
+    x_obs = int(4 * ny / 2)
+    ch.stats_detach()
+    ch.step(warmup)
+    ch.sync()
+    # forward step time alone (same lattice, statistics on at x_obs)
+    ch.stats_attach([x_obs])
+    ch.kernel_timing(2)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ch.step(steps)
+    torch.cuda.synchronize()
+    fwd_ms = (time.perf_counter() - t0) * 1e3 / steps
+    k_ms, k_n, _ = ch.kernel_timing(0)
+    fwd_kernel_ms = k_ms / max(k_n, 1)
+    run = StatsGradient(ch, [x_obs], steps, segment=segment)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    means = run.forward()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    m = torch.tensor(means, dtype=torch.float64, requires_grad=True)
+    U_t = torch.as_tensor(ch._stg_tensors["u_rans"][0].cpu())
+    R12_t = torch.as_tensor(S.reynolds_stress(ny, w["u_tau"])[1])
+    loss = mean_profile_loss(m[0], U_t, R12_t)
+    loss.backward()
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    g, adj_ms_total = run.backward(m.grad.numpy(), time_kernel=True)
+    torch.cuda.synchronize()
+    t3 = time.perf_counter()
+    status = "ok"
+    try:
+        ch.sync()
+    except Exception as e:
+        status = str(e)
+    adj_ms = adj_ms_total / steps
+    res = dict(workload="256x64x64 channel (FP32), loss at x=%d over %d steps, checkpoint every %d" % (
+        x_obs, steps, segment), nodes=N, forward_ms_per_step=round(fwd_ms, 5),
+        forward_kernel_ms=round(fwd_kernel_ms, 5), adjoint_step_ms=round(adj_ms, 5),
+        adjoint_mlups=round(N / (adj_ms * 1e-3) / 1e6, 1),
+        adjoint_gbs=round(ADJ_BYTES_PER_NODE * N / (adj_ms * 1e-3) / 1e9, 1),
+        adjoint_vs_forward=round(adj_ms / fwd_ms, 3),
+        gradient_forward_ms=round((t1 - t0) * 1e3, 3), gradient_backward_ms=round((t3 - t2) * 1e3, 3),
+        backward_vs_forward_end_to_end=round((t3 - t2) / (t1 - t0), 3),
+        loss=float(loss), grad_cs=float(g[-1]), grad_amp_linf=float(np.abs(g[:-1]).max()), status=status)
+    ch.close()
+    del ch, run
     torch.cuda.empty_cache()
     return res
 
@@ -166,6 +232,9 @@ def main():
     if args.copy_only:
         print(json.dumps({"copy_kernel_gbs": copy_bandwidth(device, reps=args.steps)}), flush=True)
         return
+    if args.only == "adjoint":
+        print(json.dumps(time_adjoint(device)), flush=True)
+        return
     if args.only:
         name, storage = args.only.split(":")
         r = time_channel(name, storage, args.steps, args.warmup, device)
@@ -179,6 +248,8 @@ def main():
     c3_steps = max(10, args.steps // 5)
     r3 = time_channel("c3", "f32", c3_steps, max(5, args.warmup // 5), device)
     r3h = time_channel("c3", "f16dev", c3_steps, max(5, args.warmup // 5), device)
+    log("bench: adjoint 256x64x64")
+    radj = time_adjoint(device)
     log("bench: copy bandwidth")
     copy_gbs = copy_bandwidth(device)
     cpu = None
@@ -216,6 +287,7 @@ def main():
                                 "f16dev_kernel_gbs": round(r3h["kernel_gbs"], 1),
                                 "f16dev_vs_f32": round(r3h["mlups"] / r3["mlups"], 3),
                                 "status": [r3["status"], r3h["status"]]},
+        "adjoint": radj,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

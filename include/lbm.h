@@ -226,23 +226,46 @@ lbm_status lbm_set_cs_smag(lbm_handle h, double cs_smag);
  *           statistics planes, see lbm_stats), or NULL when the step is not
  *           sampled;
  *  g_uin    (written, optional) dL/du_in(t_next), device float [3][ny][nz];
- *  grad     (accumulated, optional) device double [n_bins + 1]:
- *           grad[b] += dL/ds_b for the bins of the bound STG inputs (n_bins = 0
- *           with LBM_X_PERIODIC), grad[n_bins] += dL/dC_s (FP64, fixed-order
- *           sums: the result does not depend on scheduling).
+ *  u_in_next, fluct_next  (optional, both or neither) the inlet plane of the
+ *           step (u_in and a v' at t_next, device float [3][ny][nz], as
+ *           lbm_step_record keeps them); when NULL it is recomputed;
+ *  grad     (optional) device double [n_bins + 1].  Every step adds its
+ *           dL/ds_b (the bins of the bound STG inputs; n_bins = 0 with
+ *           LBM_X_PERIODIC) and dL/dC_s to accumulators in the handle; a call
+ *           with grad != NULL adds all that was accumulated since the last
+ *           such call, this step included, to grad[b] and grad[n_bins] and
+ *           clears the accumulators.  Pass it on the last step of a sweep.
+ *           FP64, fixed-order sums: the result does not depend on scheduling.
  * Chaining calls backwards from lam = eta = 0, with the states of the forward
  * run, gives the gradient of a loss of the accumulated statistics.  The wall
  * law's u_tau is differentiated at its root.  Uses the handle's configuration
  * (C_s, rates, STG tables) and statistics planes; the handle's own state is
- * neither read nor changed.  Overwrites the bound stg->u_in (and stg->fluct)
- * with the plane at t_next.  Errors: LBM_ERR_ARG (NULL or aliasing
- * buffers), LBM_ERR_SHAPE (alignment), LBM_ERR_STATE (LBM_X_INFLOW without
- * bound STG inputs, coef without statistics planes).  Asynchronous on the
- * handle's stream.
+ * neither read nor changed.  Without u_in_next, overwrites the bound
+ * stg->u_in (and stg->fluct) with the plane at t_next.  Errors: LBM_ERR_ARG (NULL or aliasing
+ * buffers), LBM_ERR_SHAPE (alignment, ny > 4096), LBM_ERR_STATE
+ * (LBM_X_INFLOW without bound STG inputs, coef without statistics planes).
+ * Asynchronous on the handle's stream.
  */
 lbm_status lbm_adjoint_step(lbm_handle h, const lbm_stg* stg, const void* s_n, const float* hist_n, double t_next,
                             const float* lam_next, const float* eta_next, float* lam_prev, float* eta_prev,
-                            const float* coef, float* g_uin, double* grad);
+                            const float* coef, float* g_uin, double* grad, const float* u_in_next,
+                            const float* fluct_next);
+
+/*
+ * Forward recompute for an adjoint sweep (Algorithm 1 steps, as lbm_step):
+ * nsteps steps from the state s_start (device, 256-byte aligned, time
+ * t_start) with outlet history hist_start, writing the state after step k
+ * (time t_start + k + 1) to f_out[k] and its history to hist_out[k], and the
+ * inlet plane that step k used (t = t_start + k + 1) to uin_out[k] and
+ * fluct_out[k].  f_out, hist_out, uin_out, fluct_out are host arrays of
+ * nsteps device pointers (buffers as for lbm_create / lbm_stg); uin_out and
+ * fluct_out may be NULL (planes not kept); hist_out is required with
+ * LBM_X_INFLOW.  Consecutive buffers must differ.  Statistics are not
+ * accumulated; the handle's own state is neither read nor changed.
+ */
+lbm_status lbm_step_record(lbm_handle h, const lbm_stg* stg, const void* s_start, const float* hist_start,
+                           double t_start, int32_t nsteps, void* const* f_out, float* const* hist_out,
+                           float* const* uin_out, float* const* fluct_out);
 
 /* Float brick field (an adjoint field lam) <-> float SoA [19][N], device buffers. */
 lbm_status lbm_field_export(lbm_handle h, const float* bricks, float* soa);

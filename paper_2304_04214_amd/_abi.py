@@ -17,7 +17,7 @@ EXPORTED = [
     "lbm_inflow_reichardt", "stg_inlet_fill", "lbm_step", "lbm_stream_only", "lbm_export_f32", "lbm_import_f32",
     "lbm_state_elems",
     "lbm_stats", "lbm_sync", "lbm_status_str", "lbm_kernel_timing", "lbm_copy_probe", "lbm_lattice_tables",
-    "lbm_set_cs_smag", "lbm_adjoint_step", "lbm_field_export", "lbm_field_import",
+    "lbm_set_cs_smag", "lbm_adjoint_step", "lbm_step_record", "lbm_field_export", "lbm_field_import",
 ]
 
 
@@ -72,7 +72,8 @@ def lib():
             "lbm_kernel_timing": [P, I32, P, P, P],
             "lbm_copy_probe": [P, P, I64, P],
             "lbm_set_cs_smag": [P, D],
-            "lbm_adjoint_step": [P, P, P, P, D, P, P, P, P, P, P, P],
+            "lbm_adjoint_step": [P, P, P, P, D, P, P, P, P, P, P, P, P, P],
+            "lbm_step_record": [P, P, P, P, D, I32, P, P, P, P],
             "lbm_field_export": [P, P, P],
             "lbm_field_import": [P, P, P],
         }

@@ -1,9 +1,9 @@
 """Gradients of plane-statistics losses by the library's discrete adjoint step.
 
 The forward run keeps the state every `segment` steps (default about
-sqrt(T)); the backward sweep restores each checkpoint, recomputes its segment
-with the library's step into a ring of state buffers, and runs
-lbm_adjoint_step backwards through it.  Every step of both sweeps runs in the
+sqrt(T)); the backward sweep recomputes each segment from its checkpoint into
+a ring of state buffers (lbm_step_record, which also keeps each step's inlet
+plane) and runs lbm_adjoint_step backwards through it.  Every step of both sweeps runs in the
 library's kernels; this module only orders the calls and holds the buffers.
 
     run = StatsGradient(ch, planes=[128], nsteps=400)
@@ -59,18 +59,23 @@ class StatsGradient:
         if self._ring is None:
             ch = self.ch
             f, h = ch.state()
-            self._ring = ([torch.empty_like(f) for _ in range(self.seg + 1)],
-                          [torch.empty_like(h) for _ in range(self.seg + 1)])
+            n = max(self.seg - 1, 1)
+            plane = (3, ch.ny, ch.nz)
+            self._ring = dict(f=[torch.empty_like(f) for _ in range(n)], h=[torch.empty_like(h) for _ in range(n)],
+                              u=[torch.empty(plane, dtype=torch.float32, device=ch.device) for _ in range(n)],
+                              fl=[torch.empty(plane, dtype=torch.float32, device=ch.device) for _ in range(n)])
             self._lam = [ch.new_field(), ch.new_field()]
             self._eta = [torch.zeros_like(h), torch.zeros_like(h)]
         return self._ring
 
     def backward(self, dmeans, time_kernel=False):
         """Gradient from dL/dmeans [n_planes, ny, 9]: returns float64 numpy [n_bins + 1]
-        (dL/ds_b..., dL/dC_s).  With time_kernel, also the summed adjoint-kernel time in ms."""
+        (dL/ds_b..., dL/dC_s).  With time_kernel, also the summed time of the adjoint steps in ms
+        (HIP events around each segment's adjoint steps)."""
         ch = self.ch
-        states, hists = self._buffers()
+        ring = self._buffers()
         ch.stats_detach()
+        open_ = ch.cfg.xbc == 1
         # each step adds one z-sum per (plane, y) to the accumulators; means divide by nz T
         coef = torch.as_tensor(np.asarray(dmeans, dtype=np.float64) / (ch.nz * self.T), dtype=torch.float32,
                                device=ch.device).contiguous()
@@ -80,25 +85,29 @@ class StatsGradient:
         for t in lam + eta:
             t.zero_()
         ev = []
+        t_last = self.t0 + 1  # the sweep's last adjoint step reduces the parameter gradient
         for f_k, h_k, t_k in reversed(self.ckpt):
             L = min(self.seg, self.t0 + self.T - t_k)
-            states[0].copy_(f_k)
-            hists[0].copy_(h_k)
-            for j in range(L - 1):  # recompute s_{t_k + j}, j < L
-                ch.point_state(states[j], states[j + 1], hists[j], hists[j + 1], t_k + j)
-                ch.step(1)
+            # recompute s_{t_k + j}, j = 1 .. L-1, and the inlet planes of those steps
+            if L > 1:
+                ch.step_record(f_k, h_k, t_k, ring["f"][:L - 1], ring["h"][:L - 1],
+                               ring["u"][:L - 1] if open_ else None, ring["fl"][:L - 1] if open_ else None)
+            states = [f_k] + ring["f"][:L - 1]
+            hists = [h_k] + ring["h"][:L - 1]
+            if time_kernel:
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                e0.record()
             for j in reversed(range(L)):
-                if time_kernel:
-                    e0 = torch.cuda.Event(enable_timing=True)
-                    e1 = torch.cuda.Event(enable_timing=True)
-                    e0.record()
+                kept = open_ and j < L - 1  # the plane of step j was kept by the recompute
                 ch.adjoint_step(states[j], hists[j], t_k + j + 1, lam[0], lam[1], eta[0], eta[1], coef=coef,
-                                grad=grad)
-                if time_kernel:
-                    e1.record()
-                    ev.append((e0, e1))
+                                grad=grad if t_k + j + 1 == t_last else None,
+                                u_in=ring["u"][j] if kept else None, fluct=ring["fl"][j] if kept else None)
                 lam.reverse()
                 eta.reverse()
+            if time_kernel:
+                e1.record()
+                ev.append((e0, e1))
         ch.point_state(ch.f[0], ch.f[1], ch.hist[0], ch.hist[1], self.t0)
         ch.set_state(self.f0, self.h0, self.t0)
         ch.sync()

@@ -242,15 +242,26 @@ class Channel:
         return bricks
 
     def adjoint_step(self, s_n, hist_n, t_next, lam_next, lam_prev, eta_next=None, eta_prev=None, coef=None,
-                     g_uin=None, grad=None):
-        """lam_prev = dL/ds_n (and eta_prev = dL/dhist_n) from lam_next = dL/ds_{n+1}; grad (device
-        float64 [n_bins + 1]) += (dL/ds_b..., dL/dC_s).  coef: [n_planes, ny, 9] statistics weights."""
+                     g_uin=None, grad=None, u_in=None, fluct=None):
+        """lam_prev = dL/ds_n (and eta_prev = dL/dhist_n) from lam_next = dL/ds_{n+1}.  The parameter
+        sensitivities accumulate in the library; grad (device float64 [n_bins + 1]), when given, receives
+        (dL/ds_b..., dL/dC_s) accumulated so far.  coef: [n_planes, ny, 9] statistics weights; u_in and
+        fluct: the step's inlet plane if kept by step_record (else recomputed)."""
         coef = None if coef is None else _dev(coef, torch.float32, self.device)
         st = A.lib().lbm_adjoint_step(self._h, self._stg_arg(), _ptr(s_n), _ptr(hist_n), float(t_next),
                                       _ptr(lam_next), _ptr(eta_next), _ptr(lam_prev), _ptr(eta_prev), _ptr(coef),
-                                      _ptr(g_uin), _ptr(grad))
+                                      _ptr(g_uin), _ptr(grad), _ptr(u_in), _ptr(fluct))
         A.check(st, "lbm_adjoint_step")
         self._keep_coef = coef
+
+    def step_record(self, s_start, hist_start, t_start, f_out, hist_out, uin_out=None, fluct_out=None):
+        """len(f_out) steps from (s_start, hist_start) at time t_start into the given buffers, keeping
+        each step's inlet plane in uin_out / fluct_out (lists of device tensors) when given."""
+        n = len(f_out)
+        arr = lambda ts: None if ts is None else (C.c_void_p * n)(*[t.data_ptr() for t in ts])
+        st = A.lib().lbm_step_record(self._h, self._stg_arg(), _ptr(s_start), _ptr(hist_start), float(t_start), n,
+                                     arr(f_out), arr(hist_out), arr(uin_out), arr(fluct_out))
+        A.check(st, "lbm_step_record")
 
     # ---- timing ----
     def kernel_timing(self, enable):

@@ -15,16 +15,16 @@
 //  * wall model: a first off-wall cell reads the velocity of the next row;
 //    its sensitivity goes back to that row through LDS (the block holds both);
 //  * convective outlet: the outlet node at x = nx-1 reads the pulled values of
-//    the node at nx-2.  The outlet plane runs first; it stores dL/dhist_n,
-//    and the nodes at nx-2 add U_c times it to their c_x < 0 values.
-// Elements of s_n that no node pulls (the x = 0 and x = nx-1 planes of an open
-// channel) get zero from a fill that runs before the scatter.
+//    the node at nx-2.  The thread of node (nx-2, y, z) does the outlet node
+//    (nx-1, y, z) first, stores dL/dhist_n and adds U_c times it to its own
+//    c_x < 0 values.
+// Elements of s_n that no node pulls (on the x = 0 and x = nx-1 planes of an
+// open channel) are set to zero by the thread of the node that holds them.
 //
 // The Newton solve for u_tau is differentiated through its converged root
 // (implicit function theorem), not through the truncated iteration.
 #include <hip/hip_runtime.h>
 
-#include <algorithm>
 #include <cmath>
 
 #include "internal.h"
@@ -148,29 +148,30 @@ __device__ __forceinline__ void inlet_adjoint(float rin, float ux, float uy, flo
   ubx += rb * rin * i1u;
 }
 
-// One thread per node; a block is 4 consecutive y rows of one (x, z-chunk),
-// entries first .. first + gridDim.x - 1 in memory order.
+// Whether this block scatters row y (block y-group gy, first row base).  The
+// block that scatters a row must hold every term of its adjoint: with the
+// wall model, row ny-2 receives the top wall row's sensitivity, so it belongs
+// to the top block even where ragged ny puts it in another group.
+__device__ __forceinline__ bool row_owned(const CollideArgs& a, int y, int gy, int base) {
+  if (a.wall_model && y == a.ny - 2) return base == a.ny - YROWS;
+  return y >= YROWS * gy;
+}
+
+// Per-block state of the adjoint kernel.
+struct AdjLds {
+  float u2[2][2][ZT];  // forward: (u_x, u_z) of rows 1 and ny-2
+  float g2[2][2][ZT];  // reverse: dL/d(u_x, u_z) of those rows, from the wall rows
+  double part[YROWS];
+};
+
+// The adjoint of one node (x, y, z) of the calling thread (see the file
+// comment).  gup: on the outlet plane (x = nx-1) receives U_c dL/dhist_n of the
+// c_x < 0 populations; on the plane x = nx-2 it is added to them.  csb: the
+// node's dL/dC_s is added.  Block-uniform x; contains __syncthreads.
 template <bool F16>
-__global__ __launch_bounds__(BLOCK) void adjoint_kernel(AdjointArgs A) {
-  __shared__ float lds_u2[2][2][ZT];  // forward: (u_x, u_z) of rows 1 and ny-2
-  __shared__ float lds_g2[2][2][ZT];  // reverse: dL/d(u_x, u_z) of those rows, from the wall rows
-  __shared__ double lds_cs[YROWS];
+__device__ __forceinline__ void node_adjoint(const AdjointArgs& A, AdjLds& L, int x, int y, int z, int lane,
+                                             int base, int zci, bool own, bool active, float gup[5], float& csb) {
   const CollideArgs& a = A.c;
-  const int e = A.first + (int)blockIdx.x;
-  int x, zci, gy;
-  block_coords(a, e, x, zci, gy);
-  const int lane = threadIdx.x & (ZT - 1);
-  const int w = uni(threadIdx.x >> 6);
-  const int base = min(YROWS * gy, a.ny - YROWS);
-  const int y = base + w;
-  // The block that scatters a row must hold every term of its adjoint: with
-  // the wall model, row ny-2 receives the top wall row's sensitivity, so it
-  // belongs to the top block even where ragged ny puts it in another group.
-  bool own = y >= YROWS * gy;
-  if (a.wall_model && y == a.ny - 2) own = base == a.ny - YROWS;
-  const int zraw = zci * ZT + lane;
-  const bool active = zraw < a.nz;
-  const int z = active ? zraw : a.nz - 1;  // inactive lanes compute a valid node and store nothing
   const bool mine = own && active;
   const Col col = make_col<F16>(a, z);
   const Geo g = make_geo(a, x, y);
@@ -215,12 +216,12 @@ __global__ __launch_bounds__(BLOCK) void adjoint_kernel(AdjointArgs A) {
   float wex = 0.f, wez = 0.f, witn = 0.f, wtw = 0.f, wut = 1.f, wdg = 1.f, wsg = 0.f;
   if (wblock) {
     if (nrow) {
-      lds_u2[wslot][0][lane] = jx * iw;
-      lds_u2[wslot][1][lane] = jz * iw;
+      L.u2[wslot][0][lane] = jx * iw;
+      L.u2[wslot][1][lane] = jz * iw;
     }
     __syncthreads();
     if (wrow) {
-      const float u2x = lds_u2[wslot][0][lane], u2z = lds_u2[wslot][1][lane];
+      const float u2x = L.u2[wslot][0][lane], u2z = L.u2[wslot][1][lane];
       const float tn2 = u2x * u2x + u2z * u2z;
       if (tn2 > 0.f) {
         witn = 1.f / sqrtf(tn2);
@@ -245,12 +246,7 @@ __global__ __launch_bounds__(BLOCK) void adjoint_kernel(AdjointArgs A) {
 
   // ---- forward recompute: collision quantities (as in collide()) ----
   float ml[Q];
-  {
-    float mf[Q];
-    moments(f, mf);
-#pragma unroll
-    for (int k = 0; k < Q; ++k) ml[k] = mf[k];  // forward moments, replaced by those of lambda below
-  }
+  moments(f, ml);
   const float ir = rcp_fast(rho);
   const float px = jx + 0.5f * Fx, py = jy + 0.5f * Fy, pz = jz + 0.5f * Fz;
   const float ux = px * ir, uy = py * ir, uz = pz * ir;
@@ -270,7 +266,6 @@ __global__ __launch_bounds__(BLOCK) void adjoint_kernel(AdjointArgs A) {
   const float tau = 0.5f * a.tau0 + 0.5f * rr;
   const float sv = rcp_fast(tau);
   const float hv = 1.f - 0.5f * sv;
-  const float uF = ux * Fx + uy * Fy + uz * Fz;
   const float F9 = 2.f * (2.f * ux * Fx - uy * Fy - uz * Fz);
   const float F11 = 2.f * (uy * Fy - uz * Fz);
   const float F13 = ux * Fy + uy * Fx, F14 = uy * Fz + uz * Fy, F15 = ux * Fz + uz * Fx;
@@ -278,24 +273,18 @@ __global__ __launch_bounds__(BLOCK) void adjoint_kernel(AdjointArgs A) {
   // ---- reverse: collision ----
   moments(lam, ml);  // (M lambda)_k; delta_k / D_k enters f*, so mu_k = (M lambda)_k / D_k
   float nu[Q];       // dL/dm (moment-space cotangent of the pre-collision populations)
-  float Fb1, Fb2, Fb4, Fb6, Fb8, Fb10, Fb12;
   nu[1] = -a.rs[1] * ml[1];
-  Fb1 = a.rf[1] * ml[1];
   nu[2] = -a.rs[2] * ml[2];
-  Fb2 = a.rf[2] * ml[2];
   nu[4] = -a.rs[4] * ml[4];
-  Fb4 = a.rf[4] * ml[4];
   nu[6] = -a.rs[6] * ml[6];
-  Fb6 = a.rf[6] * ml[6];
   nu[8] = -a.rs[8] * ml[8];
-  Fb8 = a.rf[8] * ml[8];
   nu[10] = -a.rs[10] * ml[10];
-  Fb10 = a.rf[10] * ml[10];
   nu[12] = -a.rs[12] * ml[12];
-  Fb12 = a.rf[12] * ml[12];
   nu[16] = -a.rs[16] * ml[16];
   nu[17] = -a.rs[17] * ml[17];
   nu[18] = -a.rs[18] * ml[18];
+  const float Fb1 = a.rf[1] * ml[1], Fb2 = a.rf[2] * ml[2], Fb4 = a.rf[4] * ml[4], Fb6 = a.rf[6] * ml[6];
+  const float Fb8 = a.rf[8] * ml[8], Fb10 = a.rf[10] * ml[10], Fb12 = a.rf[12] * ml[12];
   const float mu9 = ml[9] * (1.f / 36.f), mu11 = ml[11] * (1.f / 12.f);
   const float mu13 = 0.25f * ml[13], mu14 = 0.25f * ml[14], mu15 = 0.25f * ml[15];
   nu[9] = -sv * mu9;
@@ -311,7 +300,7 @@ __global__ __launch_bounds__(BLOCK) void adjoint_kernel(AdjointArgs A) {
   const float Xb = taub * 0.25f * rcp_fast(rr);
   const float Qhb = Xb * a.smag * ir;
   float rhob = -Xb * a.smag * Qh * ir * ir;
-  const float csb = Xb * Qh * ir * A.dsmag;
+  if (mine) csb += Xb * Qh * ir * A.dsmag;
   const float q2b = Qh > 0.f ? 0.5f * Qhb * rcp_fast(Qh) : 0.f;
   {
     const float pxxb = 2.f * q2b * pxx, pyyb = 2.f * q2b * pyy, pzzb = 2.f * q2b * pzz;
@@ -385,12 +374,12 @@ __global__ __launch_bounds__(BLOCK) void adjoint_kernel(AdjointArgs A) {
       u2zb = (ezb - wez * ed) * witn;
     }
     if (wrow) {
-      lds_g2[wslot][0][lane] = u2xb;
-      lds_g2[wslot][1][lane] = u2zb;
+      L.g2[wslot][0][lane] = u2xb;
+      L.g2[wslot][1][lane] = u2zb;
     }
     __syncthreads();
     if (nrow) {  // this row's pre-force velocity fed the wall row's base vector
-      const float gx = lds_g2[wslot][0][lane], gz = lds_g2[wslot][1][lane];
+      const float gx = L.g2[wslot][0][lane], gz = L.g2[wslot][1][lane];
       jxb += gx * iw;
       jzb += gz * iw;
       rhob -= (gx * jx + gz * jz) * iw * iw;
@@ -413,13 +402,16 @@ __global__ __launch_bounds__(BLOCK) void adjoint_kernel(AdjointArgs A) {
       const int hidx = (k * a.ny + y) * a.nz + z;
       const float v = (gb[i] + A.eta_next[hidx]) * a.inv_1pu;  // hist_{n+1} holds these populations
       if (mine) A.eta_prev[hidx] = v;
+      gup[k] = a.u_conv * v;
       gb[i] = 0.f;
     }
   }
-  if (inflow && x == a.nx - 2) {  // values read by the outlet node through its upstream term
+  if (inflow && x == a.nx - 2) {  // values the outlet node read through its upstream term
 #pragma unroll
-    for (int k = 0; k < 5; ++k) gb[OUT5[k]] += a.u_conv * A.eta_prev[(k * a.ny + y) * a.nz + z];
+    for (int k = 0; k < 5; ++k) gb[OUT5[k]] += gup[k];
   }
+  const Col cl = make_col<false>(a, z);
+  char* lp = reinterpret_cast<char*>(A.lam_prev);
   if (inlet) {
     const int pl = a.ny * a.nz, o = y * a.nz + z;
     const float uix = a.u_in[o], uiy = a.u_in[pl + o], uiz = a.u_in[2 * pl + o];
@@ -430,12 +422,26 @@ __global__ __launch_bounds__(BLOCK) void adjoint_kernel(AdjointArgs A) {
       A.g_uin[pl + o] = uby;
       A.g_uin[2 * pl + o] = ubz;
     }
+    // dL/ds_b: sum over the row of g_uin . (a v'), per wave (FP64, fixed order)
+    double v = mine ? (double)ubx * A.fluct[o] + (double)uby * A.fluct[pl + o] + (double)ubz * A.fluct[2 * pl + o]
+                    : 0.0;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, ZT);
+    if (lane == 0 && own) A.amp_part[y * a.zc + zci] += v;  // one writer per entry and step
+  }
+  // Populations of an open channel's end planes that no node pulls (c_x = -1
+  // at x = 0, c_x = +1 at x = nx-1) are zero; the only other writer of such an
+  // element is this thread's own bounce-back scatter below, which follows.
+  if (mine && (inlet || outlet)) {
+    const int cxz = inlet ? -1 : 1;
+#pragma unroll
+    for (int i = 0; i < Q; ++i)
+      if (CX[i] == cxz)
+        *reinterpret_cast<float*>(lp + (size_t)(rowpart(a, x, y) + (uint32_t)i * ZT) * 4u + cl.b0) = 0.f;
   }
 
   // ---- scatter to the addresses the pulls read ----
   if (mine) {
-    const Col cl = make_col<false>(a, z);
-    char* base_l = reinterpret_cast<char*>(A.lam_prev);
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
       const int cx = CX[i], cy = CY[i], cz = CZ[i];
@@ -450,104 +456,119 @@ __global__ __launch_bounds__(BLOCK) void adjoint_kernel(AdjointArgs A) {
         cs = bb ? cl.b0 : cs;
       }
       if (pull_ok(a, g, i))
-        *reinterpret_cast<float*>(base_l + (size_t)(rowpart(a, xsrc, ysrc) + (uint32_t)plane * ZT) * 4u + cs) = gb[i];
+        *reinterpret_cast<float*>(lp + (size_t)(rowpart(a, xsrc, ysrc) + (uint32_t)plane * ZT) * 4u + cs) = gb[i];
     }
   }
+}
 
-  // ---- dL/dC_s of the block (fixed-order FP64 reduction) ----
-  double c = mine ? (double)csb : 0.0;
+// One thread per node; a block is 4 consecutive y rows of one (x, z-chunk).
+// With an open channel the grid starts with the blocks of the planes x = 0
+// and x = nx-2 (dispatched first, so their longer work overlaps the bulk):
+// each block at nx-2 first does the outlet node of its (y, z) (x = nx-1),
+// whose dL/dhist feeds its own c_x < 0 values.  The bulk blocks follow in
+// memory order (x = 1 .. nx-3; every block of a periodic channel).
+template <bool F16>
+__global__ __launch_bounds__(BLOCK) void adjoint_kernel(AdjointArgs A) {
+  __shared__ AdjLds L;
+  const CollideArgs& a = A.c;
+  const int per_x = a.zc * a.yg;
+  const int b = (int)blockIdx.x;
+  const bool open = a.xbc == LBM_X_INFLOW;
+  int e = b;
+  if (open) e = b < per_x ? b : (b < 2 * per_x ? (a.nx - 3) * per_x + b : b - per_x);
+  int x0, zci, gy;
+  block_coords(a, e, x0, zci, gy);
+  const int lane = threadIdx.x & (ZT - 1);
+  const int w = uni(threadIdx.x >> 6);
+  const int base = min(YROWS * gy, a.ny - YROWS);
+  const int y = base + w;
+  const int zraw = zci * ZT + lane;
+  const bool active = zraw < a.nz;
+  const int z = active ? zraw : a.nz - 1;  // inactive lanes compute a valid node and store nothing
+  const bool own = row_owned(a, y, gy, base);
+  float gup[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
+  float csb = 0.f;
+  if (open && x0 == a.nx - 2) {  // block-uniform
+    node_adjoint<F16>(A, L, a.nx - 1, y, z, lane, base, zci, own, active, gup, csb);
+    __syncthreads();  // LDS reuse by the second node
+  }
+  node_adjoint<F16>(A, L, x0, y, z, lane, base, zci, own, active, gup, csb);
+  // dL/dC_s of the block (fixed-order FP64 reduction)
+  double c = (double)csb;
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) c += __shfl_xor(c, off, ZT);
-  if (lane == 0) lds_cs[w] = c;
+  if (lane == 0) L.part[w] = c;
   __syncthreads();
-  if (threadIdx.x == 0) A.cs_part[e] = ((lds_cs[0] + lds_cs[1]) + lds_cs[2]) + lds_cs[3];
+  if (threadIdx.x == 0) A.cs_part[e] += ((L.part[0] + L.part[1]) + L.part[2]) + L.part[3];  // one writer per step
 }
 
-// Zero fill of float elements [begin, end).
-__global__ void zero_kernel(float* p, int64_t n) {
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += stride) p[k] = 0.f;
-}
-
-// Row sums over z and components of g_uin . fluct (FP64, fixed order).
-__global__ __launch_bounds__(256) void amp_rows_kernel(const float* g_uin, const float* fluct, double* rowsum, int ny,
-                                                       int nz) {
+// grad[n_bins] += the accumulated per-block dL/dC_s (fixed-order tree), and
+// grad[b] += the accumulated inlet-row partial sums of bin b (rows, then
+// z-chunks, in order).  The accumulators are cleared for the next sweep.
+__global__ __launch_bounds__(256) void adjoint_finalize_kernel(double* cs_part, int nparts, double* amp_part, int zc,
+                                                               const int* bin_of_y, int ny, int n_bins,
+                                                               double* grad) {
   __shared__ double part[256];
-  const int y = blockIdx.x;
+  __shared__ double rows[LBM_ADJ_MAX_NY];
+  __shared__ int bins[LBM_ADJ_MAX_NY];
   double s = 0.0;
-  for (int k = threadIdx.x; k < 3 * nz; k += 256) {
-    const int c = k / nz, z = k - c * nz;
-    const size_t o = ((size_t)c * ny + y) * nz + z;
-    s += (double)g_uin[o] * (double)fluct[o];
+  for (int k = threadIdx.x; k < nparts; k += 256) {
+    s += cs_part[k];
+    cs_part[k] = 0.0;
   }
   part[threadIdx.x] = s;
-  __syncthreads();
-  for (int h = 128; h > 0; h >>= 1) {
-    if ((int)threadIdx.x < h) part[threadIdx.x] += part[threadIdx.x + h];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) rowsum[y] = part[0];
-}
-
-// grad[b] += sum of the bin's row sums (rows in order); grad[n_bins] += sum of
-// the per-block dL/dC_s (fixed-order tree).
-__global__ __launch_bounds__(256) void adjoint_finalize_kernel(const double* cs_part, int nblocks,
-                                                               const double* rowsum, const int* bin_of_y, int ny,
-                                                               int n_bins, double* grad) {
-  __shared__ double part[256];
-  double s = 0.0;
-  for (int k = threadIdx.x; k < nblocks; k += 256) s += cs_part[k];
-  part[threadIdx.x] = s;
-  __syncthreads();
-  for (int h = 128; h > 0; h >>= 1) {
-    if ((int)threadIdx.x < h) part[threadIdx.x] += part[threadIdx.x + h];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) {
-    grad[n_bins] += part[0];
-    if (rowsum)
-      for (int y = 0; y < ny; ++y) {
-        int b = bin_of_y[y];
-        b = b < 0 ? 0 : (b >= n_bins ? n_bins - 1 : b);  // clamped like the STG binding
-        grad[b] += rowsum[y];
+  if (amp_part)
+    for (int y = threadIdx.x; y < ny; y += 256) {
+      double r = 0.0;
+      for (int c = 0; c < zc; ++c) {
+        r += amp_part[y * zc + c];
+        amp_part[y * zc + c] = 0.0;
       }
+      rows[y] = r;
+      const int by = bin_of_y[y];
+      bins[y] = by < 0 ? 0 : (by >= n_bins ? n_bins - 1 : by);  // clamped like the STG binding
+    }
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h) part[threadIdx.x] += part[threadIdx.x + h];
+    __syncthreads();
   }
+  if (threadIdx.x == 0) grad[n_bins] += part[0];
+  if (amp_part)
+    for (int bn = threadIdx.x; bn < n_bins; bn += 256) {
+      double acc = 0.0;
+      for (int y = 0; y < ny; ++y)
+        if (bins[y] == bn) acc += rows[y];
+      grad[bn] += acc;
+    }
 }
 
 }  // namespace
 
-// Edge-plane fill (open channel), the outlet plane, then the rest.
-hipError_t launch_adjoint(lbm_ctx* h, const AdjointArgs& args, int storage_f16) {
-  const lbm_config& c = h->cfg;
-  const int per_x = h->zc * h->yg;
-  AdjointArgs A = args;
-  auto run = [&](int first, int count) {
-    A.first = first;
-    if (count <= 0) return;
-    if (storage_f16)
-      adjoint_kernel<true><<<count, BLOCK, 0, h->stream>>>(A);
-    else
-      adjoint_kernel<false><<<count, BLOCK, 0, h->stream>>>(A);
-  };
-  if (c.xbc == LBM_X_INFLOW) {
-    const int64_t plane = (int64_t)h->zc * c.ny * BRICK;  // elements of one x plane (zc * ny bricks)
-    zero_kernel<<<(unsigned)std::min<int64_t>((plane + 255) / 256, 4096), 256, 0, h->stream>>>(A.lam_prev, plane);
-    zero_kernel<<<(unsigned)std::min<int64_t>((plane + 255) / 256, 4096), 256, 0, h->stream>>>(
-        A.lam_prev + (int64_t)(c.nx - 1) * plane, plane);
-    run((c.nx - 1) * per_x, per_x);
-    run(0, (c.nx - 1) * per_x);
-  } else {
-    run(0, h->nblocks);
-  }
+// Block entries whose partial sums the accumulators hold: x = 0 .. nx-2 of
+// an open channel (the plane nx-2 includes the outlet plane), all blocks of a
+// periodic one.
+int adjoint_blocks(const lbm_ctx* h) {
+  return h->cfg.xbc == LBM_X_INFLOW ? (h->cfg.nx - 1) * h->zc * h->yg : h->nblocks;
+}
+
+// One launch over all block entries of adjoint_blocks(); the inlet plane at
+// t_next, unless given, is computed first.
+hipError_t launch_adjoint(lbm_ctx* h, const AdjointArgs& args, int storage_f16, double t_next, bool fill_inlet,
+                          float* u_in, float* fluct) {
+  hipError_t e;
+  if (fill_inlet && (e = launch_stg_fill(h, t_next, h->stream, fluct, u_in)) != hipSuccess) return e;
+  if (storage_f16)
+    adjoint_kernel<true><<<adjoint_blocks(h), BLOCK, 0, h->stream>>>(args);
+  else
+    adjoint_kernel<false><<<adjoint_blocks(h), BLOCK, 0, h->stream>>>(args);
   return hipGetLastError();
 }
 
-hipError_t launch_adjoint_reduce(lbm_ctx* h, const float* g_uin, const float* fluct, double* grad) {
-  const int ny = h->cfg.ny, nz = h->cfg.nz;
-  const bool bins = g_uin && fluct && h->stg_bound;
-  if (bins) amp_rows_kernel<<<ny, 256, 0, h->stream>>>(g_uin, fluct, h->d_rowsum, ny, nz);
-  adjoint_finalize_kernel<<<1, 256, 0, h->stream>>>(h->d_cs_part, h->nblocks, bins ? h->d_rowsum : nullptr,
-                                                    bins ? h->stg.bin_of_y : nullptr, ny,
+hipError_t launch_adjoint_reduce(lbm_ctx* h, double* grad) {
+  const bool bins = h->cfg.xbc == LBM_X_INFLOW && h->stg_bound;
+  adjoint_finalize_kernel<<<1, 256, 0, h->stream>>>(h->d_cs_part, adjoint_blocks(h), bins ? h->d_amp_part : nullptr,
+                                                    h->zc, bins ? h->stg.bin_of_y : nullptr, h->cfg.ny,
                                                     bins ? h->stg.n_bins : 0, grad);
   return hipGetLastError();
 }

@@ -244,7 +244,7 @@ lbm_status lbm_destroy(lbm_handle h) {
   if (h->d_blist_bnd) (void)hipFree(h->d_blist_bnd);
   if (h->d_err) (void)hipFree(h->d_err);
   if (h->d_cs_part) (void)hipFree(h->d_cs_part);
-  if (h->d_rowsum) (void)hipFree(h->d_rowsum);
+  if (h->d_amp_part) (void)hipFree(h->d_amp_part);
   if (h->d_fluct) (void)hipFree(h->d_fluct);
   if (h->d_guin) (void)hipFree(h->d_guin);
   for (hipEvent_t e : h->ev) (void)hipEventDestroy(e);
@@ -435,13 +435,49 @@ lbm_status lbm_set_cs_smag(lbm_handle h, double cs_smag) {
   return LBM_OK;
 }
 
+lbm_status lbm_step_record(lbm_handle h, const lbm_stg* stg, const void* s_start, const float* hist_start,
+                           double t_start, int32_t nsteps, void* const* f_out, float* const* hist_out,
+                           float* const* uin_out, float* const* fluct_out) {
+  if (!h || !s_start || nsteps < 0 || (nsteps > 0 && !f_out)) return LBM_ERR_ARG;
+  const bool inflow = h->cfg.xbc == LBM_X_INFLOW;
+  if (inflow && (!hist_start || (nsteps > 0 && !hist_out))) return LBM_ERR_ARG;
+  if (!aligned256(s_start)) return LBM_ERR_SHAPE;
+  for (int32_t k = 0; k < nsteps; ++k) {
+    const void* src = k == 0 ? s_start : f_out[k - 1];
+    if (!f_out[k] || f_out[k] == src) return LBM_ERR_ARG;
+    if (!aligned256(f_out[k])) return LBM_ERR_SHAPE;
+    if (inflow) {
+      const float* hsrc = k == 0 ? hist_start : hist_out[k - 1];
+      if (!hist_out[k] || hist_out[k] == hsrc) return LBM_ERR_ARG;
+      if (uin_out && !uin_out[k]) return LBM_ERR_ARG;
+    }
+  }
+  if (stg) {
+    lbm_status st = bind_stg(h, stg);
+    if (st != LBM_OK) return st;
+  }
+  if (inflow && !h->stg_bound) return LBM_ERR_STATE;
+  for (int32_t k = 0; k < nsteps; ++k) {
+    const void* src = k == 0 ? s_start : f_out[k - 1];
+    float* uin = uin_out ? uin_out[k] : h->stg.u_in;
+    float* fl = fluct_out ? fluct_out[k] : nullptr;
+    if (inflow) HIPCHK(lbm::launch_stg_fill(h, t_start + k + 1, h->stream, fl, uin));
+    const float* hsrc = inflow ? (k == 0 ? hist_start : hist_out[k - 1]) : nullptr;
+    HIPCHK(lbm::launch_step_explicit(h, src, f_out[k], hsrc, inflow ? hist_out[k] : nullptr, inflow ? uin : nullptr,
+                                     h->stream));
+  }
+  return LBM_OK;
+}
+
 lbm_status lbm_adjoint_step(lbm_handle h, const lbm_stg* stg, const void* s_n, const float* hist_n, double t_next,
                             const float* lam_next, const float* eta_next, float* lam_prev, float* eta_prev,
-                            const float* coef, float* g_uin, double* grad) {
+                            const float* coef, float* g_uin, double* grad, const float* u_in_next,
+                            const float* fluct_next) {
   if (!h || !s_n || !lam_next || !lam_prev || lam_next == lam_prev) return LBM_ERR_ARG;
   if (!aligned256(s_n) || !aligned256(lam_next) || !aligned256(lam_prev)) return LBM_ERR_SHAPE;
   const bool inflow = h->cfg.xbc == LBM_X_INFLOW;
   if (inflow && (!hist_n || !eta_next || !eta_prev || eta_next == eta_prev)) return LBM_ERR_ARG;
+  if (!u_in_next != !fluct_next) return LBM_ERR_ARG;  // the inlet plane is given whole or recomputed
   if (stg) {
     lbm_status st = bind_stg(h, stg);
     if (st != LBM_OK) return st;
@@ -449,8 +485,15 @@ lbm_status lbm_adjoint_step(lbm_handle h, const lbm_stg* stg, const void* s_n, c
   if (inflow && !h->stg_bound) return LBM_ERR_STATE;
   if (coef && h->n_planes < 1) return LBM_ERR_STATE;
   const size_t plane = (size_t)3 * h->cfg.ny * h->cfg.nz;
-  if (!h->d_cs_part) HIPCHK(hipMalloc(&h->d_cs_part, sizeof(double) * h->nblocks));
-  if (!h->d_rowsum) HIPCHK(hipMalloc(&h->d_rowsum, sizeof(double) * h->cfg.ny));
+  if (h->cfg.ny > LBM_ADJ_MAX_NY) return LBM_ERR_SHAPE;
+  if (!h->d_cs_part) {  // accumulators start at zero; each reduction clears them
+    HIPCHK(hipMalloc(&h->d_cs_part, sizeof(double) * h->nblocks));
+    HIPCHK(hipMemset(h->d_cs_part, 0, sizeof(double) * h->nblocks));
+  }
+  if (!h->d_amp_part) {
+    HIPCHK(hipMalloc(&h->d_amp_part, sizeof(double) * h->cfg.ny * h->zc));
+    HIPCHK(hipMemset(h->d_amp_part, 0, sizeof(double) * h->cfg.ny * h->zc));
+  }
   if (inflow && !h->stg.fluct && !h->d_fluct) HIPCHK(hipMalloc(&h->d_fluct, sizeof(float) * plane));
   if (inflow && !g_uin && !h->d_guin) HIPCHK(hipMalloc(&h->d_guin, sizeof(float) * plane));
   lbm::AdjointArgs A;
@@ -461,7 +504,7 @@ lbm_status lbm_adjoint_step(lbm_handle h, const lbm_stg* stg, const void* s_n, c
   A.c.hist_out = nullptr;
   A.c.stats = nullptr;
   A.c.stats_on = 0;
-  A.c.u_in = inflow ? h->stg.u_in : nullptr;
+  A.c.u_in = inflow ? (u_in_next ? u_in_next : h->stg.u_in) : nullptr;
   A.lam_next = lam_next;
   A.lam_prev = lam_prev;
   A.eta_next = inflow ? eta_next : nullptr;
@@ -469,15 +512,12 @@ lbm_status lbm_adjoint_step(lbm_handle h, const lbm_stg* stg, const void* s_n, c
   A.coef = coef;
   A.g_uin = inflow ? (g_uin ? g_uin : h->d_guin) : nullptr;
   A.cs_part = h->d_cs_part;
+  A.amp_part = h->d_amp_part;
   A.dsmag = (float)(36.0 * std::sqrt(2.0) * h->cfg.cs_smag);  // d(18 sqrt(2) C_s^2)/dC_s
-  A.first = 0;
-  float* fluct = nullptr;
-  if (inflow) {
-    fluct = h->stg.fluct ? h->stg.fluct : h->d_fluct;
-    HIPCHK(lbm::launch_stg_fill(h, t_next, h->stream, fluct));
-  }
-  HIPCHK(lbm::launch_adjoint(h, A, h->cfg.storage == LBM_STORE_F16DEV));
-  if (grad) HIPCHK(lbm::launch_adjoint_reduce(h, inflow ? A.g_uin : nullptr, fluct, grad));
+  float* fluct = inflow ? (h->stg.fluct ? h->stg.fluct : h->d_fluct) : nullptr;
+  A.fluct = fluct_next ? fluct_next : fluct;
+  HIPCHK(lbm::launch_adjoint(h, A, h->cfg.storage == LBM_STORE_F16DEV, t_next, inflow && !u_in_next, nullptr, fluct));
+  if (grad) HIPCHK(lbm::launch_adjoint_reduce(h, grad));
   return LBM_OK;
 }
 

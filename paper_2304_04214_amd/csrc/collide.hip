@@ -497,6 +497,38 @@ hipError_t launch_boundary(lbm_ctx* h, int src, int dst, hipStream_t stream) {
   return hipGetLastError();
 }
 
+// One step between caller buffers (statistics off), on one stream: the
+// boundary and interior block lists with FP16 storage, the single list with FP32.
+hipError_t launch_step_explicit(lbm_ctx* h, const void* src, void* dst, const float* hist_in, float* hist_out,
+                                const float* u_in, hipStream_t stream) {
+  CollideArgs a;
+  fill_args(h, a, h->cur, h->cur);
+  a.src = src;
+  a.dst = dst;
+  a.hist_in = hist_in;
+  a.hist_out = hist_out;
+  a.u_in = u_in;
+  a.stats_on = 0;
+  const bool f16 = h->cfg.storage == LBM_STORE_F16DEV;
+  if (h->n_bnd > 0) {
+    if (f16)
+      collide_general_kernel<true><<<h->n_bnd, BLOCK, 0, stream>>>(a, h->d_blist_bnd);
+    else
+      collide_general_kernel<false><<<h->n_bnd, BLOCK, 0, stream>>>(a, h->d_blist_bnd);
+  }
+  if (h->n_int > 0) {
+    if (f16 && a.has_g)
+      collide_interior_kernel<true, true><<<h->n_int, BLOCK, 0, stream>>>(a, h->d_blist_int);
+    else if (f16)
+      collide_interior_kernel<true, false><<<h->n_int, BLOCK, 0, stream>>>(a, h->d_blist_int);
+    else if (a.has_g)
+      collide_interior_kernel<false, true><<<h->n_int, BLOCK, 0, stream>>>(a, h->d_blist_int);
+    else
+      collide_interior_kernel<false, false><<<h->n_int, BLOCK, 0, stream>>>(a, h->d_blist_int);
+  }
+  return hipGetLastError();
+}
+
 hipError_t launch_interior(lbm_ctx* h, int src, int dst, hipStream_t stream) {
   if (h->n_int == 0) return hipSuccess;
   CollideArgs a;

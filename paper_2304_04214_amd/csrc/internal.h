@@ -18,6 +18,8 @@ constexpr int ERRBIT_NONFINITE = 2;
 constexpr int ZT = 64;     // z-lanes per wave (one wave = one (x, y) row segment)
 constexpr int YROWS = 4;   // rows (waves) per collide block
 constexpr int BLOCK = ZT * YROWS;
+// Largest ny the adjoint supports (its bin reduction stages rows in LDS).
+#define LBM_ADJ_MAX_NY 4096
 
 // Arguments of the fused collide-stream kernel (passed by value).
 struct CollideArgs {
@@ -49,9 +51,10 @@ struct AdjointArgs {
   float* eta_prev;        // dL/dhist_n [5][ny][nz]
   const float* coef;      // [n_planes][ny][9] statistics weights, or null
   float* g_uin;           // dL/du_in [3][ny][nz]
-  double* cs_part;        // [nblocks] per-block dL/dC_s
+  const float* fluct;     // a v' of the inlet plane [3][ny][nz]
+  double* cs_part;        // [blocks] per-block dL/dC_s
+  double* amp_part;       // [ny][zc] per inlet-row-chunk sum of g_uin . fluct
   float dsmag;            // d(18 sqrt(2) C_s^2)/dC_s
-  int first;              // block entry of blockIdx.x = 0
 };
 
 struct StgTables {
@@ -98,8 +101,8 @@ struct lbm_ctx {
   lbm_stg stg{};
   lbm::StgTables tab;
   // adjoint scratch (allocated on the first adjoint step)
-  double* d_cs_part = nullptr;  // [nblocks]
-  double* d_rowsum = nullptr;   // [ny]
+  double* d_cs_part = nullptr;  // [nblocks] dL/dC_s per block, accumulated over adjoint steps
+  double* d_amp_part = nullptr; // [ny][zc] dL/ds_b partials per inlet row chunk, accumulated
   float* d_fluct = nullptr;     // [3][ny][nz], when the bound STG inputs have no fluct buffer
   float* d_guin = nullptr;      // [3][ny][nz], when the caller passes no g_uin
   int timing = 0;
@@ -123,10 +126,13 @@ void fill_args(lbm_ctx* h, CollideArgs& a, int src, int dst);
 hipError_t launch_field_export(lbm_ctx* h, const float* bricks, float* soa);
 hipError_t launch_field_import(lbm_ctx* h, const float* soa, float* bricks);
 // adjoint.hip
-hipError_t launch_adjoint(lbm_ctx* h, const AdjointArgs& args, int storage_f16);
-hipError_t launch_adjoint_reduce(lbm_ctx* h, const float* g_uin, const float* fluct, double* grad);
+hipError_t launch_adjoint(lbm_ctx* h, const AdjointArgs& args, int storage_f16, double t_next, bool fill_inlet,
+                          float* u_in, float* fluct);
+hipError_t launch_step_explicit(lbm_ctx* h, const void* src, void* dst, const float* hist_in, float* hist_out,
+                                const float* u_in, hipStream_t stream);
+hipError_t launch_adjoint_reduce(lbm_ctx* h, double* grad);
 // stg.hip
 hipError_t launch_stg_bind(lbm_ctx* h, const lbm_stg* s);
-hipError_t launch_stg_fill(lbm_ctx* h, double t, hipStream_t stream, float* fluct = nullptr);
+hipError_t launch_stg_fill(lbm_ctx* h, double t, hipStream_t stream, float* fluct = nullptr, float* u_in = nullptr);
 hipError_t launch_inflow_reichardt(lbm_ctx* h, double u_tau, double* u_rans);
 }  // namespace lbm

@@ -179,12 +179,14 @@ hipError_t launch_stg_bind(lbm_ctx* h, const lbm_stg* s) {
   return hipGetLastError();
 }
 
-// fluct, when given, replaces the bound output of the fluctuation a v'.
-hipError_t launch_stg_fill(lbm_ctx* h, double time, hipStream_t stream, float* fluct) {
+// fluct and u_in, when given, replace the bound outputs (the fluctuation a v'
+// and the inlet velocity plane).
+hipError_t launch_stg_fill(lbm_ctx* h, double time, hipStream_t stream, float* fluct, float* u_in) {
   const int ny = h->cfg.ny, nz = h->cfg.nz;
   dim3 grid((nz + 63) / 64, ny);
   lbm_stg s = h->stg;
   if (fluct) s.fluct = fluct;
+  if (u_in) s.u_in = u_in;
   stg_fill_kernel<<<grid, 256, 0, stream>>>(s, h->tab, ny, nz, time, h->d_err);
   return hipGetLastError();
 }

@@ -179,3 +179,75 @@ def loss_grad(m, U_t, R12_t):
     d[..., 1] = -db * U
     d[..., 6] = db
     return d
+
+
+@pytest.mark.parametrize("storage", ["f32", "f16dev"])
+def test_step_record_matches_step(storage):
+    """The recompute entry point reproduces lbm_step bit for bit (same kernels,
+    caller buffers) and keeps the inlet plane of every step."""
+    case = Case(8, 8, 70, ywall="slip", xbc="inflow", wall_model=True, storage=storage, g=(2e-6, 0.0, 0.0))
+    ch = case.ch
+    f0, h0 = [t.clone() for t in ch.state()]
+    t0 = ch.time
+    n = 3
+    ring_f = [torch.empty_like(f0) for _ in range(n)]
+    ring_h = [torch.empty_like(h0) for _ in range(n)]
+    ring_u = [torch.empty((3, 8, 70), dtype=torch.float32, device="cuda") for _ in range(n)]
+    ring_fl = [torch.empty((3, 8, 70), dtype=torch.float32, device="cuda") for _ in range(n)]
+    ch.step_record(f0, h0, t0, ring_f, ring_h, ring_u, ring_fl)
+    valid = torch.ones_like(f0, dtype=torch.bool)  # bricks (x, zc, y, i, z%64): padding nodes z >= nz are unwritten
+    valid[:, -1, :, :, 70 - 64:] = False
+    for k in range(n):
+        ch.step(1)
+        f, h = ch.state()
+        assert torch.equal(f[valid], ring_f[k][valid]), k
+        assert torch.equal(h, ring_h[k]), k
+        assert torch.equal(ch.u_in, ring_u[k]), k
+        assert torch.equal(ch.fluct, ring_fl[k]), k
+    ch.sync()
+
+
+def test_gradient_matches_fp64_finite_differences():
+    """GPU adjoint gradient of the mean-profile loss against central differences
+    (h = 1e-4) of the FP64 oracle's forward run, on the 64 x 32 x 32 channel of the
+    oracle configuration over 30 steps with the loss at x = 8: 7 amplitude bins and C_s.
+    Bound 1e-4 relative to the largest FD component (the gradient target)."""
+    nx, ny, nz, T = 64, 32, 32, 30
+    case = Case(nx, ny, nz, ywall="slip", xbc="inflow", wall_model=True, tau0=0.52, n_modes=100, seed=1)
+    planes = [8]
+    f0 = storage_round(case.f_or, "f32")
+    h0 = np.asarray(case.hist_or, dtype=np.float32).astype(np.float64)
+    case.ch.load_populations(torch.as_tensor(f0, dtype=torch.float32))
+    case.ch.state()[1].copy_(torch.as_tensor(h0, dtype=torch.float32))
+    U_t = case.U_or[0] * 1.02
+    R12_t = case.R[1]
+    stg = case.stg_or
+
+    def loss_of(amp, cs):
+        cfg = O.make_cfg(nx, ny, nz, ywall=2, xbc=1, wall_model=1, tau0=0.52, cs_smag=cs)
+        s2 = O.StgInputs(stg.q, stg.sigma, stg.kmag, stg.d, stg.phi, stg.omega, stg.u_rans, stg.R, amp, stg.bin_of_y)
+        acc = np.zeros((1, ny, 9))
+        st, _, _ = O.run(cfg, f0, h0, 0.0, T, stg=s2, planes=planes, acc=acc)
+        assert st == O.OK
+        m = acc / (nz * T)
+        U, V, UV = m[0, :, 0], m[0, :, 1], m[0, :, 6]
+        return ((U - U_t) ** 2).sum() / (U_t ** 2).sum() + ((UV - U * V - R12_t) ** 2).sum() / (R12_t ** 2).sum()
+
+    run = StatsGradient(case.ch, planes, T, segment=6)
+    means = run.forward()
+    g = run.backward(loss_grad(means, U_t, R12_t))
+    bins = [1, 5, 10, 15, 21, 26, 30]
+    h = 1e-4
+    amp0 = stg.amp_bin.copy()
+    fd = []
+    for b in bins:
+        e = np.zeros_like(amp0)
+        e[b] = h
+        fd.append((loss_of(amp0 + e, 0.1) - loss_of(amp0 - e, 0.1)) / (2 * h))
+    fd.append((loss_of(amp0, 0.1 + h) - loss_of(amp0, 0.1 - h)) / (2 * h))
+    fd = np.array(fd)
+    ad = np.append(g[bins], g[-1])
+    err = np.abs(ad - fd).max() / np.abs(fd).max()
+    print("FD", fd, "\nadjoint", ad, "\nrel err %.2e" % err, flush=True)
+    assert np.abs(fd).max() > 0
+    assert err < 1e-4

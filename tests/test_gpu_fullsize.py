@@ -1,0 +1,118 @@
+"""Parity at the benchmark's full lattice sizes, in its launch configuration (GPU tests).
+
+* Forward: the Re_tau = 1000 workload 768 x 64 x 192 (FP32 and FP16-deviation
+  storage) and the Re_tau = 5200 workload 1536 x 128 x 384 (FP16-deviation
+  storage), with the benchmark's four statistics planes attached, one step
+  from the oracle's seeded initial state (imported, rounded to the storage
+  type), compared with the FP64 oracle on sampled nodes: every boundary class
+  (inlet, outlet and their neighbours, wall rows and the first off-wall rows,
+  z tile edges, statistics planes) and random interior nodes.
+  Tolerances as for the small cases: FP32 1e-5, FP16 deviations 2e-4
+  relative L-inf over the sample.
+* Adjoint: one adjoint step on the whole 256 x 64 x 64 lattice against the
+  oracle's adjoint (tolerances of tests/test_gpu_adjoint.py).
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from paper_2304_04214_amd import synthetic as S
+from paper_2304_04214_amd.channel import Channel
+from parity_cases import rel_linf
+from test_gpu_adjoint import TOL_FIELD, TOL_PARAM, storage_round
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+def workload(name, storage, full_pert=True):
+    """Oracle and HIP sides of a benchmark workload from the same raw synthetic inputs."""
+    w = S.WORKLOADS[name]
+    nx, ny, nz = w["nx"], w["ny"], w["nz"]
+    k = int(name[1])
+    cfg = O.make_cfg(nx, ny, nz, ywall=2, xbc=1, wall_model=1, tau0=w["tau0"], cs_smag=S.CS_SMAG, u_conv=S.U_C)
+    U = O.reichardt_inflow(cfg, w["u_tau"])
+    mt = S.mode_table(w["n_modes"], ny / 2, seed_offset=k)
+    R = S.reynolds_stress(ny, w["u_tau"])
+    ab, boy = S.amp_bins(ny)
+    stg = O.StgInputs(mt["q"], mt["sigma"], mt["kmag"], mt["d"], mt["phi"], mt["omega"], U, R, ab, boy)
+    du, dp = S.perturbations(nx, ny, nz, seed_offset=k, dtype=np.float32) if full_pert else (None, None)
+    if du is None:  # velocity perturbation only (memory): streaming still mixes different equilibria
+        du = S.rng(1000 + k).uniform(-1.0, 1.0, (3, nx, ny, nz)).astype(np.float32)
+    f, hist = O.init(cfg, U[:, None, :, None] + 1e-3 * du, pert=dp, eps=0.05)
+    del du, dp
+    f = storage_round(f, storage)
+    hist = hist.astype(np.float32).astype(np.float64)
+    ch = Channel(nx, ny, nz, tau0=w["tau0"], storage=storage, ywall="slip", xbc="inflow", wall_model=True,
+                 cs_smag=S.CS_SMAG, u_conv=S.U_C)
+    ch.set_stg(mt, ch.inflow_reichardt(w["u_tau"]), R, ab, boy)
+    ch.load_populations(torch.as_tensor(f.astype(np.float32)))
+    ch.state()[1].copy_(torch.as_tensor(hist, dtype=torch.float32))
+    delta = ny // 2
+    planes = [p for p in (delta, 2 * delta, 4 * delta, 8 * delta) if p < nx]
+    ch.stats_attach(planes)
+    return cfg, stg, f, hist, ch, planes
+
+
+def sample_nodes(nx, ny, nz, planes, seed, n_random=3000):
+    xs = sorted({0, 1, 2, nx // 2, nx - 3, nx - 2, nx - 1, *planes, *[p - 1 for p in planes], *[p + 1 for p in planes]})
+    ys = sorted({0, 1, 2, 3, 4, ny // 2, ny - 5, ny - 4, ny - 3, ny - 2, ny - 1})
+    zs = sorted({0, 1, 62, 63, 64, 65, nz - 2, nz - 1} & set(range(nz)))
+    g = np.random.default_rng(seed)
+    nodes = [(x * ny + y) * nz + z for x in xs for y in ys for z in zs]
+    nodes += list(g.integers(0, nx * ny * nz, n_random))
+    return np.unique(np.asarray(nodes, dtype=np.int64))
+
+
+@pytest.mark.parametrize("name,storage,tol", [("c2", "f32", 1e-5), ("c2", "f16dev", 2e-4), ("c3", "f16dev", 2e-4)])
+def test_full_size_one_step_sampled(name, storage, tol):
+    _say("full size", name, storage)
+    cfg, stg, f, hist, ch, planes = workload(name, storage, full_pert=(name == "c2"))
+    ch.step(1)
+    ch.sync()
+    nodes = sample_nodes(cfg.nx, cfg.ny, cfg.nz, planes, seed=int(name[1]))
+    gpu = ch.populations().reshape(19, -1)[:, torch.as_tensor(nodes, device="cuda")].cpu().numpy()
+    st, ref, _ = O.step_nodes(cfg, f, hist, 1.0, nodes, stg=stg)
+    assert st == O.OK
+    err = rel_linf(gpu.astype(np.float64), ref)
+    _say("  %d sampled nodes, rel Linf %.3e" % (len(nodes), err))
+    assert err <= tol
+
+
+def test_full_size_adjoint_step_256x64x64():
+    _say("full size adjoint c4")
+    cfg, stg, f, hist, ch, _ = workload("c4", "f32")
+    nx, ny, nz = cfg.nx, cfg.ny, cfg.nz
+    x_obs = 2 * ny  # 4 delta
+    ch.stats_attach([x_obs])
+    g = np.random.default_rng(44)
+    lam = g.normal(size=(19, nx, ny, nz)).astype(np.float32)
+    eta = g.normal(size=(5, ny, nz)).astype(np.float32)
+    coef = g.normal(size=(1, ny, 9)).astype(np.float32)
+    ref = O.adjoint_step(cfg, f, hist, 7.0, lam.astype(np.float64), eta.astype(np.float64), stg=stg,
+                         planes=[x_obs], coef=coef.astype(np.float64), want_amp=True)
+    assert ref["status"] == O.OK
+    f_cur, h_cur = ch.state()
+    lam_n = ch.field_import(torch.as_tensor(lam))
+    lam_p = ch.new_field()
+    eta_n = torch.as_tensor(eta, device="cuda")
+    eta_p = torch.zeros_like(eta_n)
+    g_uin = torch.zeros((3, ny, nz), dtype=torch.float32, device="cuda")
+    grad = torch.zeros(ny + 1, dtype=torch.float64, device="cuda")
+    ch.adjoint_step(f_cur, h_cur, 7.0, lam_n, lam_p, eta_n, eta_p, coef=torch.as_tensor(coef), g_uin=g_uin,
+                    grad=grad)
+    ch.sync()
+    errs = dict(lam=rel_linf(ch.field_export(lam_p).cpu().numpy(), ref["lam"]),
+                eta=rel_linf(eta_p.cpu().numpy(), ref["eta"]),
+                g_uin=rel_linf(g_uin.cpu().numpy(), ref["g_uin"]),
+                g_amp=rel_linf(grad[:-1].cpu().numpy(), ref["g_amp"]),
+                g_cs=abs(float(grad[-1]) - ref["g_cs"]) / abs(ref["g_cs"]))
+    _say("  ", {k: "%.2e" % v for k, v in errs.items()})
+    for k in ("lam", "eta", "g_uin"):
+        assert errs[k] < TOL_FIELD, errs
+    for k in ("g_amp", "g_cs"):
+        assert errs[k] < TOL_PARAM, errs

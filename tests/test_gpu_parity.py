@@ -199,3 +199,38 @@ def test_bad_arguments_rejected():
     with pytest.raises(A.LbmError) as e:
         ch.step(1)  # no STG bound
     assert e.value.status == A.LBM_ERR_STATE
+
+
+def test_fp16_mean_profiles_long_horizon():
+    """Mean profiles U(y) and <u'v'>(y) over steps 501-1000 at x = 16 and 32 of
+    the 64 x 32 x 32 channel (slip walls, wall model, STG inlet): FP16-deviation
+    and FP32 storage against the FP64 oracle.  U error relative to max U; the
+    stress error relative to the prescribed stress scale max |R12|.  Bound for
+    FP16 storage 1e-3 (the mean-profile target); FP32 1e-4."""
+    nx, ny, nz = 64, 32, 32
+    planes = [16, 32]
+    res = {}
+    for storage in ("f32", "f16dev"):
+        c = Case(nx, ny, nz, ywall="slip", xbc="inflow", wall_model=True, tau0=0.52, n_modes=100, seed=3,
+                 storage=storage)
+        c.ch.step(500)
+        c.ch.stats_attach(planes)
+        c.ch.step(500)
+        means, n = c.ch.stats_read()
+        assert n == 500
+        res[storage] = means
+    st, f5, h5, _ = c.run_oracle(500)
+    assert st == O.OK
+    acc = np.zeros((2, ny, 9))
+    st, _, _ = O.run(c.ocfg, f5, h5, 500, 500, stg=c.stg_or, planes=planes, acc=acc)
+    assert st == O.OK
+    ref = acc / (500 * nz)
+    U_ref = ref[..., 0]
+    uv_ref = ref[..., 6] - ref[..., 0] * ref[..., 1]
+    scale = np.abs(c.R[1]).max()
+    for storage, bound in (("f32", 1e-4), ("f16dev", 1e-3)):
+        m = res[storage]
+        eU = np.abs(m[..., 0] - U_ref).max() / np.abs(U_ref).max()
+        euv = np.abs(m[..., 6] - m[..., 0] * m[..., 1] - uv_ref).max() / scale
+        _say("%s: U profile err %.3e, <u'v'> err %.3e (of max|R12|)" % (storage, eU, euv))
+        assert eU <= bound and euv <= bound
