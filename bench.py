@@ -141,8 +141,13 @@ def time_adjoint(device, steps=400, segment=20, warmup=20):
         x_obs, steps, segment), nodes=N, forward_ms_per_step=round(fwd_ms, 5),
         forward_kernel_ms=round(fwd_kernel_ms, 5), adjoint_step_ms=round(adj_ms, 5),
         adjoint_mlups=round(N / (adj_ms * 1e-3) / 1e6, 1),
-        adjoint_gbs=round(ADJ_BYTES_PER_NODE * N / (adj_ms * 1e-3) / 1e9, 1),
         adjoint_vs_forward=round(adj_ms / fwd_ms, 3),
+        roofline={"bound": "hbm", "achieved": round(ADJ_BYTES_PER_NODE * N / (adj_ms * 1e-3) / 1e9, 1),
+                  "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                  "frac": round(ADJ_BYTES_PER_NODE * N / (adj_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                  "traffic": measured_traffic("adjoint_traffic_256x64x64.json", "c4:adjoint"),
+                  "kernel": "adjoint_kernel<f32> (one launch per adjoint step)",
+                  "bytes_per_node": ADJ_BYTES_PER_NODE},
         gradient_forward_ms=round((t1 - t0) * 1e3, 3), gradient_backward_ms=round((t3 - t2) * 1e3, 3),
         backward_vs_forward_end_to_end=round((t3 - t2) / (t1 - t0), 3),
         loss=float(loss), grad_cs=float(g[-1]), grad_amp_linf=float(np.abs(g[:-1]).max()), status=status)
@@ -171,17 +176,19 @@ def copy_bandwidth(device, nbytes=2 << 30, reps=20):
     return 2 * nbytes / (ms * 1e-3) / 1e9
 
 
-def measured_traffic(key):
-    """HBM bytes per launch of the dominant kernel from the committed rocprofv3
-    FETCH_SIZE / WRITE_SIZE record, or None when the kernel source changed since."""
+def measured_traffic(record, key):
+    """HBM bytes per launch of a kernel from a committed rocprofv3 FETCH_SIZE /
+    WRITE_SIZE record (profiles/<record>), or None when one of the kernel's
+    source files changed since the counters were taken."""
     import hashlib
-    rec = os.path.join(ROOT, "profiles", "collide_traffic_re1000_768x64x192.json")
     try:
-        t = json.load(open(rec))
-        src = open(os.path.join(ROOT, t["kernel_source"]), "rb").read()
-        if hashlib.sha256(src).hexdigest() != t["kernel_source_sha256"]:
+        t = json.load(open(os.path.join(ROOT, "profiles", record)))[key]
+        h = hashlib.sha256()
+        for src in t["sources"]:
+            h.update(open(os.path.join(ROOT, src), "rb").read())
+        if h.hexdigest() != t["sources_sha256"]:
             return None
-        return t[key]["traffic_bytes"]
+        return t["traffic_bytes"]
     except (OSError, KeyError, ValueError):
         return None
 
@@ -221,6 +228,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--only", default=None, help="time one (workload:storage), e.g. c2:f32 (profiling)")
     ap.add_argument("--copy-only", action="store_true", help="run the 2 GiB copy kernel only (counter calibration)")
+    ap.add_argument("--adj-steps", type=int, default=400, help="steps of the adjoint workload (loss horizon)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only (the path shards over x-slabs by design, "
@@ -233,7 +241,7 @@ def main():
         print(json.dumps({"copy_kernel_gbs": copy_bandwidth(device, reps=args.steps)}), flush=True)
         return
     if args.only == "adjoint":
-        print(json.dumps(time_adjoint(device)), flush=True)
+        print(json.dumps(time_adjoint(device, steps=args.adj_steps)), flush=True)
         return
     if args.only:
         name, storage = args.only.split(":")
@@ -249,7 +257,7 @@ def main():
     r3 = time_channel("c3", "f32", c3_steps, max(5, args.warmup // 5), device)
     r3h = time_channel("c3", "f16dev", c3_steps, max(5, args.warmup // 5), device)
     log("bench: adjoint 256x64x64")
-    radj = time_adjoint(device)
+    radj = time_adjoint(device, steps=args.adj_steps)
     log("bench: copy bandwidth")
     copy_gbs = copy_bandwidth(device)
     cpu = None
@@ -274,7 +282,7 @@ def main():
                                "slip walls + Reichardt wall model, convective outlet, 4 FP64 statistics planes",
                    "nodes": main_r["nodes"], "status": main_r["status"]},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic("c2:f32"),
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic("collide_traffic_re1000_768x64x192.json", "c2:f32"),
                      "kernel": "collide_general_kernel<f32> (all blocks)", "kernel_ms": round(main_r["kernel_ms"], 5),
                      "kernel_nodes": main_r["kernel_nodes"],
                      "bytes_per_node": BYTES_PER_NODE["f32"], "copy_kernel_gbs": round(copy_gbs, 1),
