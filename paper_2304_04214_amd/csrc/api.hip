@@ -1,6 +1,7 @@
 // C ABI of the library: argument checking, handle state, launch sequencing.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdint>
 #include <cstring>
@@ -86,9 +87,10 @@ void free_tables(lbm_ctx* h) {
 
 // The timed collide launch (the interior kernel with FP16 storage, the
 // single general kernel with FP32 storage), bracketed by events when enabled.
-hipError_t timed_launch(lbm_ctx* h, int src, int dst) {
+hipError_t timed_launch(lbm_ctx* h, int src, int dst, const float* u_in = nullptr) {
   auto launch = [&]() {
-    return h->split ? lbm::launch_interior(h, src, dst, h->stream) : lbm::launch_boundary(h, src, dst, h->stream);
+    return h->split ? lbm::launch_interior(h, src, dst, h->stream)
+                    : lbm::launch_boundary(h, src, dst, h->stream, u_in);
   };
   if (!h->timing) return launch();
   const size_t need = 2 * (size_t)(h->ev_used + 1);
@@ -247,6 +249,8 @@ lbm_status lbm_destroy(lbm_handle h) {
   if (h->d_amp_part) (void)hipFree(h->d_amp_part);
   if (h->d_fluct) (void)hipFree(h->d_fluct);
   if (h->d_guin) (void)hipFree(h->d_guin);
+  if (h->d_uin_ring) (void)hipFree(h->d_uin_ring);
+  if (h->d_fl_ring) (void)hipFree(h->d_fl_ring);
   for (hipEvent_t e : h->ev) (void)hipEventDestroy(e);
   destroy_streams(h);
   delete h;
@@ -307,16 +311,29 @@ lbm_status lbm_step(lbm_handle h, const lbm_stg* stg, int32_t nsteps) {
   const bool inflow = h->cfg.xbc == LBM_X_INFLOW;
   if (inflow && !h->stg_bound) return LBM_ERR_STATE;
   if (nsteps == 0) return LBM_OK;
+  // The inlet planes of up to STG_BATCH steps are computed by one launch into
+  // a ring (the plane of the call's last step also into the bound u_in /
+  // fluct); the steps' kernels then read their plane from the ring.
+  const size_t plane = (size_t)3 * h->cfg.ny * h->cfg.nz;
+  if (inflow && !h->d_uin_ring) HIPCHK(hipMalloc(&h->d_uin_ring, sizeof(float) * plane * lbm::STG_BATCH));
+  if (inflow && h->stg.fluct && !h->d_fl_ring) HIPCHK(hipMalloc(&h->d_fl_ring, sizeof(float) * plane * lbm::STG_BATCH));
+  auto fill_batch = [&](int32_t n, hipStream_t st) -> hipError_t {
+    const int nb = (int)std::min<int64_t>(lbm::STG_BATCH, nsteps - n);
+    return lbm::launch_stg_fill_batch(h, (double)(h->time + 1), nb, st, h->d_uin_ring,
+                                      h->stg.fluct ? h->d_fl_ring : nullptr, n + nb == nsteps ? nb - 1 : -1);
+  };
+  auto ring_plane = [&](int32_t n) { return inflow ? h->d_uin_ring + plane * (size_t)(n % lbm::STG_BATCH) : nullptr; };
   if (!h->split) {
     for (int32_t n = 0; n < nsteps; ++n) {
-      if (inflow) HIPCHK(lbm::launch_stg_fill(h, (double)(h->time + 1), h->stream));
-      HIPCHK(timed_launch(h, h->cur, 1 - h->cur));
+      if (inflow && n % lbm::STG_BATCH == 0) HIPCHK(fill_batch(n, h->stream));
+      HIPCHK(timed_launch(h, h->cur, 1 - h->cur, ring_plane(n)));
       h->cur = 1 - h->cur;
       ++h->time;
       if (h->stats_on) ++h->n_samples;
     }
     return LBM_OK;
   }
+
   // Step n: the side stream fills the inlet plane and runs the boundary
   // blocks while the caller's stream runs the interior blocks.  Both read s_n
   // and write disjoint nodes of s_{n+1}; step n+1 on either stream waits for
@@ -327,8 +344,8 @@ lbm_status lbm_step(lbm_handle h, const lbm_stg* stg, int32_t nsteps) {
   for (int32_t n = 0; n < nsteps; ++n) {
     const int src = h->cur, dst = 1 - h->cur;
     if (n > 0) HIPCHK(hipStreamWaitEvent(h->side, h->ev_int[(n - 1) & 1], 0));
-    if (inflow) HIPCHK(lbm::launch_stg_fill(h, (double)(h->time + 1), h->side));
-    HIPCHK(lbm::launch_boundary(h, src, dst, h->side));
+    if (inflow && n % lbm::STG_BATCH == 0) HIPCHK(fill_batch(n, h->side));
+    HIPCHK(lbm::launch_boundary(h, src, dst, h->side, ring_plane(n)));
     HIPCHK(hipEventRecord(h->ev_bnd[n & 1], h->side));
     if (n > 0) HIPCHK(hipStreamWaitEvent(h->stream, h->ev_bnd[(n - 1) & 1], 0));
     HIPCHK(timed_launch(h, src, dst));

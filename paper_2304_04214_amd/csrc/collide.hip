@@ -486,10 +486,11 @@ void fill_args(lbm_ctx* h, CollideArgs& a, int src, int dst) {
 }
 
 
-hipError_t launch_boundary(lbm_ctx* h, int src, int dst, hipStream_t stream) {
+hipError_t launch_boundary(lbm_ctx* h, int src, int dst, hipStream_t stream, const float* u_in) {
   if (h->n_bnd == 0) return hipSuccess;
   CollideArgs a;
   fill_args(h, a, src, dst);
+  if (u_in) a.u_in = u_in;
   if (h->cfg.storage == LBM_STORE_F16DEV)
     collide_general_kernel<true><<<h->n_bnd, BLOCK, 0, stream>>>(a, h->d_blist_bnd);
   else

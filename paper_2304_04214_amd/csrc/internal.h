@@ -18,6 +18,7 @@ constexpr int ERRBIT_NONFINITE = 2;
 constexpr int ZT = 64;     // z-lanes per wave (one wave = one (x, y) row segment)
 constexpr int YROWS = 4;   // rows (waves) per collide block
 constexpr int BLOCK = ZT * YROWS;
+constexpr int STG_BATCH = 32;  // steps whose inlet planes one STG launch computes
 // Largest ny the adjoint supports (its bin reduction stages rows in LDS).
 #define LBM_ADJ_MAX_NY 4096
 
@@ -105,6 +106,8 @@ struct lbm_ctx {
   double* d_amp_part = nullptr; // [ny][zc] dL/ds_b partials per inlet row chunk, accumulated
   float* d_fluct = nullptr;     // [3][ny][nz], when the bound STG inputs have no fluct buffer
   float* d_guin = nullptr;      // [3][ny][nz], when the caller passes no g_uin
+  float* d_uin_ring = nullptr;  // [STG_BATCH][3][ny][nz] inlet planes of the steps of one batch
+  float* d_fl_ring = nullptr;   // the same for a v', when the bound STG inputs keep it
   int timing = 0;
   std::vector<hipEvent_t> ev;  // pairs (start, stop) of timed launches
   int64_t ev_used = 0;
@@ -114,7 +117,8 @@ struct lbm_ctx {
 
 namespace lbm {
 // collide.hip
-hipError_t launch_boundary(lbm_ctx* h, int src, int dst, hipStream_t stream);
+// u_in, when given, replaces the bound inlet plane.
+hipError_t launch_boundary(lbm_ctx* h, int src, int dst, hipStream_t stream, const float* u_in = nullptr);
 hipError_t launch_interior(lbm_ctx* h, int src, int dst, hipStream_t stream);
 hipError_t build_block_lists(lbm_ctx* h, const std::vector<int>& plane_of_x);
 hipError_t launch_stream_only(lbm_ctx* h, int src, int dst);
@@ -134,5 +138,7 @@ hipError_t launch_adjoint_reduce(lbm_ctx* h, double* grad);
 // stg.hip
 hipError_t launch_stg_bind(lbm_ctx* h, const lbm_stg* s);
 hipError_t launch_stg_fill(lbm_ctx* h, double t, hipStream_t stream, float* fluct = nullptr, float* u_in = nullptr);
+hipError_t launch_stg_fill_batch(lbm_ctx* h, double time0, int nb, hipStream_t stream, float* ring, float* fring,
+                                 int last_j);
 hipError_t launch_inflow_reichardt(lbm_ctx* h, double u_tau, double* u_rans);
 }  // namespace lbm

@@ -65,10 +65,13 @@ __global__ void stg_bind_kernel(lbm_stg s, StgTables t, int ny, int nz) {
   }
 }
 
-// One block per (inlet row y, 64 spanwise nodes); its four waves each sum a
-// quarter of the modes, and the partial sums are added in a fixed order.
-__global__ __launch_bounds__(256) void stg_fill_kernel(lbm_stg s, StgTables t, int ny, int nz, double time,
-                                                       int* err) {
+// One block per (inlet row y, 64 spanwise nodes, step); its four waves each
+// sum a quarter of the modes, and the partial sums are added in a fixed order.
+// Step j = blockIdx.z has time time0 + j.  With ring == nullptr the plane
+// goes to s.u_in / s.fluct; otherwise to plane j of ring / fring, and the
+// plane of step last_j also to s.u_in / s.fluct.
+__global__ __launch_bounds__(256) void stg_fill_kernel(lbm_stg s, StgTables t, int ny, int nz, double time0,
+                                                       int* err, float* ring, float* fring, int last_j) {
   __shared__ float2 rowph[LBM_MAX_MODES];
   __shared__ float amp[3][LBM_MAX_MODES];
   __shared__ float part[3][3][64];
@@ -78,6 +81,8 @@ __global__ __launch_bounds__(256) void stg_fill_kernel(lbm_stg s, StgTables t, i
   const int zr = blockIdx.x * 64 + lane;
   const int z = zr < nz ? zr : nz - 1;
   const int N = s.n_modes;
+  const int j = blockIdx.z;
+  const double time = time0 + j;
   // (y, t)-dependent phase of every mode, FP64 then reduced to [0, 2 pi)
   for (int n = threadIdx.x; n < N; n += 256) {
     const double ph = fmod(t.ky[n] * (y + 0.5) + s.omega[n] * time + s.phi[n], TWO_PI);
@@ -124,13 +129,30 @@ __global__ __launch_bounds__(256) void stg_fill_kernel(lbm_stg s, StgTables t, i
   const float sb = t.sb[y];
   const int o = y * nz + z, pl = ny * nz;
   const float ux = t.urans[y] + sb * p0;
-  s.u_in[o] = ux;
-  s.u_in[pl + o] = t.urans[ny + y] + sb * p1;
-  s.u_in[2 * pl + o] = t.urans[2 * ny + y] + sb * p2;
-  if (s.fluct) {
-    s.fluct[o] = p0;
-    s.fluct[pl + o] = p1;
-    s.fluct[2 * pl + o] = p2;
+  const float uy = t.urans[ny + y] + sb * p1;
+  const float uz = t.urans[2 * ny + y] + sb * p2;
+  const bool bound = ring == nullptr || j == last_j;
+  if (ring) {
+    float* u = ring + (size_t)j * 3 * pl;
+    u[o] = ux;
+    u[pl + o] = uy;
+    u[2 * pl + o] = uz;
+    if (fring) {
+      float* f = fring + (size_t)j * 3 * pl;
+      f[o] = p0;
+      f[pl + o] = p1;
+      f[2 * pl + o] = p2;
+    }
+  }
+  if (bound) {
+    s.u_in[o] = ux;
+    s.u_in[pl + o] = uy;
+    s.u_in[2 * pl + o] = uz;
+    if (s.fluct) {
+      s.fluct[o] = p0;
+      s.fluct[pl + o] = p1;
+      s.fluct[2 * pl + o] = p2;
+    }
   }
   if (!(fabsf(ux) < MACH_LIMIT)) atomicOr(err, ERRBIT_MACH);
 }
@@ -187,7 +209,18 @@ hipError_t launch_stg_fill(lbm_ctx* h, double time, hipStream_t stream, float* f
   lbm_stg s = h->stg;
   if (fluct) s.fluct = fluct;
   if (u_in) s.u_in = u_in;
-  stg_fill_kernel<<<grid, 256, 0, stream>>>(s, h->tab, ny, nz, time, h->d_err);
+  stg_fill_kernel<<<grid, 256, 0, stream>>>(s, h->tab, ny, nz, time, h->d_err, nullptr, nullptr, -1);
+  return hipGetLastError();
+}
+
+// The inlet planes of nb consecutive steps (times time0 .. time0 + nb - 1) in
+// one launch, into plane j of ring (and fring); the plane of step last_j
+// (-1: none) also goes to the bound u_in / fluct.
+hipError_t launch_stg_fill_batch(lbm_ctx* h, double time0, int nb, hipStream_t stream, float* ring, float* fring,
+                                 int last_j) {
+  const int ny = h->cfg.ny, nz = h->cfg.nz;
+  dim3 grid((nz + 63) / 64, ny, nb);
+  stg_fill_kernel<<<grid, 256, 0, stream>>>(h->stg, h->tab, ny, nz, time0, h->d_err, ring, fring, last_j);
   return hipGetLastError();
 }
 
