@@ -66,7 +66,10 @@ enum { LBM_STATS_ATTACH = 1, LBM_STATS_DETACH = 2, LBM_STATS_RESET = 3, LBM_STAT
  *              Sec. III.A, Eq. (26)-(31)) and convective outlet at x = nx-1
  *              for c_x < 0: f_i = (f_i^prev + u_conv f_i(x-1)) / (1 + u_conv).
  *  wall_model  1: Reichardt wall force in the first off-wall cells (Sec. II.C,
- *              Eq. (16)-(21)), u_tau by newton_iters Newton steps.
+ *              Eq. (16)-(21)), u_tau by newton_iters Newton steps from the
+ *              viscous-sublayer estimate (0: 4; in FP32 the iteration reaches
+ *              rounding level after three steps for nu0 in [1e-5, 2e-2] and
+ *              |u_hat| in [1e-6, 0.3]).
  *  tau0        molecular relaxation time (> 1/2), nu0 = (tau0 - 1/2)/3 (Eq. (5)).
  *  cs_smag     Smagorinsky C_s, C_smag = C_s^2 (Sec. II.B).  0 disables it.
  *  s[19]       MRT relaxation rates (Appendix A.1); s[9], s[11], s[13], s[14],

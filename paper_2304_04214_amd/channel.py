@@ -36,7 +36,7 @@ class Channel:
 
     def __init__(self, nx, ny, nz, *, tau0, storage="f32", ywall="slip", xbc="periodic", wall_model=False,
                  cs_smag=0.1, rates=None, kappa=0.41, b_reich=7.8, y_wall=0.5, u_conv=0.1, g=(0.0, 0.0, 0.0),
-                 newton_iters=8, device=None):
+                 newton_iters=4, device=None):
         self.device = torch.device(device if device is not None else "cuda")
         self.nx, self.ny, self.nz = nx, ny, nz
         self.N = nx * ny * nz

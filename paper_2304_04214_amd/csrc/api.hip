@@ -183,7 +183,7 @@ lbm_status lbm_create(const lbm_config* cfg, void* f_a, void* f_b, float* hist_a
   lbm_ctx* h = new (std::nothrow) lbm_ctx();
   if (!h) return LBM_ERR_ARG;
   h->cfg = *cfg;
-  if (h->cfg.newton_iters == 0 && h->cfg.wall_model) h->cfg.newton_iters = 8;
+  if (h->cfg.newton_iters == 0 && h->cfg.wall_model) h->cfg.newton_iters = 4;
   h->stream = static_cast<hipStream_t>(hip_stream);
   if (hipGetDevice(&h->device) != hipSuccess) {
     delete h;

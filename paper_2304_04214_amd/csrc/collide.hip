@@ -54,10 +54,14 @@ __device__ __forceinline__ void wall_force(const CollideArgs& a, float rho, floa
 // f* = f + M^-1 delta with delta_k = -s_k (m_k - m_eq_k) + (1 - s_k/2) F_k.
 // The moment transform uses the even/odd split of the basis over the
 // opposite-direction pairs (i, 18 - i).  Returns the force-corrected velocity.
-template <bool FORCE>
+//
+// DEV: f holds the deviations h_i = f_i - w_i and is updated as h* = h + M^-1
+// delta; pr are the pair sums of h and rhoh = rho - 1.  The weights add only
+// to m_0 = rho, m_1 (-11) and m_2 (3), which enter through e_1 and e_2.
+template <bool FORCE, bool DEV = false>
 __device__ __forceinline__ void collide(const CollideArgs& a, float f[Q], const Pairs& pr, float rho, float jx,
                                         float jy, float jz, float Fx, float Fy, float Fz, float& ux, float& uy,
-                                        float& uz) {
+                                        float& uz, float rhoh = 0.f) {
   const float* s = pr.s;
   const float* d = pr.d;
   const float f9 = f[9];
@@ -87,8 +91,8 @@ __device__ __forceinline__ void collide(const CollideArgs& a, float f[Q], const 
   uy = py * ir;
   uz = pz * ir;
   const float uxx = ux * ux, uyy = uy * uy, uzz = uz * uz, uu = uxx + uyy + uzz;
-  const float e1 = m1 - rho * (19.f * uu - 11.f);
-  const float e2 = m2 - rho * (3.f - 5.5f * uu);
+  const float e1 = DEV ? m1 + 11.f * rhoh - 19.f * rho * uu : m1 - rho * (19.f * uu - 11.f);
+  const float e2 = DEV ? m2 - 3.f * rhoh + 5.5f * rho * uu : m2 - rho * (3.f - 5.5f * uu);
   const float e4 = m4 + (2.f / 3.f) * px;
   const float e6 = m6 + (2.f / 3.f) * py;
   const float e8 = m8 + (2.f / 3.f) * pz;
@@ -331,24 +335,32 @@ __global__ __launch_bounds__(BLOCK) void collide_interior_kernel(CollideArgs a, 
     const uint32_t cs = CZ[i] == 1 ? col.bm : (CZ[i] == -1 ? col.bp : col.b0);
     r[i] = Pop<F16>::raw(row_ptr<F16>(a.src, rowpart(a, g.xs[CX[i] + 1], g.ys[CY[i] + 1]) + (uint32_t)i * ZT), cs);
   }
+  // FP16 storage computes on the deviations h = f - w directly (no w added on
+  // load or subtracted on store); FP32 storage on the populations.
   float f[Q];
 #pragma unroll
-  for (int i = 0; i < Q; ++i) f[i] = Pop<F16>::cvt(i, r[i]);
+  for (int i = 0; i < Q; ++i) f[i] = F16 ? Pop<true>::cvt_dev(r[i]) : Pop<F16>::cvt(i, r[i]);
   const Pairs pr = make_pairs(f);
-  const float rho = pr.A + pr.Bx + f[9];
+  const float rhoh = pr.A + pr.Bx + f[9];  // sum of h (F16) or rho (F32)
+  const float rho = F16 ? 1.f + rhoh : rhoh;
   const float jx = (pr.d[3] + pr.d[7]) - (pr.d[1] + pr.d[5] + pr.d[8]);
   const float jy = pr.d[4] - (pr.d[0] + pr.d[5] + pr.d[6] + pr.d[7]);
   const float jz = -(pr.d[0] + pr.d[1] + pr.d[2] + pr.d[3] + pr.d[4]);
   float ux, uy, uz;
   if (FORCE)
-    collide<true>(a, f, pr, rho, jx, jy, jz, rho * a.g[0], rho * a.g[1], rho * a.g[2], ux, uy, uz);
+    collide<true, F16>(a, f, pr, rho, jx, jy, jz, rho * a.g[0], rho * a.g[1], rho * a.g[2], ux, uy, uz, rhoh);
   else
-    collide<false>(a, f, pr, rho, jx, jy, jz, 0.f, 0.f, 0.f, ux, uy, uz);
+    collide<false, F16>(a, f, pr, rho, jx, jy, jz, 0.f, 0.f, 0.f, ux, uy, uz, rhoh);
   if (!(rho > 0.f && rho < 1e30f)) atomicOr(a.err, ERRBIT_NONFINITE);
   if (active && owned) {
     char* p = const_cast<char*>(row_ptr<F16>(a.dst, rowpart(a, x, y)));
 #pragma unroll
-    for (int i = 0; i < Q; ++i) Pop<F16>::stp(p + i * ZT * Pop<F16>::ES, i, col.b0, f[i]);
+    for (int i = 0; i < Q; ++i) {
+      if (F16)
+        Pop<true>::stp_dev(p + i * ZT * Pop<F16>::ES, col.b0, f[i]);
+      else
+        Pop<F16>::stp(p + i * ZT * Pop<F16>::ES, i, col.b0, f[i]);
+    }
   }
 }
 

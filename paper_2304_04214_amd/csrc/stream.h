@@ -77,6 +77,18 @@ struct Pop<true> {
     *reinterpret_cast<unsigned short*>(p + off) = (unsigned short)hb;
 #endif
   }
+  // The deviation h_i itself (kernels that compute on deviations).
+  __device__ static __forceinline__ float cvt_dev(Raw r) {
+    return (float)__builtin_bit_cast(_Float16, (unsigned short)r);
+  }
+  __device__ static __forceinline__ void stp_dev(char* p, uint32_t off, float h) {
+    const uint32_t hb = __builtin_bit_cast(unsigned short, (_Float16)h);
+#if LBM_EXP_F16_NT
+    __builtin_nontemporal_store((unsigned short)hb, reinterpret_cast<unsigned short*>(p + off));
+#else
+    *reinterpret_cast<unsigned short*>(p + off) = (unsigned short)hb;
+#endif
+  }
   __device__ static __forceinline__ void st_plain(void* base, int i, uint32_t e, float v) {
     static_cast<_Float16*>(base)[e] = (_Float16)(v - (float)WD[i]);
   }

@@ -22,7 +22,7 @@ def rel_linf(a, b):
 class Case:
     def __init__(self, nx, ny, nz, *, ywall="slip", xbc="inflow", wall_model=True, tau0=0.52, cs_smag=0.1,
                  u_tau=0.008369396673286735, n_modes=24, seed=0, storage="f32", g=(0.0, 0.0, 0.0), eps=0.05,
-                 du_amp=1e-3, u_conv=0.1, newton_iters=8, amp_scale=1.0, rates=None):
+                 du_amp=1e-3, u_conv=0.1, newton_iters=4, amp_scale=1.0, rates=None):
         self.nx, self.ny, self.nz = nx, ny, nz
         self.xbc = xbc
         self.ocfg = O.make_cfg(nx, ny, nz, ywall=YW[ywall], xbc=XB[xbc], wall_model=int(wall_model), tau0=tau0,
