@@ -44,11 +44,12 @@ def make_channel(name, storage, device):
     ch = Channel(nx, ny, nz, tau0=w["tau0"], storage=storage, ywall="slip", xbc="inflow", wall_model=True,
                  cs_smag=S.CS_SMAG, u_conv=S.U_C, device=device)
     U = ch.inflow_reichardt(w["u_tau"])
-    mt = S.mode_table(w["n_modes"], delta, seed_offset=int(name[1]))
+    k = int(name[1])
+    mt = S.mode_table(w["n_modes"], delta, seed_offset=k)
     ab, boy = S.amp_bins(ny)
     ch.set_stg(mt, U, S.reynolds_stress(ny, w["u_tau"]), ab, boy)
     g = torch.Generator(device=device)
-    g.manual_seed(S.SEED_BASE + int(name[1]))
+    g.manual_seed(S.SEED_BASE + k)
     u = U.float()[:, None, :, None].expand(3, nx, ny, nz).contiguous()
     u += 1e-3 * (2 * torch.rand((3, nx, ny, nz), generator=g, device=device) - 1)
     ch.init(u)
@@ -91,15 +92,17 @@ def time_channel(name, storage, steps, warmup, device):
 ADJ_BYTES_PER_NODE = 228  # s_n read + lam_{n+1} read + lam_n written, 19 floats each
 
 
-def time_adjoint(device, steps=400, segment=20, warmup=20):
-    """Gradient of the mean-profile loss at x = 4 delta over `steps` steps on the
-    256 x 64 x 64 channel (FP32) w.r.t. 64 amplitude scalings and C_s: forward with
-    checkpoints, then the checkpointed adjoint sweep (recompute included)."""
+def time_adjoint(device, name="c4", storage="f32", steps=400, segment=20, warmup=20):
+    """Gradient of the mean-profile loss at x = 4 delta over `steps` steps w.r.t. the
+    amplitude scalings (one bin per row) and C_s: forward with checkpoints, then the
+    checkpointed adjoint sweep (recompute included).  Workloads: the 256 x 64 x 64
+    channel (FP32, 400 steps, checkpoints every 20) and the 512 x 64 x 128 channel
+    (FP16-deviation storage, 2000 steps, checkpoints every 45 ~ sqrt(2000))."""
     import torch
     from paper_2304_04214_amd.adjoint import StatsGradient, mean_profile_loss
     from paper_2304_04214_amd import synthetic as S
-    ch, (nx, ny, nz) = make_channel("c4", "f32", device)
-    w = S.WORKLOADS["c4"]
+    ch, (nx, ny, nz) = make_channel(name, storage, device)
+    w = S.WORKLOADS[name]
     N = nx * ny * nz
     x_obs = int(4 * ny / 2)
     ch.stats_detach()
@@ -137,17 +140,19 @@ def time_adjoint(device, steps=400, segment=20, warmup=20):
     except Exception as e:
         status = str(e)
     adj_ms = adj_ms_total / steps
-    res = dict(workload="256x64x64 channel (FP32), loss at x=%d over %d steps, checkpoint every %d" % (
-        x_obs, steps, segment), nodes=N, forward_ms_per_step=round(fwd_ms, 5),
+    bpn = ADJ_BYTES_PER_NODE if storage == "f32" else ADJ_BYTES_PER_NODE - 38  # s_n in half deviations
+    res = dict(workload="%dx%dx%d channel (%s), loss at x=%d over %d steps, checkpoint every %d" % (
+        nx, ny, nz, "FP32" if storage == "f32" else "FP16-deviation storage", x_obs, steps, segment),
+        nodes=N, forward_ms_per_step=round(fwd_ms, 5),
         forward_kernel_ms=round(fwd_kernel_ms, 5), adjoint_step_ms=round(adj_ms, 5),
         adjoint_mlups=round(N / (adj_ms * 1e-3) / 1e6, 1),
         adjoint_vs_forward=round(adj_ms / fwd_ms, 3),
-        roofline={"bound": "hbm", "achieved": round(ADJ_BYTES_PER_NODE * N / (adj_ms * 1e-3) / 1e9, 1),
+        roofline={"bound": "hbm", "achieved": round(bpn * N / (adj_ms * 1e-3) / 1e9, 1),
                   "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                  "frac": round(ADJ_BYTES_PER_NODE * N / (adj_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
-                  "traffic": measured_traffic("adjoint_traffic_256x64x64.json", "c4:adjoint"),
-                  "kernel": "adjoint_kernel<f32> (one launch per adjoint step)",
-                  "bytes_per_node": ADJ_BYTES_PER_NODE},
+                  "frac": round(bpn * N / (adj_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                  "traffic": measured_traffic("adjoint_traffic_256x64x64.json", "c4:adjoint") if name == "c4" else None,
+                  "kernel": "adjoint_kernel<%s> (one launch per adjoint step)" % storage,
+                  "bytes_per_node": bpn},
         gradient_forward_ms=round((t1 - t0) * 1e3, 3), gradient_backward_ms=round((t3 - t2) * 1e3, 3),
         backward_vs_forward_end_to_end=round((t3 - t2) / (t1 - t0), 3),
         loss=float(loss), grad_cs=float(g[-1]), grad_amp_linf=float(np.abs(g[:-1]).max()), status=status)
@@ -243,6 +248,9 @@ def main():
     if args.only == "adjoint":
         print(json.dumps(time_adjoint(device, steps=args.adj_steps)), flush=True)
         return
+    if args.only == "adjoint-large":
+        print(json.dumps(time_adjoint(device, "c5a", "f16dev", steps=2000, segment=45)), flush=True)
+        return
     if args.only:
         name, storage = args.only.split(":")
         r = time_channel(name, storage, args.steps, args.warmup, device)
@@ -258,6 +266,8 @@ def main():
     r3h = time_channel("c3", "f16dev", c3_steps, max(5, args.warmup // 5), device)
     log("bench: adjoint 256x64x64")
     radj = time_adjoint(device, steps=args.adj_steps)
+    log("bench: adjoint 512x64x128 FP16")
+    radj5 = time_adjoint(device, "c5a", "f16dev", steps=2000, segment=45)
     log("bench: copy bandwidth")
     copy_gbs = copy_bandwidth(device)
     cpu = None
@@ -296,6 +306,7 @@ def main():
                                 "f16dev_vs_f32": round(r3h["mlups"] / r3["mlups"], 3),
                                 "status": [r3["status"], r3h["status"]]},
         "adjoint": radj,
+        "adjoint_512x64x128_fp16": radj5,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

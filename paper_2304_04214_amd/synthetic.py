@@ -41,6 +41,9 @@ WORKLOADS = {
                tau0=0.5004270558446486, n_modes=200, steps=400, ywall=2, storage="f32"),
     "c5": dict(nx=1536, ny=256, nz=384, re_tau=5200.0, u_tau=0.0037741807439038936,
                tau0=0.5002787087318575, n_modes=300, steps=5000, ywall=2, storage="f32"),
+    # the large adjoint run: 512 x 64 x 128 with the Re_tau = 1000 lattice parameters of ny = 64
+    "c5a": dict(nx=512, ny=64, nz=128, re_tau=1000.0, u_tau=0.004448498381757104,
+                tau0=0.5004270558446486, n_modes=300, steps=2000, ywall=2, storage="f16dev"),
 }
 U_C = 0.1      # centreline speed, lattice units
 CS_SMAG = 0.1  # C_s; C_smag = C_s^2 = 0.01 (Sec. IV.A)
