@@ -34,7 +34,10 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def make_channel(name, storage, device):
+SPONGE_NU = 0.1  # viscosity at the outlet plane of the 1-delta sponge (the paper gives no value)
+
+
+def make_channel(name, storage, device, sponge=False):
     import torch
     from paper_2304_04214_amd import synthetic as S
     from paper_2304_04214_amd.channel import Channel
@@ -42,7 +45,8 @@ def make_channel(name, storage, device):
     nx, ny, nz = w["nx"], w["ny"], w["nz"]
     delta = ny / 2
     ch = Channel(nx, ny, nz, tau0=w["tau0"], storage=storage, ywall="slip", xbc="inflow", wall_model=True,
-                 cs_smag=S.CS_SMAG, u_conv=S.U_C, device=device)
+                 cs_smag=S.CS_SMAG, u_conv=S.U_C, device=device, sponge_cells=int(delta) if sponge else 0,
+                 sponge_nu=SPONGE_NU if sponge else 0.0)
     U = ch.inflow_reichardt(w["u_tau"])
     k = int(name[1])
     mt = S.mode_table(w["n_modes"], delta, seed_offset=k)
@@ -59,9 +63,9 @@ def make_channel(name, storage, device):
     return ch, (nx, ny, nz)
 
 
-def time_channel(name, storage, steps, warmup, device):
+def time_channel(name, storage, steps, warmup, device, sponge=False):
     import torch
-    ch, (nx, ny, nz) = make_channel(name, storage, device)
+    ch, (nx, ny, nz) = make_channel(name, storage, device, sponge=sponge)
     N = nx * ny * nz
     ch.step(warmup)
     ch.sync()
@@ -252,14 +256,16 @@ def main():
         print(json.dumps(time_adjoint(device, "c5a", "f16dev", steps=2000, segment=45)), flush=True)
         return
     if args.only:
-        name, storage = args.only.split(":")
-        r = time_channel(name, storage, args.steps, args.warmup, device)
+        name, storage = args.only.split(":")[:2]
+        r = time_channel(name, storage, args.steps, args.warmup, device, sponge=args.only.endswith(":sponge"))
         print(json.dumps(r), flush=True)
         return
     log("bench: c2 f32")
     main_r = time_channel("c2", "f32", args.steps, args.warmup, device)
     log("bench: c2 f16dev")
     r16 = time_channel("c2", "f16dev", args.steps, args.warmup, device)
+    log("bench: c2 f32 with the outlet sponge")
+    rsp = time_channel("c2", "f32", args.steps, args.warmup, device, sponge=True)
     log("bench: c3 f32 / f16dev")
     c3_steps = max(10, args.steps // 5)
     r3 = time_channel("c3", "f32", c3_steps, max(5, args.warmup // 5), device)
@@ -300,6 +306,9 @@ def main():
         "fp16dev": {"mlups": round(r16["mlups"], 1), "ms_per_step": round(r16["ms_per_step"], 5),
                     "kernel_gbs": round(r16["kernel_gbs"], 1), "vs_fp32": round(r16["mlups"] / main_r["mlups"], 3),
                     "status": r16["status"]},
+        "with_outlet_sponge": {"mlups": round(rsp["mlups"], 1), "vs_no_sponge": round(rsp["mlups"] / main_r["mlups"], 3),
+                               "sponge": "last 32 planes (1 delta), nu 1.4e-4 -> %g" % SPONGE_NU,
+                               "status": rsp["status"]},
         "re5200_1536x128x384": {"f32_mlups": round(r3["mlups"], 1), "f32_kernel_gbs": round(r3["kernel_gbs"], 1),
                                 "f16dev_mlups": round(r3h["mlups"], 1),
                                 "f16dev_kernel_gbs": round(r3h["kernel_gbs"], 1),

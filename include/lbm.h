@@ -78,6 +78,12 @@ enum { LBM_STATS_ATTACH = 1, LBM_STATS_DETACH = 2, LBM_STATS_RESET = 3, LBM_STAT
  *              the first cell centre from the wall (0.5).
  *  u_conv      outlet convection speed.
  *  g[3]        uniform body acceleration; force density rho g (Eq. (9), (11)).
+ *  sponge_cells, sponge_nu  outlet sponge (Sec. IV.A; its law is not given
+ *              there, this is the library's reading): over the last
+ *              sponge_cells x planes the molecular viscosity rises as
+ *              nu(x) = nu0 + (sponge_nu - nu0) r^2, r = (x - nx + sponge_cells + 1)
+ *              / sponge_cells, i.e. tau0(x) = 1/2 + 3 nu(x).  0 cells: no sponge;
+ *              otherwise LBM_X_INFLOW, sponge_cells <= nx - 1, sponge_nu > 0.
  */
 typedef struct {
   int32_t nx, ny, nz;
@@ -86,12 +92,15 @@ typedef struct {
   int32_t xbc;
   int32_t wall_model;
   int32_t newton_iters;
+  int32_t sponge_cells;
+  int32_t reserved_;           /* 0 */
   double tau0;
   double cs_smag;
   double s[19];
   double kappa, b_reich, y_wall;
   double u_conv;
   double g[3];
+  double sponge_nu;
 } lbm_config;
 
 /*

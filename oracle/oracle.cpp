@@ -47,6 +47,11 @@
  *      c_x < 0 at x = nx-1, f(x-1) the post-streaming value of the same step.
  *  R14 inlet and wall rules both apply at inlet/wall corner cells
  *      (Algorithm 1 has two independent branches).
+ *  R19 outlet sponge (Sec. IV.A names a sponge of thickness delta before the
+ *      outlet but not its law): over the last L = sponge_cells planes the
+ *      molecular viscosity rises as nu(x) = nu0 + (nu_s - nu0) r^2,
+ *      r = (x - (nx - L) + 1) / L, so tau0(x) = 1/2 + 3 nu(x) in Eq. (5) and
+ *      Eq. (15); nu in the wall law's y+ stays nu0.
  */
 #include <cmath>
 #include <cstdint>
@@ -62,7 +67,7 @@ typedef struct {
   int32_t xbc;         /* 0 periodic, 1 STG inlet at x = 0 and convective outlet at x = nx-1 */
   int32_t wall_model;  /* 1: Reichardt wall force in the first off-wall cells */
   int32_t newton_max;  /* maximum Newton iterations (oracle converges to newton_tol) */
-  int32_t pad_;
+  int32_t sponge_cells;/* outlet sponge: the last sponge_cells x planes (0: none), reading R19 */
   double newton_tol;
   double tau0;         /* molecular relaxation time, nu0 = (tau0 - 1/2)/3 */
   double cs_smag;      /* Smagorinsky C_s, C_smag = C_s^2 */
@@ -70,6 +75,7 @@ typedef struct {
   double kappa, b_reich, y_wall;
   double u_conv;       /* outlet convection speed U_c */
   double g[3];         /* body acceleration */
+  double sponge_nu;    /* molecular viscosity at the outlet plane inside the sponge */
 } oracle_cfg;
 
 typedef struct {
@@ -305,6 +311,16 @@ void guo_populations(const R u[3], const R F[3], R out[19]) {
   }
 }
 
+/* ---- Sec. IV.A with reading R19: molecular relaxation time of plane x ---- */
+double tau0_at(const oracle_cfg& cfg, int x) {
+  const int L = cfg.sponge_cells;
+  if (L <= 0 || x < cfg.nx - L) return cfg.tau0;
+  const double nu0 = (cfg.tau0 - 0.5) * (1.0 / 3.0);
+  const double r = (double)(x - (cfg.nx - L) + 1) / L;
+  const double ramp = (g_mutation == 11) ? r : r * r;
+  return 0.5 + 3.0 * (nu0 + (cfg.sponge_nu - nu0) * ramp);
+}
+
 /* ---- Sec. II.B, Eq. (13)-(15): Smagorinsky relaxation time (reading R5) ---- */
 template <class R, class C>
 R tau_eff_of(const R& Qhalf, const R& rho, double tau0, const C& cs_smag) {
@@ -327,8 +343,8 @@ R safe_norm(const R& s2) {
  * out: post-collision populations.  u_out (optional): rho u = sum f c + F/2.
  */
 template <class R>
-void collide(const oracle_cfg& cfg, const R f[19], const R F[3], const R& cs_smag, R out[19], R* tau_out,
-             R u_out[3]) {
+void collide(const oracle_cfg& cfg, double tau0, const R f[19], const R F[3], const R& cs_smag, R out[19],
+             R* tau_out, R u_out[3]) {
   using std::sqrt;
   const Tables& t = T();
   R rho = 0.0 * f[0], j[3] = {0.0 * f[0], 0.0 * f[0], 0.0 * f[0]};
@@ -359,7 +375,7 @@ void collide(const oracle_cfg& cfg, const R f[19], const R F[3], const R& cs_sma
   for (int a = 0; a < 3; ++a)
     for (int b = 0; b < 3; ++b) q2 = q2 + Pn[a][b] * Pn[a][b];
   R Qhalf = safe_norm(q2);
-  R tau = tau_eff_of(Qhalf, rho, cfg.tau0, cs_smag);
+  R tau = tau_eff_of(Qhalf, rho, tau0, cs_smag);
   if (tau_out) *tau_out = tau;
   R S[19];
   for (int k = 0; k < 19; ++k) S[k] = cfg.s[k] + 0.0 * f[0];
@@ -664,7 +680,7 @@ bool is_wall_cell(const oracle_cfg& cf, int y) {
  * force-corrected velocity.  Returns the wall solve's status.
  */
 template <class R>
-int node_core(const oracle_cfg& cf, int y, const R f[19], const R f2[19], const R& cs_smag, R out[19],
+int node_core(const oracle_cfg& cf, int x, int y, const R f[19], const R f2[19], const R& cs_smag, R out[19],
               R u_stat[3]) {
   R rho, uw[3];
   pre_force_velocity(f, &rho, uw);
@@ -679,7 +695,7 @@ int node_core(const oracle_cfg& cf, int y, const R f[19], const R f2[19], const 
     for (int a = 0; a < 3; ++a) F[a] = F[a] + Fw[a];
   }
   R tau;
-  collide(cf, f, F, cs_smag, out, &tau, u_stat);
+  collide(cf, tau0_at(cf, x), f, F, cs_smag, out, &tau, u_stat);
   return st;
 }
 
@@ -698,7 +714,7 @@ int node_update(const Ctx& c, int x, int y, int z, double out[19], double hist_n
   } else {
     for (int i = 0; i < 19; ++i) f2[i] = 0.0;
   }
-  int st = node_core(cf, y, f, f2, cf.cs_smag, out, u_stat);
+  int st = node_core(cf, x, y, f, f2, cf.cs_smag, out, u_stat);
   double rho = 0.0;
   for (int i = 0; i < 19; ++i) rho += f[i];
   if (!(rho > 0.0) || !std::isfinite(rho)) st = OR_ERR_NONFINITE;
@@ -712,6 +728,8 @@ bool cfg_ok(const oracle_cfg* cf) {
   if (cf->xbc == 1 && cf->nx < 3) return false;
   if (cf->wall_model == 1 && cf->ny < 3) return false;
   if (!(cf->tau0 > 0.5)) return false;
+  if (cf->sponge_cells < 0 || cf->sponge_cells > cf->nx - 1) return false;
+  if (cf->sponge_cells > 0 && (cf->xbc != 1 || !(cf->sponge_nu > 0.0))) return false;
   return true;
 }
 
@@ -744,7 +762,7 @@ void oracle_guo(const double* u, const double* F, double* out) { guo_populations
 
 void oracle_collide_node(const oracle_cfg* cfg, const double* f, const double* F, double* out, double* tau_eff,
                          double* u) {
-  collide(*cfg, f, F, cfg->cs_smag, out, tau_eff, u);
+  collide(*cfg, cfg->tau0, f, F, cfg->cs_smag, out, tau_eff, u);
 }
 
 double oracle_tau_eff(double Qhalf, double rho, double tau0, double cs_smag) {
@@ -964,7 +982,7 @@ int oracle_adjoint_step(const oracle_cfg* cfg, const oracle_stg* stg, double t_n
           f2d[i] = wall ? D1::seed(f2[i], 19 + i) : D1(0.0);
         }
         const D1 cs = D1::seed(cfg->cs_smag, 38);
-        int st = node_core(*cfg, y, fd, f2d, cs, out, u);
+        int st = node_core(*cfg, x, y, fd, f2d, cs, out, u);
         if (st != OR_OK) {
 #pragma omp critical
           st_err = st;

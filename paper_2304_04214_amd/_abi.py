@@ -24,9 +24,10 @@ EXPORTED = [
 class Config(C.Structure):
     _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32), ("storage", C.c_int32),
                 ("ywall", C.c_int32), ("xbc", C.c_int32), ("wall_model", C.c_int32), ("newton_iters", C.c_int32),
+                ("sponge_cells", C.c_int32), ("reserved_", C.c_int32),
                 ("tau0", C.c_double), ("cs_smag", C.c_double), ("s", C.c_double * 19),
                 ("kappa", C.c_double), ("b_reich", C.c_double), ("y_wall", C.c_double),
-                ("u_conv", C.c_double), ("g", C.c_double * 3)]
+                ("u_conv", C.c_double), ("g", C.c_double * 3), ("sponge_nu", C.c_double)]
 
 
 class Stg(C.Structure):

@@ -36,7 +36,7 @@ class Channel:
 
     def __init__(self, nx, ny, nz, *, tau0, storage="f32", ywall="slip", xbc="periodic", wall_model=False,
                  cs_smag=0.1, rates=None, kappa=0.41, b_reich=7.8, y_wall=0.5, u_conv=0.1, g=(0.0, 0.0, 0.0),
-                 newton_iters=4, device=None):
+                 newton_iters=4, sponge_cells=0, sponge_nu=0.0, device=None):
         self.device = torch.device(device if device is not None else "cuda")
         self.nx, self.ny, self.nz = nx, ny, nz
         self.N = nx * ny * nz
@@ -54,6 +54,7 @@ class Channel:
         cfg.kappa, cfg.b_reich, cfg.y_wall, cfg.u_conv = kappa, b_reich, y_wall, u_conv
         for a in range(3):
             cfg.g[a] = g[a]
+        cfg.sponge_cells, cfg.sponge_nu = int(sponge_cells), float(sponge_nu)
         self.cfg = cfg
         dt = torch.float32 if storage == "f32" else torch.float16
         elems = C.c_int64()

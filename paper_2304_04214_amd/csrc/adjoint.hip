@@ -262,8 +262,9 @@ __device__ __forceinline__ void node_adjoint(const AdjointArgs& A, AdjLds& L, in
   const float pyy = 0.5f * (dc2 - pxx + e11), pzz = 0.5f * (dc2 - pxx - e11);
   const float q2 = pxx * pxx + pyy * pyy + pzz * pzz + 2.f * (e13 * e13 + e14 * e14 + e15 * e15);
   const float Qh = sqrt_fast(q2);
-  const float rr = sqrt_fast(a.tau0sq + a.smag * Qh * ir);
-  const float tau = 0.5f * a.tau0 + 0.5f * rr;
+  const Tau0 t0 = tau0_of_x(a, x);
+  const float rr = sqrt_fast(t0.tau0sq + a.smag * Qh * ir);
+  const float tau = 0.5f * t0.tau0 + 0.5f * rr;
   const float sv = rcp_fast(tau);
   const float hv = 1.f - 0.5f * sv;
   const float F9 = 2.f * (2.f * ux * Fx - uy * Fy - uz * Fz);

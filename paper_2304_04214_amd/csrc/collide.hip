@@ -59,9 +59,9 @@ __device__ __forceinline__ void wall_force(const CollideArgs& a, float rho, floa
 // delta; pr are the pair sums of h and rhoh = rho - 1.  The weights add only
 // to m_0 = rho, m_1 (-11) and m_2 (3), which enter through e_1 and e_2.
 template <bool FORCE, bool DEV = false>
-__device__ __forceinline__ void collide(const CollideArgs& a, float f[Q], const Pairs& pr, float rho, float jx,
-                                        float jy, float jz, float Fx, float Fy, float Fz, float& ux, float& uy,
-                                        float& uz, float rhoh = 0.f) {
+__device__ __forceinline__ void collide(const CollideArgs& a, const Tau0& t0, float f[Q], const Pairs& pr, float rho,
+                                        float jx, float jy, float jz, float Fx, float Fy, float Fz, float& ux,
+                                        float& uy, float& uz, float rhoh = 0.f) {
   const float* s = pr.s;
   const float* d = pr.d;
   const float f9 = f[9];
@@ -108,7 +108,7 @@ __device__ __forceinline__ void collide(const CollideArgs& a, float f[Q], const 
   const float pxx = (e9 + dc2) * (1.f / 3.f);
   const float pyy = 0.5f * (dc2 - pxx + e11), pzz = 0.5f * (dc2 - pxx - e11);
   const float q2 = pxx * pxx + pyy * pyy + pzz * pzz + 2.f * (e13 * e13 + e14 * e14 + e15 * e15);
-  const float tau = 0.5f * a.tau0 + 0.5f * sqrt_fast(a.tau0sq + a.smag * sqrt_fast(q2) * ir);
+  const float tau = 0.5f * t0.tau0 + 0.5f * sqrt_fast(t0.tau0sq + a.smag * sqrt_fast(q2) * ir);
   const float sv = rcp_fast(tau);
   const float hv = 1.f - 0.5f * sv;
 
@@ -263,10 +263,11 @@ __device__ __forceinline__ void node_update(const CollideArgs& a, int x, int y, 
   }
 
   float ux, uy, uz;
+  const Tau0 t0 = tau0_of_x(a, x);
   if (force)
-    collide<true>(a, f, pr, rho, jx, jy, jz, Fx, Fy, Fz, ux, uy, uz);
+    collide<true>(a, t0, f, pr, rho, jx, jy, jz, Fx, Fy, Fz, ux, uy, uz);
   else
-    collide<false>(a, f, pr, rho, jx, jy, jz, 0.f, 0.f, 0.f, ux, uy, uz);
+    collide<false>(a, t0, f, pr, rho, jx, jy, jz, 0.f, 0.f, 0.f, ux, uy, uz);
 
   if (!(rho > 0.f && rho < 1e30f)) atomicOr(a.err, ERRBIT_NONFINITE);
 
@@ -347,10 +348,11 @@ __global__ __launch_bounds__(BLOCK) void collide_interior_kernel(CollideArgs a, 
   const float jy = pr.d[4] - (pr.d[0] + pr.d[5] + pr.d[6] + pr.d[7]);
   const float jz = -(pr.d[0] + pr.d[1] + pr.d[2] + pr.d[3] + pr.d[4]);
   float ux, uy, uz;
+  const Tau0 t0 = tau0_of_x(a, x);
   if (FORCE)
-    collide<true, F16>(a, f, pr, rho, jx, jy, jz, rho * a.g[0], rho * a.g[1], rho * a.g[2], ux, uy, uz, rhoh);
+    collide<true, F16>(a, t0, f, pr, rho, jx, jy, jz, rho * a.g[0], rho * a.g[1], rho * a.g[2], ux, uy, uz, rhoh);
   else
-    collide<false, F16>(a, f, pr, rho, jx, jy, jz, 0.f, 0.f, 0.f, ux, uy, uz, rhoh);
+    collide<false, F16>(a, t0, f, pr, rho, jx, jy, jz, 0.f, 0.f, 0.f, ux, uy, uz, rhoh);
   if (!(rho > 0.f && rho < 1e30f)) atomicOr(a.err, ERRBIT_NONFINITE);
   if (active && owned) {
     char* p = const_cast<char*>(row_ptr<F16>(a.dst, rowpart(a, x, y)));
@@ -493,6 +495,9 @@ void fill_args(lbm_ctx* h, CollideArgs& a, int src, int dst) {
   a.b_reich = (float)c.b_reich;
   a.u_conv = (float)c.u_conv;
   a.inv_1pu = (float)(1.0 / (1.0 + c.u_conv));
+  a.sponge_x0 = c.sponge_cells > 0 ? c.nx - c.sponge_cells : c.nx;
+  a.sponge_inv_len = c.sponge_cells > 0 ? (float)(1.0 / c.sponge_cells) : 0.f;
+  a.sponge_dnu = c.sponge_cells > 0 ? (float)(c.sponge_nu - nu0) : 0.f;
   for (int k = 0; k < Q; ++k) {
     a.rs[k] = (float)(c.s[k] / DNORM[k]);
     a.rf[k] = (float)((1.0 - 0.5 * c.s[k]) / DNORM[k]);

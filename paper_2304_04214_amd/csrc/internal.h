@@ -38,6 +38,8 @@ struct CollideArgs {
   float g[3];
   float nu0, inv_nu0, y_wall, kappa, inv_kappa, b_reich;
   float u_conv, inv_1pu;
+  int sponge_x0;                 // first sponge plane (nx: no sponge)
+  float sponge_inv_len, sponge_dnu;  // 1 / sponge_cells, sponge_nu - nu0
   float rs[Q], rf[Q];  // s_k / D_k and (1 - s_k/2) / D_k for the fixed-rate moments
 };
 

@@ -279,6 +279,19 @@ __device__ __forceinline__ void block_coords(const CollideArgs& a, int e, int& x
   x = r / a.zc;
 }
 
+// Molecular relaxation time of plane x (wave-uniform): tau0, or inside the
+// outlet sponge 1/2 + 3 nu(x), nu(x) = nu0 + (nu_s - nu0) r^2,
+// r = (x - x0 + 1) / L (Sec. IV.A names the sponge; the ramp is a reading).
+struct Tau0 {
+  float tau0, tau0sq;
+};
+__device__ __forceinline__ Tau0 tau0_of_x(const CollideArgs& a, int x) {
+  if (x < a.sponge_x0) return Tau0{a.tau0, a.tau0sq};
+  const float r = (float)(x - a.sponge_x0 + 1) * a.sponge_inv_len;
+  const float t = 0.5f + 3.f * (a.nu0 + a.sponge_dnu * r * r);
+  return Tau0{t, t * t};
+}
+
 // Reichardt law u+ and du+/dy+ (Sec. II.C, Eq. (16), with log1p / expm1 so
 // that small y+ loses no digits).
 __device__ __forceinline__ void reichardt(const CollideArgs& a, float yp, float& up, float& dup) {

@@ -51,6 +51,7 @@ def _cfg(**kw):
     c.xbc = kw.get("xbc", 0)
     c.wall_model = kw.get("wall_model", 0)
     c.newton_iters = 8
+    c.sponge_cells, c.sponge_nu = kw.get("sponge_cells", 0), kw.get("sponge_nu", 0.0)
     c.tau0 = kw.get("tau0", 0.6)
     c.cs_smag = 0.1
     c.kappa, c.b_reich, c.y_wall = 0.41, 7.8, 0.5
@@ -64,7 +65,10 @@ def test_bad_configurations_are_rejected_without_a_device():
     for kw, code in [(dict(ny=3), A.LBM_ERR_SHAPE), (dict(nx=0), A.LBM_ERR_SHAPE),
                      (dict(xbc=1, nx=2), A.LBM_ERR_SHAPE), (dict(tau0=0.5), A.LBM_ERR_ARG),
                      (dict(storage=7), A.LBM_ERR_ARG), (dict(ywall=0, wall_model=1), A.LBM_ERR_ARG),
-                     (dict(nx=2048, ny=2048, nz=1024), A.LBM_ERR_SHAPE)]:
+                     (dict(nx=2048, ny=2048, nz=1024), A.LBM_ERR_SHAPE),
+                     (dict(sponge_cells=3), A.LBM_ERR_ARG),  # sponge needs the open channel
+                     (dict(xbc=1, sponge_cells=8, sponge_nu=0.1), A.LBM_ERR_ARG),  # more planes than nx - 1
+                     (dict(xbc=1, sponge_cells=3, sponge_nu=0.0), A.LBM_ERR_ARG)]:
         st = L.lbm_create(C.byref(_cfg(**kw)), buf, C.c_void_p(512), None, None, None, C.byref(h))
         assert st == code, (kw, st)
     assert L.lbm_create(None, buf, buf, None, None, None, C.byref(h)) == A.LBM_ERR_ARG

@@ -106,6 +106,8 @@ CASES = {
     "periodic_all_force": (dict(nx=5, ny=4, nz=9, ywall="periodic", xbc="periodic", wall_model=False,
                                 g=(4e-6, 1e-6, 0.0)), "f32"),
     "f16_slip_inflow_wallmodel": (dict(nx=6, ny=8, nz=70, ywall="slip", xbc="inflow", wall_model=True), "f16dev"),
+    "slip_inflow_wallmodel_sponge": (dict(nx=9, ny=8, nz=20, ywall="slip", xbc="inflow", wall_model=True,
+                                          sponge_cells=5, sponge_nu=0.02), "f32"),
 }
 
 

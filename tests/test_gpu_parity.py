@@ -62,6 +62,8 @@ PARITY_CASES = {
                                                             n_modes=40)),
     "bounceback-inflow-ny4": dict(shape=(5, 4, 66), kw=dict(ywall="bounceback", xbc="inflow", wall_model=True)),
     "slip-inflow-nz1": dict(shape=(3, 5, 1), kw=dict(ywall="slip", xbc="inflow", wall_model=True)),
+    "slip-inflow-wallmodel-sponge": dict(shape=(12, 10, 70), kw=dict(ywall="slip", xbc="inflow", wall_model=True,
+                                                                    sponge_cells=6, sponge_nu=0.02)),
     "re1000-like": dict(shape=(8, 12, 64), kw=dict(ywall="slip", xbc="inflow", wall_model=True,
                                                   tau0=0.5004270558446486, u_tau=0.004448498381757104,
                                                   n_modes=50)),
@@ -174,7 +176,7 @@ def test_nonfinite_density_is_reported():
     assert e.value.status == A.LBM_ERR_NONFINITE
 
 
-@pytest.mark.parametrize("name", ["slip-inflow-wallmodel", "periodic-smag-force"])
+@pytest.mark.parametrize("name", ["slip-inflow-wallmodel", "periodic-smag-force", "slip-inflow-wallmodel-sponge"])
 def test_fp16_deviation_storage_matches_oracle(name):
     spec = PARITY_CASES[name]
     _say("fp16 parity", name)
