@@ -52,6 +52,7 @@ typedef enum {
 enum { LBM_STORE_F32 = 0, LBM_STORE_F16DEV = 1 };
 enum { LBM_Y_PERIODIC = 0, LBM_Y_BOUNCEBACK = 1, LBM_Y_SLIP = 2 };
 enum { LBM_X_PERIODIC = 0, LBM_X_INFLOW = 1 };
+enum { LBM_OUTLET_CONVECTIVE = 0, LBM_OUTLET_ZERO_GRADIENT = 1 };
 enum { LBM_STATS_ATTACH = 1, LBM_STATS_DETACH = 2, LBM_STATS_RESET = 3, LBM_STATS_READ = 4 };
 
 /*
@@ -63,8 +64,12 @@ enum { LBM_STATS_ATTACH = 1, LBM_STATS_DETACH = 2, LBM_STATS_RESET = 3, LBM_STAT
  *              paper's slip wall (specular reflection), LBM_Y_BOUNCEBACK is
  *              halfway bounce-back; LBM_Y_PERIODIC has no walls.
  *  xbc         LBM_X_INFLOW: STG inlet at x = 0 (regularised populations,
- *              Sec. III.A, Eq. (26)-(31)) and convective outlet at x = nx-1
- *              for c_x < 0: f_i = (f_i^prev + u_conv f_i(x-1)) / (1 + u_conv).
+ *              Sec. III.A, Eq. (26)-(31)) and an outlet at x = nx-1 for the
+ *              unknown c_x < 0 populations (Sec. IV.A calls it pressure-free;
+ *              the rule is a reading):
+ *  outlet      LBM_OUTLET_CONVECTIVE: f_i = (f_i^prev + u_conv f_i(x-1)) /
+ *              (1 + u_conv); LBM_OUTLET_ZERO_GRADIENT: f_i = f_i(x-1) (the
+ *              limit u_conv -> infinity), with f(x-1) the post-streaming value.
  *  wall_model  1: Reichardt wall force in the first off-wall cells (Sec. II.C,
  *              Eq. (16)-(21)), u_tau by newton_iters Newton steps from the
  *              viscous-sublayer estimate (0: 4; in FP32 the iteration reaches
@@ -93,7 +98,7 @@ typedef struct {
   int32_t wall_model;
   int32_t newton_iters;
   int32_t sponge_cells;
-  int32_t reserved_;           /* 0 */
+  int32_t outlet;
   double tau0;
   double cs_smag;
   double s[19];

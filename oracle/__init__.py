@@ -48,7 +48,8 @@ class Cfg(C.Structure):
                 ("newton_max", C.c_int32), ("sponge_cells", C.c_int32),
                 ("newton_tol", C.c_double), ("tau0", C.c_double), ("cs_smag", C.c_double),
                 ("s", C.c_double * 19), ("kappa", C.c_double), ("b_reich", C.c_double),
-                ("y_wall", C.c_double), ("u_conv", C.c_double), ("g", C.c_double * 3), ("sponge_nu", C.c_double)]
+                ("y_wall", C.c_double), ("u_conv", C.c_double), ("g", C.c_double * 3), ("sponge_nu", C.c_double),
+                ("outlet", C.c_int32), ("pad2_", C.c_int32)]
 
 
 class Stg(C.Structure):
@@ -113,7 +114,7 @@ def _d(a):
 
 def make_cfg(nx, ny, nz, *, ywall=0, xbc=0, wall_model=0, tau0=0.52, cs_smag=0.1, rates=None,
              kappa=0.41, b_reich=7.8, y_wall=0.5, u_conv=0.1, g=(0.0, 0.0, 0.0),
-             newton_max=50, newton_tol=1e-14, sponge_cells=0, sponge_nu=0.0):
+             newton_max=50, newton_tol=1e-14, sponge_cells=0, sponge_nu=0.0, outlet=0):
     c = Cfg()
     c.nx, c.ny, c.nz = nx, ny, nz
     c.ywall, c.xbc, c.wall_model = ywall, xbc, wall_model
@@ -125,6 +126,7 @@ def make_cfg(nx, ny, nz, *, ywall=0, xbc=0, wall_model=0, tau0=0.52, cs_smag=0.1
     for a in range(3):
         c.g[a] = g[a]
     c.sponge_cells, c.sponge_nu = sponge_cells, sponge_nu
+    c.outlet = outlet
     return c
 
 

@@ -47,6 +47,8 @@
  *      c_x < 0 at x = nx-1, f(x-1) the post-streaming value of the same step.
  *  R14 inlet and wall rules both apply at inlet/wall corner cells
  *      (Algorithm 1 has two independent branches).
+ *  R20 "pressure-free" outlet, alternative reading: zero gradient,
+ *      f_i = f_i(x-1) for c_x < 0 at x = nx-1 (the limit U_c -> infinity of R13).
  *  R19 outlet sponge (Sec. IV.A names a sponge of thickness delta before the
  *      outlet but not its law): over the last L = sponge_cells planes the
  *      molecular viscosity rises as nu(x) = nu0 + (nu_s - nu0) r^2,
@@ -76,6 +78,8 @@ typedef struct {
   double u_conv;       /* outlet convection speed U_c */
   double g[3];         /* body acceleration */
   double sponge_nu;    /* molecular viscosity at the outlet plane inside the sponge */
+  int32_t outlet;      /* 0 convective (R13), 1 zero gradient (R20) */
+  int32_t pad2_;
 } oracle_cfg;
 
 typedef struct {
@@ -640,7 +644,7 @@ void boundary_rules(const oracle_cfg& cf, bool outlet, bool inlet, const R pv[19
   if (outlet) { /* convective outlet (R13) */
     for (int k = 0; k < 5; ++k) {
       const int i = OUT5[k];
-      fo[i] = (hist[k] + cf.u_conv * up[k]) / (1.0 + cf.u_conv);
+      fo[i] = (cf.outlet == 1) ? up[k] + 0.0 * hist[k] : (hist[k] + cf.u_conv * up[k]) / (1.0 + cf.u_conv);
       hist_new[k] = fo[i];
     }
   }
@@ -729,6 +733,7 @@ bool cfg_ok(const oracle_cfg* cf) {
   if (cf->wall_model == 1 && cf->ny < 3) return false;
   if (!(cf->tau0 > 0.5)) return false;
   if (cf->sponge_cells < 0 || cf->sponge_cells > cf->nx - 1) return false;
+  if (cf->outlet != 0 && cf->outlet != 1) return false;
   if (cf->sponge_cells > 0 && (cf->xbc != 1 || !(cf->sponge_nu > 0.0))) return false;
   return true;
 }

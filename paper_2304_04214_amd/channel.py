@@ -19,6 +19,7 @@ PAPER_RATES = (1.0, 1.19, 1.6, 1.0, 1.2, 1.0, 1.2, 1.0, 1.2, 1.0,
 _YWALL = {"periodic": A.Y_PERIODIC, "bounceback": A.Y_BOUNCEBACK, "slip": A.Y_SLIP}
 _XBC = {"periodic": A.X_PERIODIC, "inflow": A.X_INFLOW}
 _STORE = {"f32": A.STORE_F32, "f16dev": A.STORE_F16DEV}
+_OUTLET = {"convective": A.OUTLET_CONVECTIVE, "zero-gradient": A.OUTLET_ZERO_GRADIENT}
 
 
 def _ptr(t):
@@ -36,7 +37,7 @@ class Channel:
 
     def __init__(self, nx, ny, nz, *, tau0, storage="f32", ywall="slip", xbc="periodic", wall_model=False,
                  cs_smag=0.1, rates=None, kappa=0.41, b_reich=7.8, y_wall=0.5, u_conv=0.1, g=(0.0, 0.0, 0.0),
-                 newton_iters=4, sponge_cells=0, sponge_nu=0.0, device=None):
+                 newton_iters=4, sponge_cells=0, sponge_nu=0.0, outlet="convective", device=None):
         self.device = torch.device(device if device is not None else "cuda")
         self.nx, self.ny, self.nz = nx, ny, nz
         self.N = nx * ny * nz
@@ -55,6 +56,7 @@ class Channel:
         for a in range(3):
             cfg.g[a] = g[a]
         cfg.sponge_cells, cfg.sponge_nu = int(sponge_cells), float(sponge_nu)
+        cfg.outlet = _OUTLET[outlet]
         self.cfg = cfg
         dt = torch.float32 if storage == "f32" else torch.float16
         elems = C.c_int64()

@@ -16,8 +16,8 @@
 //    its sensitivity goes back to that row through LDS (the block holds both);
 //  * convective outlet: the outlet node at x = nx-1 reads the pulled values of
 //    the node at nx-2.  The thread of node (nx-2, y, z) does the outlet node
-//    (nx-1, y, z) first, stores dL/dhist_n and adds U_c times it to its own
-//    c_x < 0 values.
+//    (nx-1, y, z) first, stores dL/dhist_n and adds the outlet node's
+//    sensitivity to its upstream term to its own c_x < 0 values.
 // Elements of s_n that no node pulls (on the x = 0 and x = nx-1 planes of an
 // open channel) are set to zero by the thread of the node that holds them.
 //
@@ -193,7 +193,7 @@ __device__ __forceinline__ void node_adjoint(const AdjointArgs& A, AdjLds& L, in
     for (int k = 0; k < 5; ++k) {
       const int i = OUT5[k];
       const float up = pull_dir<F16>(a, g2, i, col, 0.f);
-      f[i] = (a.hist_in[(k * a.ny + y) * a.nz + z] + a.u_conv * up) * a.inv_1pu;
+      f[i] = a.out_wh * a.hist_in[(k * a.ny + y) * a.nz + z] + a.out_wu * up;
     }
   }
   float rin = 0.f;
@@ -401,9 +401,9 @@ __device__ __forceinline__ void node_adjoint(const AdjointArgs& A, AdjLds& L, in
     for (int k = 0; k < 5; ++k) {
       const int i = OUT5[k];
       const int hidx = (k * a.ny + y) * a.nz + z;
-      const float v = (gb[i] + A.eta_next[hidx]) * a.inv_1pu;  // hist_{n+1} holds these populations
-      if (mine) A.eta_prev[hidx] = v;
-      gup[k] = a.u_conv * v;
+      const float t = gb[i] + A.eta_next[hidx];  // hist_{n+1} holds these populations
+      if (mine) A.eta_prev[hidx] = a.out_wh * t;
+      gup[k] = a.out_wu * t;
       gb[i] = 0.f;
     }
   }

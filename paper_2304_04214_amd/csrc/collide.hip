@@ -216,7 +216,7 @@ __device__ __forceinline__ void node_update(const CollideArgs& a, int x, int y, 
       const int i = OUT5[k];
       const float up = pull_dir<F16>(a, g2, i, col, 0.f);
       const int hidx = (k * a.ny + y) * a.nz + z;
-      const float v = (a.hist_in[hidx] + a.u_conv * up) * a.inv_1pu;
+      const float v = a.out_wh * a.hist_in[hidx] + a.out_wu * up;
       f[i] = v;
       if (active && owned) a.hist_out[hidx] = v;
     }
@@ -493,8 +493,13 @@ void fill_args(lbm_ctx* h, CollideArgs& a, int src, int dst) {
   a.kappa = (float)c.kappa;
   a.inv_kappa = (float)(1.0 / c.kappa);
   a.b_reich = (float)c.b_reich;
-  a.u_conv = (float)c.u_conv;
-  a.inv_1pu = (float)(1.0 / (1.0 + c.u_conv));
+  if (c.outlet == LBM_OUTLET_ZERO_GRADIENT) {
+    a.out_wh = 0.f;
+    a.out_wu = 1.f;
+  } else {  // convective: (f^prev + U_c f(x-1)) / (1 + U_c)
+    a.out_wh = (float)(1.0 / (1.0 + c.u_conv));
+    a.out_wu = (float)(c.u_conv / (1.0 + c.u_conv));
+  }
   a.sponge_x0 = c.sponge_cells > 0 ? c.nx - c.sponge_cells : c.nx;
   a.sponge_inv_len = c.sponge_cells > 0 ? (float)(1.0 / c.sponge_cells) : 0.f;
   a.sponge_dnu = c.sponge_cells > 0 ? (float)(c.sponge_nu - nu0) : 0.f;

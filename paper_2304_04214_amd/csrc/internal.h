@@ -37,7 +37,7 @@ struct CollideArgs {
   float tau0, tau0sq, smag;  // smag = 18 sqrt(2) C_s^2
   float g[3];
   float nu0, inv_nu0, y_wall, kappa, inv_kappa, b_reich;
-  float u_conv, inv_1pu;
+  float out_wh, out_wu;  // outlet rule f_i = out_wh f_i^prev + out_wu f_i(x-1) for c_x < 0
   int sponge_x0;                 // first sponge plane (nx: no sponge)
   float sponge_inv_len, sponge_dnu;  // 1 / sponge_cells, sponge_nu - nu0
   float rs[Q], rf[Q];  // s_k / D_k and (1 - s_k/2) / D_k for the fixed-rate moments

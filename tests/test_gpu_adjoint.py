@@ -108,6 +108,8 @@ CASES = {
     "f16_slip_inflow_wallmodel": (dict(nx=6, ny=8, nz=70, ywall="slip", xbc="inflow", wall_model=True), "f16dev"),
     "slip_inflow_wallmodel_sponge": (dict(nx=9, ny=8, nz=20, ywall="slip", xbc="inflow", wall_model=True,
                                           sponge_cells=5, sponge_nu=0.02), "f32"),
+    "slip_inflow_zero_gradient_outlet": (dict(nx=6, ny=8, nz=20, ywall="slip", xbc="inflow", wall_model=True,
+                                              outlet="zero-gradient"), "f32"),
 }
 
 

@@ -64,6 +64,8 @@ PARITY_CASES = {
     "slip-inflow-nz1": dict(shape=(3, 5, 1), kw=dict(ywall="slip", xbc="inflow", wall_model=True)),
     "slip-inflow-wallmodel-sponge": dict(shape=(12, 10, 70), kw=dict(ywall="slip", xbc="inflow", wall_model=True,
                                                                     sponge_cells=6, sponge_nu=0.02)),
+    "slip-inflow-zero-gradient-outlet": dict(shape=(7, 10, 70), kw=dict(ywall="slip", xbc="inflow", wall_model=True,
+                                                                       outlet="zero-gradient")),
     "re1000-like": dict(shape=(8, 12, 64), kw=dict(ywall="slip", xbc="inflow", wall_model=True,
                                                   tau0=0.5004270558446486, u_tau=0.004448498381757104,
                                                   n_modes=50)),

@@ -162,8 +162,8 @@ def test_periodic_momentum_gain_equals_body_force():
     assert np.abs(p1 - p0 - 5 * g * mass).max() < 1e-13 * mass
 
 
-def _uniform_channel(ywall, nx=6, ny=6, nz=4, U=0.08):
-    cfg = O.make_cfg(nx, ny, nz, ywall=ywall, xbc=1, wall_model=0, tau0=0.52, cs_smag=0.1, u_conv=U)
+def _uniform_channel(ywall, nx=6, ny=6, nz=4, U=0.08, outlet=0):
+    cfg = O.make_cfg(nx, ny, nz, ywall=ywall, xbc=1, wall_model=0, tau0=0.52, cs_smag=0.1, u_conv=U, outlet=outlet)
     u_rans = np.zeros((3, ny))
     u_rans[0] = U
     mt = S.mode_table(8, ny / 2)
@@ -182,6 +182,27 @@ def test_uniform_flow_is_preserved_by_slip_walls_inlet_and_outlet():
     assert st == O.OK
     assert np.abs(f2 - f).max() < 1e-15
     assert np.abs(h2 - hist).max() < 1e-15
+
+
+def test_uniform_flow_is_preserved_by_the_zero_gradient_outlet():
+    cfg, stg, f, hist = _uniform_channel(2, outlet=1)
+    st, f2, _ = O.run(cfg, f, hist, 0, 10, stg=stg)
+    assert st == O.OK
+    assert np.abs(f2 - f).max() < 1e-15
+
+
+def test_zero_gradient_outlet_is_the_fast_convection_limit():
+    """f_i = f_i(x-1) is the limit U_c -> infinity of (f_i^prev + U_c f_i(x-1)) / (1 + U_c)."""
+    cfg0, stg, f, hist = _uniform_channel(2, nx=7, outlet=1)
+    du, dp = S.perturbations(7, 6, 4, seed_offset=5)
+    f, hist = O.init(cfg0, 0.08 * np.array([1.0, 0, 0])[:, None, None, None] + 1e-2 * du, pert=dp, eps=0.05)
+    zg = O.run(cfg0, f, hist, 0, 6, stg=stg)[1]
+    fast = O.make_cfg(7, 6, 4, ywall=2, xbc=1, wall_model=0, tau0=0.52, cs_smag=0.1, u_conv=1e9)
+    conv = O.run(fast, f, hist, 0, 6, stg=stg)[1]
+    slow = O.make_cfg(7, 6, 4, ywall=2, xbc=1, wall_model=0, tau0=0.52, cs_smag=0.1, u_conv=0.1)
+    other = O.run(slow, f, hist, 0, 6, stg=stg)[1]
+    assert np.abs(conv - zg).max() < 1e-9
+    assert np.abs(other - zg).max() > 1e-5  # the rules do differ
 
 
 def test_statistics_of_a_uniform_flow():
