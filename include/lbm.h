@@ -53,7 +53,7 @@ enum { LBM_STORE_F32 = 0, LBM_STORE_F16DEV = 1 };
 enum { LBM_Y_PERIODIC = 0, LBM_Y_BOUNCEBACK = 1, LBM_Y_SLIP = 2 };
 enum { LBM_X_PERIODIC = 0, LBM_X_INFLOW = 1 };
 enum { LBM_OUTLET_CONVECTIVE = 0, LBM_OUTLET_ZERO_GRADIENT = 1 };
-enum { LBM_STATS_ATTACH = 1, LBM_STATS_DETACH = 2, LBM_STATS_RESET = 3, LBM_STATS_READ = 4 };
+enum { LBM_STATS_ATTACH = 1, LBM_STATS_DETACH = 2, LBM_STATS_RESET = 3, LBM_STATS_READ = 4, LBM_STATS_READ_WALL = 5 };
 
 /*
  * Problem statement (Sec. II, Sec. IV.A).
@@ -216,6 +216,9 @@ lbm_status lbm_import_f32(lbm_handle h, const float* in);
  *   READ    synchronise; host_out[n_planes][ny][9] = the means over z and the
  *           sampled steps; *n_samples = number of steps accumulated.  Returns
  *           any latched device error.
+ *   READ_WALL  (wall_model = 1) synchronise; host_out[2][nx] = the mean over z
+ *           and the sampled steps of the wall law's u_tau (Eq. (20)) in the first
+ *           off-wall cells, bottom (y = 0) then top (y = ny-1), at every x.
  */
 lbm_status lbm_stats(lbm_handle h, int32_t op, const int32_t* x_planes, int32_t n_planes, double* host_out,
                      int64_t* n_samples);

@@ -89,12 +89,12 @@ def lib():
             "oracle_reichardt_inflow": (None, [P, D, P]),
             "oracle_init": (I, [P, P, P, P, D, P, P]),
             "oracle_stream_only": (I, [P, P, P]),
-            "oracle_step": (I, [P, P, D, P, P, P, P, P, I, P]),
+            "oracle_step": (I, [P, P, D, P, P, P, P, P, I, P, P]),
             "oracle_step_uin": (I, [P, P, P, P, P, P, P, I, P]),
             "oracle_adjoint_step": (I, [P, P, D, P, P, P, P, P, P, I, P, P, P, P, P, P]),
             "oracle_step_nodes": (I, [P, P, D, P, P, C.c_int64, P, P, P]),
             "oracle_macro": (None, [P, P, P, P]),
-            "oracle_run": (I, [P, P, D, I, P, P, P, I, P]),
+            "oracle_run": (I, [P, P, D, I, P, P, P, I, P, P]),
             "oracle_num_threads": (I, []),
         }
         for name, (res, args) in sig.items():
@@ -269,14 +269,15 @@ def stream_only(cfg, f):
     return out
 
 
-def step(cfg, f, hist, t_next, stg=None, planes=None, acc=None):
-    """One step; returns (status, f_new, hist_new).  acc[p,ny,9] accumulates sums in place."""
+def step(cfg, f, hist, t_next, stg=None, planes=None, acc=None, wall_acc=None):
+    """One step; returns (status, f_new, hist_new).  acc[p,ny,9] accumulates sums in place;
+    wall_acc[2, nx] (bottom, top) accumulates the sums over z of the wall law's u_tau."""
     out = np.empty(shape(cfg))
     hist_out = hist.copy() if hist is not None else None
     pl = None if planes is None else np.ascontiguousarray(planes, dtype=np.int32)
     st = lib().oracle_step(C.byref(cfg), _ref(stg.c if stg is not None else None), float(t_next),
                            _p(_d(f)), _p(out), _p(None if hist is None else _d(hist)), _p(hist_out),
-                           _p(pl), 0 if pl is None else len(pl), _p(acc))
+                           _p(pl), 0 if pl is None else len(pl), _p(acc), _p(wall_acc))
     return st, out, hist_out
 
 
@@ -353,13 +354,13 @@ def gradient_run(cfg, stg, f0, hist0, t0, nsteps, planes, coef, sample_from=1, w
     return out
 
 
-def run(cfg, f, hist, t0, nsteps, stg=None, planes=None, acc=None):
-    """nsteps steps from time t0; returns (status, f, hist) as new arrays."""
+def run(cfg, f, hist, t0, nsteps, stg=None, planes=None, acc=None, wall_acc=None):
+    """nsteps steps from time t0; returns (status, f, hist) as new arrays (acc, wall_acc as for step)."""
     f = _d(f).copy()
     hist = None if hist is None else _d(hist).copy()
     pl = None if planes is None else np.ascontiguousarray(planes, dtype=np.int32)
     st = lib().oracle_run(C.byref(cfg), _ref(stg.c if stg is not None else None), float(t0), int(nsteps),
-                          _p(f), _p(hist), _p(pl), 0 if pl is None else len(pl), _p(acc))
+                          _p(f), _p(hist), _p(pl), 0 if pl is None else len(pl), _p(acc), _p(wall_acc))
     return st, f, hist
 
 

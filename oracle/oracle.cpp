@@ -685,7 +685,7 @@ bool is_wall_cell(const oracle_cfg& cf, int y) {
  */
 template <class R>
 int node_core(const oracle_cfg& cf, int x, int y, const R f[19], const R f2[19], const R& cs_smag, R out[19],
-              R u_stat[3]) {
+              R u_stat[3], R* utau = nullptr) {
   R rho, uw[3];
   pre_force_velocity(f, &rho, uw);
   R F[3] = {rho * cf.g[0], rho * cf.g[1], rho * cf.g[2]}; /* R9 */
@@ -695,7 +695,7 @@ int node_core(const oracle_cfg& cf, int x, int y, const R f[19], const R f2[19],
     R rho2, u2[3];
     pre_force_velocity(f2, &rho2, u2);
     R Fw[3];
-    st = wall_force(cf, rho, uw, u2, top, Fw, (R*)nullptr);
+    st = wall_force(cf, rho, uw, u2, top, Fw, utau);
     for (int a = 0; a < 3; ++a) F[a] = F[a] + Fw[a];
   }
   R tau;
@@ -705,9 +705,10 @@ int node_core(const oracle_cfg& cf, int x, int y, const R f[19], const R f2[19],
 
 int wall_neighbour_row(const oracle_cfg& cf, int y) { return (y == cf.ny - 1) ? y - 1 : y + 1; }
 
-/* One node of Algorithm 1: boundaries, wall branch, stream-collide.  Returns status. */
+/* One node of Algorithm 1: boundaries, wall branch, stream-collide.  Returns
+   status; *utau (optional) receives the wall law's u_tau (0 off the wall rows). */
 int node_update(const Ctx& c, int x, int y, int z, double out[19], double hist_new[5], bool* is_outlet,
-                double u_stat[3]) {
+                double u_stat[3], double* utau = nullptr) {
   const oracle_cfg& cf = *c.cfg;
   double f[19], f2[19];
   post_boundary(c, x, y, z, f, hist_new, is_outlet);
@@ -718,7 +719,8 @@ int node_update(const Ctx& c, int x, int y, int z, double out[19], double hist_n
   } else {
     for (int i = 0; i < 19; ++i) f2[i] = 0.0;
   }
-  int st = node_core(cf, x, y, f, f2, cf.cs_smag, out, u_stat);
+  if (utau) *utau = 0.0;
+  int st = node_core(cf, x, y, f, f2, cf.cs_smag, out, u_stat, utau);
   double rho = 0.0;
   for (int i = 0; i < 19; ++i) rho += f[i];
   if (!(rho > 0.0) || !std::isfinite(rho)) st = OR_ERR_NONFINITE;
@@ -857,7 +859,7 @@ int oracle_stream_only(const oracle_cfg* cfg, const double* fin, double* fout) {
  * force-corrected velocity.
  */
 int step_core(const oracle_cfg* cfg, const double* uin, const double* fin, double* fout, const double* hist_in,
-              double* hist_out, const int32_t* planes, int32_t n_planes, double* acc) {
+              double* hist_out, const int32_t* planes, int32_t n_planes, double* acc, double* wall_acc) {
   const int nx = cfg->nx, ny = cfg->ny, nz = cfg->nz;
   Ctx c{cfg, fin, hist_in, uin, (size_t)nx * ny * nz, nx, ny, nz};
   std::vector<int> plane_of(nx, -1);
@@ -867,12 +869,13 @@ int step_core(const oracle_cfg* cfg, const double* uin, const double* fin, doubl
 #pragma omp parallel for collapse(2) schedule(static)
   for (int x = 0; x < nx; ++x)
     for (int y = 0; y < ny; ++y) {
-      double sums[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+      double sums[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0}, ut_sum = 0.0;
       int st_local = OR_OK;
       for (int z = 0; z < nz; ++z) {
-        double out[19], hn[5], u[3];
+        double out[19], hn[5], u[3], ut;
         bool is_out;
-        int st = node_update(c, x, y, z, out, hn, &is_out, u);
+        int st = node_update(c, x, y, z, out, hn, &is_out, u, &ut);
+        ut_sum += ut;
         if (st != OR_OK) st_local = st;
         for (int i = 0; i < 19; ++i) fout[c.at(i, x, y, z)] = out[i];
         if (is_out)
@@ -889,6 +892,8 @@ int step_core(const oracle_cfg* cfg, const double* uin, const double* fin, doubl
       }
       if (plane_of[x] >= 0 && acc)
         for (int k = 0; k < 9; ++k) acc[((size_t)plane_of[x] * ny + y) * 9 + k] += sums[k];
+      /* wall statistics: sum over z of u_tau in the first off-wall rows [bottom, top][x] */
+      if (wall_acc && is_wall_cell(*cfg, y)) wall_acc[(y == ny - 1 ? nx : 0) + x] += ut_sum;
       if (st_local != OR_OK) {
 #pragma omp critical
         st_err = st_local;
@@ -898,7 +903,8 @@ int step_core(const oracle_cfg* cfg, const double* uin, const double* fin, doubl
 }
 
 int oracle_step(const oracle_cfg* cfg, const oracle_stg* stg, double t_next, const double* fin, double* fout,
-                const double* hist_in, double* hist_out, const int32_t* planes, int32_t n_planes, double* acc) {
+                const double* hist_in, double* hist_out, const int32_t* planes, int32_t n_planes, double* acc,
+                double* wall_acc) {
   if (!cfg_ok(cfg) || !fin || !fout) return OR_ERR_ARG;
   if (cfg->xbc == 1 && (!stg || !hist_in || !hist_out)) return OR_ERR_ARG;
   std::vector<double> uin;
@@ -907,7 +913,8 @@ int oracle_step(const oracle_cfg* cfg, const oracle_stg* stg, double t_next, con
     uin.resize((size_t)3 * cfg->ny * cfg->nz);
     st_all = stg_plane(*cfg, *stg, t_next, uin.data(), nullptr);
   }
-  int st = step_core(cfg, uin.empty() ? nullptr : uin.data(), fin, fout, hist_in, hist_out, planes, n_planes, acc);
+  int st = step_core(cfg, uin.empty() ? nullptr : uin.data(), fin, fout, hist_in, hist_out, planes, n_planes, acc,
+                     wall_acc);
   return st != OR_OK ? st : st_all;
 }
 
@@ -916,7 +923,7 @@ int oracle_step_uin(const oracle_cfg* cfg, const double* uin, const double* fin,
                     const double* hist_in, double* hist_out, const int32_t* planes, int32_t n_planes, double* acc) {
   if (!cfg_ok(cfg) || !fin || !fout) return OR_ERR_ARG;
   if (cfg->xbc == 1 && (!uin || !hist_in || !hist_out)) return OR_ERR_ARG;
-  return step_core(cfg, uin, fin, fout, hist_in, hist_out, planes, n_planes, acc);
+  return step_core(cfg, uin, fin, fout, hist_in, hist_out, planes, n_planes, acc, nullptr);
 }
 
 /*
@@ -1106,7 +1113,7 @@ void oracle_macro(const oracle_cfg* cfg, const double* f, double* rho, double* u
 extern "C" {
 /* nsteps steps from t0 (STG time t0 + n + 1 for step n); f and hist updated in place. */
 int oracle_run(const oracle_cfg* cfg, const oracle_stg* stg, double t0, int32_t nsteps, double* f, double* hist,
-               const int32_t* planes, int32_t n_planes, double* acc) {
+               const int32_t* planes, int32_t n_planes, double* acc, double* wall_acc) {
   if (!cfg_ok(cfg) || !f) return OR_ERR_ARG;
   const size_t N = (size_t)cfg->nx * cfg->ny * cfg->nz;
   std::vector<double> tmp(19 * N), htmp(hist ? (size_t)5 * cfg->ny * cfg->nz : 0);
@@ -1114,7 +1121,7 @@ int oracle_run(const oracle_cfg* cfg, const oracle_stg* stg, double t0, int32_t 
   for (int n = 0; n < nsteps; ++n) {
     if (hist) std::memcpy(htmp.data(), hist, htmp.size() * sizeof(double));
     int st = oracle_step(cfg, stg, t0 + n + 1, f, tmp.data(), hist, hist ? htmp.data() : nullptr, planes,
-                         n_planes, acc);
+                         n_planes, acc, wall_acc);
     if (st != OR_OK) st_all = st;
     std::memcpy(f, tmp.data(), 19 * N * sizeof(double));
     if (hist) std::memcpy(hist, htmp.data(), htmp.size() * sizeof(double));

@@ -10,7 +10,7 @@ STORE_F32, STORE_F16DEV = 0, 1
 Y_PERIODIC, Y_BOUNCEBACK, Y_SLIP = 0, 1, 2
 X_PERIODIC, X_INFLOW = 0, 1
 OUTLET_CONVECTIVE, OUTLET_ZERO_GRADIENT = 0, 1
-STATS_ATTACH, STATS_DETACH, STATS_RESET, STATS_READ = 1, 2, 3, 4
+STATS_ATTACH, STATS_DETACH, STATS_RESET, STATS_READ, STATS_READ_WALL = 1, 2, 3, 4, 5
 MAX_MODES = 1024
 
 EXPORTED = [

@@ -223,6 +223,14 @@ class Channel:
                 "lbm_stats read")
         return out, n.value
 
+    def stats_read_wall(self):
+        """Means over z and sampled steps of the wall law's u_tau: array [2, nx] (bottom, top), n_samples."""
+        out = np.zeros((2, self.nx))
+        n = C.c_int64()
+        A.check(A.lib().lbm_stats(self._h, A.STATS_READ_WALL, None, 0, out.ctypes.data_as(C.c_void_p),
+                                  C.byref(n)), "lbm_stats read wall")
+        return out, n.value
+
     # ---- adjoint ----
     def set_cs_smag(self, cs):
         A.check(A.lib().lbm_set_cs_smag(self._h, float(cs)), "lbm_set_cs_smag")

@@ -244,6 +244,7 @@ lbm_status lbm_destroy(lbm_handle h) {
   (void)hipStreamSynchronize(h->stream);
   free_tables(h);
   if (h->d_stats) (void)hipFree(h->d_stats);
+  if (h->d_wall_acc) (void)hipFree(h->d_wall_acc);
   if (h->d_plane_of_x) (void)hipFree(h->d_plane_of_x);
   if (h->d_blist_int) (void)hipFree(h->d_blist_int);
   if (h->d_blist_bnd) (void)hipFree(h->d_blist_bnd);
@@ -402,6 +403,8 @@ lbm_status lbm_stats(lbm_handle h, int32_t op, const int32_t* x_planes, int32_t 
       const size_t bytes = sizeof(double) * (size_t)n_planes * ny * h->zc * 9;
       HIPCHK(hipMalloc(&h->d_stats, bytes));
       HIPCHK(hipMemsetAsync(h->d_stats, 0, bytes, h->stream));
+      if (h->cfg.wall_model && !h->d_wall_acc) HIPCHK(hipMalloc(&h->d_wall_acc, sizeof(double) * 2 * nx * h->zc));
+      if (h->d_wall_acc) HIPCHK(hipMemsetAsync(h->d_wall_acc, 0, sizeof(double) * 2 * nx * h->zc, h->stream));
       HIPCHK(hipMemcpyAsync(h->d_plane_of_x, map.data(), sizeof(int) * nx, hipMemcpyHostToDevice, h->stream));
       HIPCHK(hipStreamSynchronize(h->stream));
       h->n_planes = n_planes;
@@ -422,6 +425,7 @@ lbm_status lbm_stats(lbm_handle h, int32_t op, const int32_t* x_planes, int32_t 
       if (!h->d_stats) return LBM_ERR_STATE;
       const size_t bytes = sizeof(double) * (size_t)h->n_planes * ny * h->zc * 9;
       HIPCHK(hipMemsetAsync(h->d_stats, 0, bytes, h->stream));
+      if (h->d_wall_acc) HIPCHK(hipMemsetAsync(h->d_wall_acc, 0, sizeof(double) * 2 * nx * h->zc, h->stream));
       h->n_samples = 0;
       return LBM_OK;
     }
@@ -441,6 +445,23 @@ lbm_status lbm_stats(lbm_handle h, int32_t op, const int32_t* x_planes, int32_t 
             for (int c = 0; c < h->zc; ++c) acc += raw[(((size_t)p * ny + y) * h->zc + c) * 9 + k];
             host_out[((size_t)p * ny + y) * 9 + k] = denom > 0 ? acc / denom : 0.0;
           }
+      if (n_samples) *n_samples = h->n_samples;
+      return st;
+    }
+    case LBM_STATS_READ_WALL: {
+      if (!h->d_wall_acc) return LBM_ERR_STATE;
+      if (!host_out) return LBM_ERR_ARG;
+      const size_t cnt = (size_t)2 * nx * h->zc;
+      std::vector<double> raw(cnt);
+      HIPCHK(hipMemcpyAsync(raw.data(), h->d_wall_acc, sizeof(double) * cnt, hipMemcpyDeviceToHost, h->stream));
+      lbm_status st = take_error(h);
+      const double denom = (double)h->n_samples * h->cfg.nz;
+      for (int w = 0; w < 2; ++w)
+        for (int x = 0; x < nx; ++x) {
+          double acc = 0.0;  // fixed-order sum over the z-chunks
+          for (int c = 0; c < h->zc; ++c) acc += raw[((size_t)w * nx + x) * h->zc + c];
+          host_out[(size_t)w * nx + x] = denom > 0 ? acc / denom : 0.0;
+        }
       if (n_samples) *n_samples = h->n_samples;
       return st;
     }

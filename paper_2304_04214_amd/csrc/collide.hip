@@ -34,9 +34,10 @@ namespace {
 // from a fixed number of Newton steps on u_tau u+(y u_tau / nu0) = |u_hat|,
 // F_w = -sign(u_hat) rho u_tau^2 e_x.  The wall normal is along y.
 __device__ __forceinline__ void wall_force(const CollideArgs& a, float rho, float uwx, float uwz, float u2x,
-                                           float u2z, float& fx, float& fz) {
+                                           float u2z, float& fx, float& fz, float& ut_out) {
   fx = 0.f;
   fz = 0.f;
+  ut_out = 0.f;
   const float tn2 = u2x * u2x + u2z * u2z;
   if (!(tn2 > 0.f)) return;
   const float itn = 1.f / sqrtf(tn2);
@@ -47,6 +48,7 @@ __device__ __forceinline__ void wall_force(const CollideArgs& a, float rho, floa
   const float tw = (uhat > 0.f ? -1.f : 1.f) * rho * ut * ut;
   fx = tw * ex;
   fz = tw * ez;
+  ut_out = ut;
 }
 
 // MRT collision with Guo forcing in moment space and the Smagorinsky
@@ -253,11 +255,17 @@ __device__ __forceinline__ void node_update(const CollideArgs& a, int x, int y, 
       const bool wb = bot && y == 0, wt = top && y == a.ny - 1;
       if (wb || wt) {
         const int w = wb ? 0 : 1;
-        float fwx, fwz;
-        wall_force(a, rho, jx * ir, jz * ir, lds_u2[w][0][lane], lds_u2[w][1][lane], fwx, fwz);
+        float fwx, fwz, ut;
+        wall_force(a, rho, jx * ir, jz * ir, lds_u2[w][0][lane], lds_u2[w][1][lane], fwx, fwz, ut);
         Fx += fwx;
         Fz += fwz;
         force = true;
+        if (a.wall_acc) {  // wall statistics: sum over the wave's z of u_tau (FP64, one writer per slot)
+          double v = active ? (double)ut : 0.0;
+#pragma unroll
+          for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, ZT);
+          if (lane == 0) a.wall_acc[((size_t)w * a.nx + x) * a.zc + zci] += v;
+        }
       }
     }
   }
@@ -468,6 +476,7 @@ void fill_args(lbm_ctx* h, CollideArgs& a, int src, int dst) {
   a.hist_out = h->hist[dst];
   a.u_in = h->stg_bound ? h->stg.u_in : nullptr;
   a.stats = h->d_stats;
+  a.wall_acc = h->stats_on ? h->d_wall_acc : nullptr;
   a.plane_of_x = h->d_plane_of_x;
   a.err = h->d_err;
   a.nx = c.nx;
@@ -534,6 +543,7 @@ hipError_t launch_step_explicit(lbm_ctx* h, const void* src, void* dst, const fl
   a.hist_out = hist_out;
   a.u_in = u_in;
   a.stats_on = 0;
+  a.wall_acc = nullptr;
   const bool f16 = h->cfg.storage == LBM_STORE_F16DEV;
   if (h->n_bnd > 0) {
     if (f16)

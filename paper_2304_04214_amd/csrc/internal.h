@@ -30,6 +30,7 @@ struct CollideArgs {
   float* hist_out;        // [5][ny][nz]
   const float* u_in;      // [3][ny][nz]
   double* stats;          // [n_planes][ny][zc][9]
+  double* wall_acc;       // [2][nx][zc] sums of u_tau in the first off-wall rows, or null
   const int* plane_of_x;  // [nx], -1 when not sampled
   int* err;
   int nx, ny, nz, zc, yg, nblocks;
@@ -96,6 +97,7 @@ struct lbm_ctx {
   // with the general kernel alone: one launch over all blocks.
   bool split = false;
   double* d_stats = nullptr;
+  double* d_wall_acc = nullptr;  // [2][nx][zc], with the wall model
   int n_planes = 0;
   std::vector<int> plane_of_x;  // host copy of d_plane_of_x
   int stats_on = 0;

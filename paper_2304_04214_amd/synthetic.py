@@ -45,6 +45,8 @@ WORKLOADS = {
     "c5a": dict(nx=512, ny=64, nz=128, re_tau=1000.0, u_tau=0.004448498381757104,
                 tau0=0.5004270558446486, n_modes=300, steps=2000, ywall=2, storage="f16dev"),
 }
+# u_tau of the centreline speed U_C at each friction Reynolds number (u_tau u+(Re_tau) = U_C, Reichardt law).
+U_TAU_OF_RE = {1000.0: 0.004448498381757104, 2000.0: 0.004137851781451391, 5200.0: 0.0037741807439038936}
 U_C = 0.1      # centreline speed, lattice units
 CS_SMAG = 0.1  # C_s; C_smag = C_s^2 = 0.01 (Sec. IV.A)
 

@@ -129,6 +129,23 @@ def test_statistics_match_oracle():
     assert err <= TOL32
 
 
+@pytest.mark.parametrize("storage", ["f32", "f16dev"])
+def test_wall_statistics_match_oracle(storage):
+    """Mean over z and steps of the wall law's u_tau at every x, both walls."""
+    c = Case(9, 10, 70, ywall="slip", xbc="inflow", wall_model=True, n_modes=30, storage=storage)
+    c.ch.stats_attach([4])
+    c.ch.step(12)
+    wall, n = c.ch.stats_read_wall()
+    assert n == 12
+    acc = np.zeros((2, c.nx))
+    st, _, _ = O.run(c.ocfg, c.f_or, c.hist_or, 0, 12, stg=c.stg_or, wall_acc=acc)
+    assert st == O.OK
+    ref = acc / (12 * c.nz)
+    err = np.abs(wall - ref).max() / np.abs(ref).max()
+    _say("wall stats (%s) rel err %.3e" % (storage, err))
+    assert err <= (1e-5 if storage == "f32" else 2e-3)
+
+
 @pytest.mark.parametrize("t", [0.0, 1.0, 137.0, 5000.0])
 def test_stg_plane_matches_oracle(t):
     c = Case(4, 10, 70, ywall="slip", xbc="inflow", wall_model=True, n_modes=300, amp_scale=3.0)
@@ -238,3 +255,14 @@ def test_fp16_mean_profiles_long_horizon():
         euv = np.abs(m[..., 6] - m[..., 0] * m[..., 1] - uv_ref).max() / scale
         _say("%s: U profile err %.3e, <u'v'> err %.3e (of max|R12|)" % (storage, eU, euv))
         assert eU <= bound and euv <= bound
+
+
+def test_recovery_run_executes():
+    """The inflow-recovery driver on the H = 20 channel for one domain-through time
+    (statistics from the start): finite results, u_tau / u_theory near 1."""
+    from paper_2304_04214_amd import recovery
+    r = recovery.run(1000.0, 20, periods=1, stats_from=0)
+    ratio = np.asarray(r["u_tau_ratio"])
+    _say("recovery: u_tau ratio range %.3f .. %.3f" % (ratio.min(), ratio.max()))
+    assert np.all(np.isfinite(ratio)) and np.abs(ratio - 1).max() < 0.2
+    assert all(np.isfinite(p["uv_plus_err_l2"]) for p in r["planes"])

@@ -236,3 +236,16 @@ def test_step_nodes_matches_full_step():
     st, out, _ = O.step_nodes(cfg, f, hist, 1.0, nodes, stg=stg)
     assert st == O.OK
     assert np.array_equal(out, full.reshape(19, -1)[:, nodes])
+
+
+def test_wall_statistics_of_a_uniform_flow():
+    """One step from a uniform state: every first off-wall cell sees u_w = u_2 = U, so
+    the wall statistics hold nz u_tau(U) at every x for both walls."""
+    nx, ny, nz, U = 6, 6, 4, 0.08
+    cfg, stg, f, hist = _uniform_channel(2, nx=nx, ny=ny, nz=nz, U=U)
+    cfg.wall_model = 1
+    wall = np.zeros((2, nx))
+    st, _, _ = O.step(cfg, f, hist, 1.0, stg=stg, wall_acc=wall)
+    assert st == O.OK
+    st, ut = O.utau(cfg, U)
+    assert np.allclose(wall, nz * ut, rtol=1e-14, atol=0)
