@@ -53,6 +53,7 @@ enum { LBM_STORE_F32 = 0, LBM_STORE_F16DEV = 1 };
 enum { LBM_Y_PERIODIC = 0, LBM_Y_BOUNCEBACK = 1, LBM_Y_SLIP = 2 };
 enum { LBM_X_PERIODIC = 0, LBM_X_INFLOW = 1 };
 enum { LBM_OUTLET_CONVECTIVE = 0, LBM_OUTLET_ZERO_GRADIENT = 1 };
+enum { LBM_WALL_REICHARDT = 0, LBM_WALL_MUSKER = 1 };
 enum { LBM_STATS_ATTACH = 1, LBM_STATS_DETACH = 2, LBM_STATS_RESET = 3, LBM_STATS_READ = 4, LBM_STATS_READ_WALL = 5 };
 
 /*
@@ -70,6 +71,13 @@ enum { LBM_STATS_ATTACH = 1, LBM_STATS_DETACH = 2, LBM_STATS_RESET = 3, LBM_STAT
  *  outlet      LBM_OUTLET_CONVECTIVE: f_i = (f_i^prev + u_conv f_i(x-1)) /
  *              (1 + u_conv); LBM_OUTLET_ZERO_GRADIENT: f_i = f_i(x-1) (the
  *              limit u_conv -> infinity), with f(x-1) the post-streaming value.
+ *  wall_law    the law of the wall in Eq. (20): LBM_WALL_REICHARDT (Eq. (16),
+ *              with kappa and b_reich) or LBM_WALL_MUSKER (the explicit profile of
+ *              Musker's law that Sec. II.C names as the alternative:
+ *              u+ = 5.424 atan((2y+ - 8.15)/16.7) + log10((y+ + 10.6)^9.6 /
+ *              (y+^2 - 8.15y+ + 86)^2) + C, with C = -3.5113 so that u+(0) = 0;
+ *              the rounded -3.52 often printed would leave no positive u_tau
+ *              below y+ = 0.009).
  *  wall_model  1: Reichardt wall force in the first off-wall cells (Sec. II.C,
  *              Eq. (16)-(21)), u_tau by newton_iters Newton steps from the
  *              viscous-sublayer estimate (0: 4; in FP32 the iteration reaches
@@ -99,6 +107,8 @@ typedef struct {
   int32_t newton_iters;
   int32_t sponge_cells;
   int32_t outlet;
+  int32_t wall_law;
+  int32_t reserved_;           /* 0 */
   double tau0;
   double cs_smag;
   double s[19];

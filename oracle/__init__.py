@@ -49,7 +49,7 @@ class Cfg(C.Structure):
                 ("newton_tol", C.c_double), ("tau0", C.c_double), ("cs_smag", C.c_double),
                 ("s", C.c_double * 19), ("kappa", C.c_double), ("b_reich", C.c_double),
                 ("y_wall", C.c_double), ("u_conv", C.c_double), ("g", C.c_double * 3), ("sponge_nu", C.c_double),
-                ("outlet", C.c_int32), ("pad2_", C.c_int32)]
+                ("outlet", C.c_int32), ("wall_law", C.c_int32)]
 
 
 class Stg(C.Structure):
@@ -81,6 +81,8 @@ def lib():
             "oracle_tau_eff": (D, [D, D, D, D]),
             "oracle_uplus": (D, [D, D, D]),
             "oracle_duplus": (D, [D, D, D]),
+            "oracle_uplus_musker": (D, [D]),
+            "oracle_duplus_musker": (D, [D]),
             "oracle_utau": (I, [P, D, P]),
             "oracle_wall_force": (I, [P, D, P, P, I, P, P]),
             "oracle_inlet_node": (None, [P, P, P, P]),
@@ -114,7 +116,7 @@ def _d(a):
 
 def make_cfg(nx, ny, nz, *, ywall=0, xbc=0, wall_model=0, tau0=0.52, cs_smag=0.1, rates=None,
              kappa=0.41, b_reich=7.8, y_wall=0.5, u_conv=0.1, g=(0.0, 0.0, 0.0),
-             newton_max=50, newton_tol=1e-14, sponge_cells=0, sponge_nu=0.0, outlet=0):
+             newton_max=50, newton_tol=1e-14, sponge_cells=0, sponge_nu=0.0, outlet=0, wall_law=0):
     c = Cfg()
     c.nx, c.ny, c.nz = nx, ny, nz
     c.ywall, c.xbc, c.wall_model = ywall, xbc, wall_model
@@ -127,6 +129,7 @@ def make_cfg(nx, ny, nz, *, ywall=0, xbc=0, wall_model=0, tau0=0.52, cs_smag=0.1
         c.g[a] = g[a]
     c.sponge_cells, c.sponge_nu = sponge_cells, sponge_nu
     c.outlet = outlet
+    c.wall_law = wall_law
     return c
 
 
@@ -199,6 +202,14 @@ def tau_eff(Qhalf, rho, tau0, cs):
 
 def uplus(yp, kappa=0.41, B=7.8):
     return lib().oracle_uplus(float(yp), kappa, B)
+
+
+def uplus_musker(yp):
+    return lib().oracle_uplus_musker(float(yp))
+
+
+def duplus_musker(yp):
+    return lib().oracle_duplus_musker(float(yp))
 
 
 def duplus(yp, kappa=0.41, B=7.8):

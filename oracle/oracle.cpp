@@ -49,6 +49,15 @@
  *      (Algorithm 1 has two independent branches).
  *  R20 "pressure-free" outlet, alternative reading: zero gradient,
  *      f_i = f_i(x-1) for c_x < 0 at x = nx-1 (the limit U_c -> infinity of R13).
+ *  R21 Musker's law of the wall (Sec. II.C names it as the alternative to the
+ *      Reichardt law, by citation): the explicit profile
+ *      u+ = 5.424 atan((2y+ - 8.15)/16.7) + log10((y+ + 10.6)^9.6 / (y+^2 - 8.15y+ + 86)^2) + C
+ *      with C the constant that gives u+(0) = 0 (C = -3.5113; the rounded -3.52
+ *      usually printed leaves u+(0) = -0.0087, and then u_tau u+ = |u_hat| has no
+ *      positive root once y+ < 0.009).  Written as differences from y+ = 0,
+ *      5.424 [atan(t) - atan(t0)] + (9.6 ln(1 + y+/10.6) - 2 ln(1 + y+(y+ - 8.15)/86)) / ln 10,
+ *      t = (2y+ - 8.15)/16.7, t0 = t(0), with atan(t) - atan(t0) = atan2(t - t0, 1 + t t0)
+ *      and t - t0 = 2y+/16.7: every term is O(y+) at small y+, free of cancellation.
  *  R19 outlet sponge (Sec. IV.A names a sponge of thickness delta before the
  *      outlet but not its law): over the last L = sponge_cells planes the
  *      molecular viscosity rises as nu(x) = nu0 + (nu_s - nu0) r^2,
@@ -79,7 +88,7 @@ typedef struct {
   double g[3];         /* body acceleration */
   double sponge_nu;    /* molecular viscosity at the outlet plane inside the sponge */
   int32_t outlet;      /* 0 convective (R13), 1 zero gradient (R20) */
-  int32_t pad2_;
+  int32_t wall_law;    /* 0 Reichardt (R6), 1 Musker (R21) */
 } oracle_cfg;
 
 typedef struct {
@@ -263,6 +272,15 @@ template <int K> Dual<K> exp(const Dual<K>& a) { const double e = std::exp(a.v);
 template <int K> Dual<K> log(const Dual<K>& a) { return chain(a, std::log(a.v), 1.0 / a.v); }
 template <int K> Dual<K> log1p(const Dual<K>& a) { return chain(a, std::log1p(a.v), 1.0 / (1.0 + a.v)); }
 template <int K> Dual<K> expm1(const Dual<K>& a) { return chain(a, std::expm1(a.v), std::exp(a.v)); }
+template <int K> Dual<K> atan(const Dual<K>& a) { return chain(a, std::atan(a.v), 1.0 / (1.0 + a.v * a.v)); }
+template <int K>
+Dual<K> atan2(const Dual<K>& y, const Dual<K>& x) {
+  Dual<K> r;
+  r.v = std::atan2(y.v, x.v);
+  const double n = x.v * x.v + y.v * y.v;
+  for (int k = 0; k < K; ++k) r.d[k] = (x.v * y.d[k] - y.v * x.d[k]) / n;
+  return r;
+}
 
 /* ---- Sec. III.A, Eq. (27): second-order equilibrium ---- */
 template <class R>
@@ -424,6 +442,33 @@ R duplus(const R& yp, double kappa, double B) {
          B * (exp(-yp / 11.0) / 11.0 - exp(-yp / 3.0) / 11.0 + (yp / 33.0) * exp(-yp / 3.0));
 }
 
+/* ---- Sec. II.C with reading R21: Musker's explicit law of the wall ---- */
+template <class R>
+R uplus_musker(const R& yp) {
+  using std::atan2;
+  using std::log1p;
+  const double c = (g_mutation == 12) ? -8.15 : 8.15;
+  const R t = (2.0 * yp - c) / 16.7;
+  const double t0 = -8.15 / 16.7;
+  const R dt = 2.0 * yp / 16.7 + (8.15 - c) / 16.7; /* t - t0 */
+  return 5.424 * atan2(dt, 1.0 + t0 * t) + (9.6 * log1p(yp / 10.6) - 2.0 * log1p(yp * (yp - 8.15) / 86.0)) /
+                                               std::log(10.0);
+}
+template <class R>
+R duplus_musker(const R& yp) {
+  const R t = (2.0 * yp - 8.15) / 16.7;
+  const R q = yp * yp - 8.15 * yp + 86.0;
+  return 5.424 * (2.0 / 16.7) / (1.0 + t * t) + (9.6 / (yp + 10.6) - 2.0 * (2.0 * yp - 8.15) / q) / std::log(10.0);
+}
+template <class R>
+R law_uplus(const oracle_cfg& cfg, const R& yp) {
+  return cfg.wall_law == 1 ? uplus_musker(yp) : uplus(yp, cfg.kappa, cfg.b_reich);
+}
+template <class R>
+R law_duplus(const oracle_cfg& cfg, const R& yp) {
+  return cfg.wall_law == 1 ? duplus_musker(yp) : duplus(yp, cfg.kappa, cfg.b_reich);
+}
+
 /* ---- Sec. II.C, Eq. (20): u_tau u+(y u_tau / nu) = |u_hat| by Newton (R11) ---- */
 template <class R>
 int solve_utau(const R& ua, double y, double nu, const oracle_cfg& cfg, R* out) {
@@ -431,19 +476,20 @@ int solve_utau(const R& ua, double y, double nu, const oracle_cfg& cfg, R* out) 
   R ut = sqrt(nu * ua / y);
   for (int it = 0; it < cfg.newton_max; ++it) {
     R yp = y * ut / nu;
-    R up = uplus(yp, cfg.kappa, cfg.b_reich);
+    R up = law_uplus(cfg, yp);
     R g = ut * up - ua;
-    R dg = up + yp * duplus(yp, cfg.kappa, cfg.b_reich);
+    R dg = up + yp * law_duplus(cfg, yp);
     R du = g / dg;
     ut = ut - du;
     if (std::fabs(val(du)) <= cfg.newton_tol * std::fabs(val(ut))) {
       yp = y * ut / nu;
-      up = uplus(yp, cfg.kappa, cfg.b_reich);
+      up = law_uplus(cfg, yp);
       g = ut * up - ua;
-      dg = up + yp * duplus(yp, cfg.kappa, cfg.b_reich);
+      dg = up + yp * law_duplus(cfg, yp);
       ut = ut - g / dg; /* one more step: exact implicit-function derivative */
       *out = ut;
-      return OR_OK;
+      /* a root u_tau <= 0 is not a friction velocity (the Musker fit is negative for y+ < 0.009) */
+      return val(ut) > 0.0 ? OR_OK : OR_ERR_NEWTON;
     }
   }
   *out = ut;
@@ -736,6 +782,7 @@ bool cfg_ok(const oracle_cfg* cf) {
   if (!(cf->tau0 > 0.5)) return false;
   if (cf->sponge_cells < 0 || cf->sponge_cells > cf->nx - 1) return false;
   if (cf->outlet != 0 && cf->outlet != 1) return false;
+  if (cf->wall_law != 0 && cf->wall_law != 1) return false;
   if (cf->sponge_cells > 0 && (cf->xbc != 1 || !(cf->sponge_nu > 0.0))) return false;
   return true;
 }
@@ -778,6 +825,8 @@ double oracle_tau_eff(double Qhalf, double rho, double tau0, double cs_smag) {
 
 double oracle_uplus(double yp, double kappa, double B) { return uplus(yp, kappa, B); }
 double oracle_duplus(double yp, double kappa, double B) { return duplus(yp, kappa, B); }
+double oracle_uplus_musker(double yp) { return uplus_musker(yp); }
+double oracle_duplus_musker(double yp) { return duplus_musker(yp); }
 
 int oracle_utau(const oracle_cfg* cfg, double uhat_abs, double* ut) {
   const double nu0 = (cfg->tau0 - 0.5) * CS2;

@@ -20,6 +20,7 @@ _YWALL = {"periodic": A.Y_PERIODIC, "bounceback": A.Y_BOUNCEBACK, "slip": A.Y_SL
 _XBC = {"periodic": A.X_PERIODIC, "inflow": A.X_INFLOW}
 _STORE = {"f32": A.STORE_F32, "f16dev": A.STORE_F16DEV}
 _OUTLET = {"convective": A.OUTLET_CONVECTIVE, "zero-gradient": A.OUTLET_ZERO_GRADIENT}
+_WALL_LAW = {"reichardt": A.WALL_REICHARDT, "musker": A.WALL_MUSKER}
 
 
 def _ptr(t):
@@ -37,7 +38,8 @@ class Channel:
 
     def __init__(self, nx, ny, nz, *, tau0, storage="f32", ywall="slip", xbc="periodic", wall_model=False,
                  cs_smag=0.1, rates=None, kappa=0.41, b_reich=7.8, y_wall=0.5, u_conv=0.1, g=(0.0, 0.0, 0.0),
-                 newton_iters=4, sponge_cells=0, sponge_nu=0.0, outlet="convective", device=None):
+                 newton_iters=4, sponge_cells=0, sponge_nu=0.0, outlet="convective", wall_law="reichardt",
+                 device=None):
         self.device = torch.device(device if device is not None else "cuda")
         self.nx, self.ny, self.nz = nx, ny, nz
         self.N = nx * ny * nz
@@ -57,6 +59,7 @@ class Channel:
             cfg.g[a] = g[a]
         cfg.sponge_cells, cfg.sponge_nu = int(sponge_cells), float(sponge_nu)
         cfg.outlet = _OUTLET[outlet]
+        cfg.wall_law = _WALL_LAW[wall_law]
         self.cfg = cfg
         dt = torch.float32 if storage == "f32" else torch.float16
         elems = C.c_int64()

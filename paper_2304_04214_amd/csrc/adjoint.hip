@@ -237,7 +237,7 @@ __device__ __forceinline__ void node_adjoint(const AdjointArgs& A, AdjLds& L, in
           Fz += wtw * wez;
           const float yp = a.y_wall * wut * a.inv_nu0;
           float up, dup;
-          reichardt(a, yp, up, dup);
+          wall_law(a, yp, up, dup);
           wdg = up + yp * dup;  // d(u_tau u+)/du_tau at the root
         }
       }

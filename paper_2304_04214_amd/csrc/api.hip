@@ -40,6 +40,7 @@ lbm_status check_config(const lbm_config* c) {
   if (c->wall_model == 1 && (!(c->kappa > 0.0) || !(c->y_wall > 0.0))) return LBM_ERR_ARG;
   if (c->xbc == LBM_X_INFLOW && !(c->u_conv >= 0.0)) return LBM_ERR_ARG;
   if (c->outlet != LBM_OUTLET_CONVECTIVE && c->outlet != LBM_OUTLET_ZERO_GRADIENT) return LBM_ERR_ARG;
+  if (c->wall_law != LBM_WALL_REICHARDT && c->wall_law != LBM_WALL_MUSKER) return LBM_ERR_ARG;
   if (c->sponge_cells < 0 || c->sponge_cells > c->nx - 1) return LBM_ERR_ARG;
   if (c->sponge_cells > 0 && (c->xbc != LBM_X_INFLOW || !(c->sponge_nu > 0.0))) return LBM_ERR_ARG;
   return LBM_OK;

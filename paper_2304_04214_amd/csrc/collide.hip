@@ -488,6 +488,7 @@ void fill_args(lbm_ctx* h, CollideArgs& a, int src, int dst) {
   a.ywall = c.ywall;
   a.xbc = c.xbc;
   a.wall_model = c.wall_model;
+  a.wall_law = c.wall_law;
   a.newton_iters = c.newton_iters;
   a.stats_on = h->stats_on && h->d_stats != nullptr;
   a.has_g = (c.g[0] != 0.0 || c.g[1] != 0.0 || c.g[2] != 0.0) ? 1 : 0;

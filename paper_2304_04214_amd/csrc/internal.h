@@ -34,7 +34,7 @@ struct CollideArgs {
   const int* plane_of_x;  // [nx], -1 when not sampled
   int* err;
   int nx, ny, nz, zc, yg, nblocks;
-  int ywall, xbc, wall_model, newton_iters, stats_on, has_g;
+  int ywall, xbc, wall_model, newton_iters, stats_on, has_g, wall_law;
   float tau0, tau0sq, smag;  // smag = 18 sqrt(2) C_s^2
   float g[3];
   float nu0, inv_nu0, y_wall, kappa, inv_kappa, b_reich;

@@ -300,6 +300,30 @@ __device__ __forceinline__ void reichardt(const CollideArgs& a, float yp, float&
   dup = 1.f / (1.f + a.kappa * yp) + a.b_reich * ((e1 - e3) * (1.f / 11.f) + yp * (1.f / 33.f) * e3);
 }
 
+// Musker's explicit law of the wall (the alternative Sec. II.C names):
+// u+ = 5.424 atan((2y+ - 8.15)/16.7) + log10((y+ + 10.6)^9.6 / (y+^2 - 8.15y+ + 86)^2) + C,
+// C = -3.5113 so that u+(0) = 0 (the rounded -3.52 often printed leaves -0.0087 at the
+// wall and no positive u_tau root below y+ = 0.009).
+__device__ __forceinline__ void musker(float yp, float& up, float& dup) {
+  constexpr float LOG10E = 0.43429448190325182f;
+  const float t = (2.f * yp - 8.15f) * (1.f / 16.7f);
+  const float q = yp * yp - 8.15f * yp + 86.f;  // > 0 for every y+
+  // differences from y+ = 0 (atan(t) - atan(t0) = atan2(t - t0, 1 + t t0)): u+(0) = 0
+  // exactly and no term cancels at small y+
+  constexpr float T0 = -8.15f / 16.7f;
+  up = 5.424f * atan2f(yp * (2.f / 16.7f), 1.f + T0 * t) +
+       (9.6f * log1pf(yp * (1.f / 10.6f)) - 2.f * log1pf(yp * (yp - 8.15f) * (1.f / 86.f))) * LOG10E;
+  dup = 5.424f * (2.f / 16.7f) / (1.f + t * t) + LOG10E * (9.6f / (yp + 10.6f) - 2.f * (2.f * yp - 8.15f) / q);
+}
+
+// The configured law of the wall (wave-uniform switch).
+__device__ __forceinline__ void wall_law(const CollideArgs& a, float yp, float& up, float& dup) {
+  if (a.wall_law == LBM_WALL_MUSKER)
+    musker(yp, up, dup);
+  else
+    reichardt(a, yp, up, dup);
+}
+
 // u_tau from a fixed number of Newton steps on u_tau u+(y u_tau / nu0) = ua
 // (Sec. II.C, Eq. (20)), started from the viscous-sublayer estimate.
 __device__ __forceinline__ float newton_utau(const CollideArgs& a, float ua) {
@@ -307,7 +331,7 @@ __device__ __forceinline__ float newton_utau(const CollideArgs& a, float ua) {
   for (int it = 0; it < a.newton_iters; ++it) {
     const float yp = a.y_wall * ut * a.inv_nu0;
     float up, dup;
-    reichardt(a, yp, up, dup);
+    wall_law(a, yp, up, dup);
     ut -= (ut * up - ua) / (up + yp * dup);
   }
   return ut;

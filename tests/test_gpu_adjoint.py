@@ -110,6 +110,10 @@ CASES = {
                                           sponge_cells=5, sponge_nu=0.02), "f32"),
     "slip_inflow_zero_gradient_outlet": (dict(nx=6, ny=8, nz=20, ywall="slip", xbc="inflow", wall_model=True,
                                               outlet="zero-gradient"), "f32"),
+    "slip_inflow_musker_wall_law": (dict(nx=6, ny=8, nz=20, ywall="slip", xbc="inflow", wall_model=True,
+                                         wall_law="musker"), "f32"),
+    "f16_slip_inflow_musker_wall_law": (dict(nx=6, ny=8, nz=70, ywall="slip", xbc="inflow", wall_model=True,
+                                             wall_law="musker"), "f16dev"),
 }
 
 

@@ -66,6 +66,10 @@ PARITY_CASES = {
                                                                     sponge_cells=6, sponge_nu=0.02)),
     "slip-inflow-zero-gradient-outlet": dict(shape=(7, 10, 70), kw=dict(ywall="slip", xbc="inflow", wall_model=True,
                                                                        outlet="zero-gradient")),
+    "slip-inflow-musker-wall-law": dict(shape=(6, 10, 70), kw=dict(ywall="slip", xbc="inflow", wall_model=True,
+                                                                  wall_law="musker")),
+    "bounceback-inflow-musker-wall-law": dict(shape=(6, 9, 66), kw=dict(ywall="bounceback", xbc="inflow",
+                                                                       wall_model=True, wall_law="musker")),
     "re1000-like": dict(shape=(8, 12, 64), kw=dict(ywall="slip", xbc="inflow", wall_model=True,
                                                   tau0=0.5004270558446486, u_tau=0.004448498381757104,
                                                   n_modes=50)),
@@ -129,10 +133,10 @@ def test_statistics_match_oracle():
     assert err <= TOL32
 
 
-@pytest.mark.parametrize("storage", ["f32", "f16dev"])
-def test_wall_statistics_match_oracle(storage):
+@pytest.mark.parametrize("storage,law", [("f32", "reichardt"), ("f16dev", "reichardt"), ("f32", "musker")])
+def test_wall_statistics_match_oracle(storage, law):
     """Mean over z and steps of the wall law's u_tau at every x, both walls."""
-    c = Case(9, 10, 70, ywall="slip", xbc="inflow", wall_model=True, n_modes=30, storage=storage)
+    c = Case(9, 10, 70, ywall="slip", xbc="inflow", wall_model=True, n_modes=30, storage=storage, wall_law=law)
     c.ch.stats_attach([4])
     c.ch.step(12)
     wall, n = c.ch.stats_read_wall()
@@ -195,7 +199,8 @@ def test_nonfinite_density_is_reported():
     assert e.value.status == A.LBM_ERR_NONFINITE
 
 
-@pytest.mark.parametrize("name", ["slip-inflow-wallmodel", "periodic-smag-force", "slip-inflow-wallmodel-sponge"])
+@pytest.mark.parametrize("name", ["slip-inflow-wallmodel", "periodic-smag-force", "slip-inflow-wallmodel-sponge",
+                                  "slip-inflow-musker-wall-law"])
 def test_fp16_deviation_storage_matches_oracle(name):
     spec = PARITY_CASES[name]
     _say("fp16 parity", name)

@@ -36,3 +36,36 @@ def test_four_fp32_newton_steps_reach_the_root():
                 worst[k] = max(worst[k], abs(newton_fp32(nu, ua, k) - ref) / ref)
     assert worst[4] < 1e-6, worst
     assert worst[2] > 1e-5, worst
+
+
+def newton_fp32_musker(nu, ua, steps, y=0.5):
+    """The kernels' FP32 form of the Musker profile (differences from y+ = 0)."""
+    f = np.float32
+    nu, ua, y = f(nu), f(ua), f(y)
+    t0 = f(-8.15 / 16.7)
+    ut = np.sqrt(nu * ua / y).astype(f)
+    for _ in range(steps):
+        yp = y * ut / nu
+        t = (f(2) * yp - f(8.15)) / f(16.7)
+        up = f(5.424) * np.arctan2(yp * f(2 / 16.7), f(1) + t * t0) + \
+            (f(9.6) * np.log1p(yp / f(10.6)) - f(2) * np.log1p(yp * (yp - f(8.15)) / f(86))) * f(0.4342944819)
+        q = yp * yp - f(8.15) * yp + f(86)
+        dup = f(5.424) * (f(2) / f(16.7)) / (f(1) + t * t) + f(0.4342944819) * (f(9.6) / (yp + f(10.6)) - f(2) * (f(2) * yp - f(8.15)) / q)
+        ut = (ut - (ut * up - ua) / (up + yp * dup)).astype(f)
+    return float(ut)
+
+
+def test_four_fp32_newton_steps_reach_the_musker_root():
+    """The same for the Musker law over first-cell y+ 0.01 .. 3000."""
+    worst = {2: 0.0, 4: 0.0}
+    for nu in np.geomspace(1e-5, 2e-2, 12):
+        for yp in np.geomspace(0.01, 3000.0, 20):
+            ut = yp * nu / 0.5
+            ua = ut * O.uplus_musker(yp)
+            cfg = O.make_cfg(4, 4, 4, tau0=0.5 + 3 * nu, wall_law=1)
+            st, ref = O.utau(cfg, ua)
+            assert st == O.OK
+            for k in worst:
+                worst[k] = max(worst[k], abs(newton_fp32_musker(nu, ua, k) - ref) / ref)
+    assert worst[4] < 1e-6, worst
+    assert worst[2] > 1e-5, worst

@@ -19,9 +19,9 @@ TOL = 2e-6  # central differences with h = 1e-4 on O(1e-2) directions: truncatio
 
 
 def setup(nx=5, ny=NY, nz=NZ, ywall=2, xbc=1, wm=1, g=(2e-6, 0.0, 0.0), seed=3, n_bins=3, cs=0.1, sponge=0,
-          outlet=0):
+          outlet=0, law=0):
     cfg = O.make_cfg(nx, ny, nz, ywall=ywall, xbc=xbc, wall_model=wm, tau0=0.52, cs_smag=cs, g=g,
-                     sponge_cells=sponge, sponge_nu=0.02 if sponge else 0.0, outlet=outlet)
+                     sponge_cells=sponge, sponge_nu=0.02 if sponge else 0.0, outlet=outlet, wall_law=law)
     U = O.reichardt_inflow(cfg, 0.0084)
     du, dp = S.perturbations(nx, ny, nz, seed_offset=seed)
     u = U[:, None, :, None] + 3e-3 * du
@@ -36,7 +36,7 @@ def setup(nx=5, ny=NY, nz=NZ, ywall=2, xbc=1, wm=1, g=(2e-6, 0.0, 0.0), seed=3, 
 def with_cs(cfg, cs):
     c = O.make_cfg(cfg.nx, cfg.ny, cfg.nz, ywall=cfg.ywall, xbc=cfg.xbc, wall_model=cfg.wall_model,
                    tau0=cfg.tau0, cs_smag=cs, g=tuple(cfg.g), rates=list(cfg.s), sponge_cells=cfg.sponge_cells,
-                   sponge_nu=cfg.sponge_nu, outlet=cfg.outlet)
+                   sponge_nu=cfg.sponge_nu, outlet=cfg.outlet, wall_law=cfg.wall_law)
     return c
 
 
@@ -48,6 +48,8 @@ CASES = {
     "periodic_all": dict(ywall=0, xbc=0, wm=0, g=(4e-6, 1e-6, 0.0)),
     "slip_inflow_wallmodel_sponge": dict(ywall=2, xbc=1, wm=1, nx=8, sponge=4),
     "slip_inflow_zero_gradient_outlet": dict(ywall=2, xbc=1, wm=1, outlet=1),
+    "slip_inflow_musker_wall_law": dict(ywall=2, xbc=1, wm=1, law=1),
+    "bounceback_inflow_musker_wall_law": dict(ywall=1, xbc=1, wm=1, law=1),
 }
 
 
