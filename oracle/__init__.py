@@ -56,7 +56,8 @@ class Stg(C.Structure):
     _fields_ = [("n_modes", C.c_int32), ("n_bins", C.c_int32),
                 ("q", C.c_void_p), ("sigma", C.c_void_p), ("kmag", C.c_void_p), ("d", C.c_void_p),
                 ("phi", C.c_void_p), ("omega", C.c_void_p), ("u_rans", C.c_void_p), ("R", C.c_void_p),
-                ("amp_bin", C.c_void_p), ("bin_of_y", C.c_void_p)]
+                ("amp_bin", C.c_void_p), ("bin_of_y", C.c_void_p), ("k_rans", C.c_void_p),
+                ("omega_rans", C.c_void_p)]
 
 
 _lib = None
@@ -88,6 +89,7 @@ def lib():
             "oracle_inlet_node": (None, [P, P, P, P]),
             "oracle_cholesky": (None, [P, P]),
             "oracle_stg_plane": (I, [P, P, D, P, P]),
+            "oracle_stg_weights": (I, [P, P, I, P]),
             "oracle_reichardt_inflow": (None, [P, D, P]),
             "oracle_init": (I, [P, P, P, P, D, P, P]),
             "oracle_stream_only": (I, [P, P, P]),
@@ -136,7 +138,7 @@ def make_cfg(nx, ny, nz, *, ywall=0, xbc=0, wall_model=0, tau0=0.52, cs_smag=0.1
 class StgInputs:
     """Host FP64 STG inputs with their ctypes view (keeps arrays alive)."""
 
-    def __init__(self, q, sigma, kmag, d, phi, omega, u_rans, R, amp_bin, bin_of_y):
+    def __init__(self, q, sigma, kmag, d, phi, omega, u_rans, R, amp_bin, bin_of_y, k_rans=None, omega_rans=None):
         self.q, self.sigma, self.kmag, self.d = _d(q), _d(sigma), _d(kmag), _d(d)
         self.phi, self.omega, self.u_rans, self.R = _d(phi), _d(omega), _d(u_rans), _d(R)
         self.amp_bin = _d(amp_bin)
@@ -146,6 +148,10 @@ class StgInputs:
         s.q, s.sigma, s.kmag, s.d = _p(self.q), _p(self.sigma), _p(self.kmag), _p(self.d)
         s.phi, s.omega, s.u_rans, s.R = _p(self.phi), _p(self.omega), _p(self.u_rans), _p(self.R)
         s.amp_bin, s.bin_of_y = _p(self.amp_bin), _p(self.bin_of_y)
+        # per-row spectrum inputs (RANS k and omega); None: the table q serves every row
+        self.k_rans = None if k_rans is None else _d(k_rans)
+        self.omega_rans = None if omega_rans is None else _d(omega_rans)
+        s.k_rans, s.omega_rans = _p(self.k_rans), _p(self.omega_rans)
         self.c = s
 
 
@@ -247,6 +253,13 @@ def stg_plane(cfg, stg, t, want_fluct=False):
     fl = np.zeros((3, cfg.ny, cfg.nz)) if want_fluct else None
     st = lib().oracle_stg_plane(C.byref(cfg), C.byref(stg.c), float(t), _p(uin), _p(fl))
     return (st, uin, fl) if want_fluct else (st, uin)
+
+
+def stg_weights(cfg, stg, y):
+    """Spectral weights q^n of inlet row y (the bound table, or the per-row spectrum)."""
+    q = np.zeros(stg.c.n_modes)
+    st = lib().oracle_stg_weights(C.byref(cfg), C.byref(stg.c), int(y), _p(q))
+    return st, q
 
 
 def reichardt_inflow(cfg, u_tau):

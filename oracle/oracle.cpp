@@ -58,6 +58,17 @@
  *      5.424 [atan(t) - atan(t0)] + (9.6 ln(1 + y+/10.6) - 2 ln(1 + y+(y+ - 8.15)/86)) / ln 10,
  *      t = (2y+ - 8.15)/16.7, t0 = t(0), with atan(t) - atan(t0) = atan2(t - t0, 1 + t t0)
  *      and t - t0 = 2y+/16.7: every term is O(y+) at small y+, free of cancellation.
+ *  R22 the "modified von Karman spectrum" of Eq. (25) (details deferred to the
+ *      cited STG of Shur et al.): with RANS k(y), omega(y) and the wall
+ *      distance d_w = min(y + 1/2, ny - y - 1/2) of each inlet row,
+ *      l_t = sqrt(k)/(C_mu omega), l_e = min(2 d_w, C_l l_t), eta = (nu^3/eps)^(1/4),
+ *      eps = C_mu k omega, l_cut = 2 min(max(h_y, h_z, 0.3 h_max) + 0.1 d_w, h_max)
+ *      (= 2 on the unit lattice), k_e, k_eta, k_cut = 2 pi / (l_e, eta, l_cut);
+ *      E(k) = (k/k_e)^4 / (1 + 2.4 (k/k_e)^2)^(17/6) exp(-(12 k/k_eta)^2)
+ *             exp(-(4 max(k - 0.9 k_cut, 0)/k_cut)^3),
+ *      q^n(y) = E(k_n) dk_n / sum_m E(k_m) dk_m, C_mu = 0.09, C_l = 3, nu = nu0,
+ *      dk_n the centred differences of the ascending k_n (one-sided at the ends).
+ *      Without k, omega a single table q^n serves every row.
  *  R19 outlet sponge (Sec. IV.A names a sponge of thickness delta before the
  *      outlet but not its law): over the last L = sponge_cells planes the
  *      molecular viscosity rises as nu(x) = nu0 + (nu_s - nu0) r^2,
@@ -103,6 +114,8 @@ typedef struct {
   const double* R;        /* [6][ny] R11 R21 R22 R31 R32 R33 */
   const double* amp_bin;  /* [n_bins] amplitude scalings s_b */
   const int32_t* bin_of_y;/* [ny] */
+  const double* k_rans;   /* [ny] RANS turbulent kinetic energy, or NULL (then q is used) */
+  const double* omega_rans;/* [ny] RANS specific dissipation rate */
 } oracle_stg;
 
 }  // extern "C"
@@ -571,10 +584,54 @@ void cholesky(const double R6[6], double a[6]) {
 }
 
 /* ---- Sec. III.A, Eq. (22)-(25): STG inlet velocity plane at time t (R12) ---- */
+/* ---- Sec. III.A, Eq. (25) with reading R22: spectral weights of one inlet row ---- */
+int stg_weights(const oracle_cfg& cfg, const oracle_stg& s, int y, double* q) {
+  const int N = s.n_modes, ny = cfg.ny;
+  if (!s.k_rans) {
+    if (!s.q) return OR_ERR_ARG;
+    for (int n = 0; n < N; ++n) q[n] = s.q[n];
+    return OR_OK;
+  }
+  if (!s.omega_rans || cfg.ywall == 0) return OR_ERR_ARG; /* the spectrum needs a wall distance */
+  const double PI = 3.14159265358979323846;
+  const double Cmu = 0.09, Cl = 3.0;
+  const double nu = (cfg.tau0 - 0.5) * CS2;
+  const double k = s.k_rans[y], om = s.omega_rans[y];
+  if (!(k > 0.0) || !(om > 0.0) || !std::isfinite(k) || !std::isfinite(om)) return OR_ERR_ARG;
+  const double dw = std::fmin(y + 0.5, ny - y - 0.5);
+  const double lt = (g_mutation == 14) ? std::sqrt(k) / om : std::sqrt(k) / (Cmu * om);
+  const double le = std::fmin(2.0 * dw, Cl * lt);
+  const double eta = std::pow(nu * nu * nu / (Cmu * k * om), 0.25);
+  const double h = 1.0; /* lattice spacing in every direction */
+  const double lcut = 2.0 * std::fmin(std::fmax(std::fmax(h, h), 0.3 * h) + 0.1 * dw, h);
+  const double ke = 2.0 * PI / le, keta = 2.0 * PI / eta, kcut = 2.0 * PI / lcut;
+  const double p = (g_mutation == 13) ? 11.0 / 6.0 : 17.0 / 6.0;
+  double sum = 0.0;
+  for (int n = 0; n < N; ++n) {
+    if (n > 0 && !(s.kmag[n] > s.kmag[n - 1])) return OR_ERR_ARG;
+    double dk = 1.0;
+    if (N > 1) {
+      const int lo = n > 0 ? n - 1 : 0, hi = n < N - 1 ? n + 1 : N - 1;
+      dk = (s.kmag[hi] - s.kmag[lo]) / (hi - lo);
+    }
+    const double kn = s.kmag[n], r = kn / ke;
+    const double E = std::pow(r, 4.0) / std::pow(1.0 + 2.4 * r * r, p) * std::exp(-std::pow(12.0 * kn / keta, 2.0)) *
+                     std::exp(-std::pow(4.0 * std::fmax(kn - 0.9 * kcut, 0.0) / kcut, 3.0));
+    q[n] = E * dk;
+    sum += q[n];
+  }
+  if (!(sum > 0.0)) return OR_ERR_ARG;
+  for (int n = 0; n < N; ++n) q[n] /= sum;
+  return OR_OK;
+}
+
 int stg_plane(const oracle_cfg& cfg, const oracle_stg& s, double t, double* uin, double* fluct) {
   const int ny = cfg.ny, nz = cfg.nz, N = s.n_modes;
   int st = OR_OK;
+  std::vector<double> q(N);
   for (int y = 0; y < ny; ++y) {
+    const int sw = stg_weights(cfg, s, y, q.data());
+    if (sw != OR_OK) return sw;
     double R6[6], a[6];
     for (int k = 0; k < 6; ++k) R6[k] = s.R[k * ny + y];
     cholesky(R6, a);
@@ -585,7 +642,7 @@ int stg_plane(const oracle_cfg& cfg, const oracle_stg& s, double t, double* uin,
       for (int n = 0; n < N; ++n) {
         const double ph = s.kmag[n] * (s.d[1 * N + n] * yc + s.d[2 * N + n] * z) + s.omega[n] * t + s.phi[n];
         const double c = std::cos(ph);
-        const double amp = std::sqrt(6.0 * s.q[n]); /* Eq. (25): sqrt(6) sqrt(q^n) */
+        const double amp = std::sqrt(6.0 * q[n]); /* Eq. (25): sqrt(6) sqrt(q^n) */
         for (int a3 = 0; a3 < 3; ++a3) v[a3] += amp * s.sigma[a3 * N + n] * c;
       }
       /* Eq. (23): u' = a v' (lower triangular a), scaled by s_b */
@@ -847,6 +904,11 @@ void oracle_cholesky(const double* R6, double* a) { cholesky(R6, a); }
 int oracle_stg_plane(const oracle_cfg* cfg, const oracle_stg* s, double t, double* uin, double* fluct) {
   if (!cfg_ok(cfg) || !s) return OR_ERR_ARG;
   return stg_plane(*cfg, *s, t, uin, fluct);
+}
+
+int oracle_stg_weights(const oracle_cfg* cfg, const oracle_stg* s, int32_t y, double* q) {
+  if (!cfg_ok(cfg) || !s || y < 0 || y >= cfg->ny) return OR_ERR_ARG;
+  return stg_weights(*cfg, *s, y, q);
 }
 
 /* Reichardt inflow U(y) = u_tau u+(d u_tau / nu0), d the distance to the nearer wall. */

@@ -18,6 +18,11 @@ are not available):
 * Reynolds stresses: smooth SPD profiles in units of u_tau^2 with
   eta = (y + 1/2)/delta - 1:  R11 = 1 + 3 eta^2, R22 = 0.5 + 0.5 eta^2,
   R33 = 0.7 + 0.8 eta^2, R21 = eta (linear total shear stress), R31 = R32 = 0.
+* RANS k and omega (for the per-row spectrum): k = tr(R)/2 of the synthetic
+  Reynolds stresses; omega = sqrt(k) / (0.09^(1/4) l_m) with the mixing
+  length l_m = min(0.41 d_w, 0.09 delta), d_w = distance of the row centre
+  to the nearer wall.  A textbook mixing-length closure standing in for the
+  k-omega precursor.
 * Initial perturbations: uniform noise for a velocity perturbation and a
   population perturbation (the mean profile itself is built by each side).
 """
@@ -55,10 +60,11 @@ def rng(seed_offset=0):
     return np.random.Generator(np.random.PCG64(SEED_BASE + seed_offset))
 
 
-def mode_table(n_modes, delta, seed_offset=0, u_c=U_C):
+def mode_table(n_modes, delta, seed_offset=0, u_c=U_C, k_range=None):
     """Random STG mode parameters (raw draws, no method arithmetic).
 
     Returns dict with q[N], sigma[3,N], kmag[N], d[3,N], phi[N], omega[N].
+    k_range = (k_lo, k_hi) replaces the wavenumber range (q keeps its shape).
     """
     g = rng(seed_offset)
     ct = g.uniform(-1.0, 1.0, n_modes)
@@ -80,7 +86,7 @@ def mode_table(n_modes, delta, seed_offset=0, u_c=U_C):
     k_e = 2 * np.pi / l_e
     k_cut = np.pi
     k_eta = 4 * k_cut
-    kmag = np.geomspace(0.5 * k_e, 1.5 * k_cut, n_modes)
+    kmag = np.geomspace(0.5 * k_e, 1.5 * k_cut, n_modes) if k_range is None else np.geomspace(*k_range, n_modes)
     r = kmag / k_e
     E = r ** 4 / (1 + 2.4 * r * r) ** (17.0 / 6.0) * np.exp(-(12 * kmag / k_eta) ** 2) \
         * np.exp(-(4 * np.maximum(kmag - 0.9 * k_cut, 0.0) / k_cut) ** 3)
@@ -100,6 +106,23 @@ def reynolds_stress(ny, u_tau):
     R[2] = 0.5 + 0.5 * eta ** 2
     R[5] = 0.7 + 0.8 * eta ** 2
     return R * u_tau ** 2
+
+
+def spectrum_k_range(delta):
+    """Wavenumbers for the per-row spectrum: from half the wavenumber of the
+    largest eddy length any row can have (2 d_w <= 2 delta) to 1.5 times the
+    unit lattice's cut-off pi."""
+    return 0.5 * 2 * np.pi / (2 * delta), 1.5 * np.pi
+
+
+def rans_k_omega(ny, u_tau):
+    """Synthetic RANS k[ny], omega[ny] (see the module docstring)."""
+    delta = ny / 2
+    R = reynolds_stress(ny, u_tau)
+    k = 0.5 * (R[0] + R[2] + R[5])
+    d_w = np.minimum(np.arange(ny) + 0.5, ny - np.arange(ny) - 0.5)
+    l_m = np.minimum(0.41 * d_w, 0.09 * delta)
+    return k, np.sqrt(k) / (0.09 ** 0.25 * l_m)
 
 
 def amp_bins(ny, n_bins=None):
