@@ -130,6 +130,20 @@ typedef struct {
  *  u_rans[3][ny]  mean inflow;  R[6][ny] Reynolds stresses (R11 R21 R22 R31 R32 R33,
  *      symmetric positive definite); amp_bin[n_bins] amplitude scalings s_b;
  *      bin_of_y[ny] bin of each row.  u' = s_b(y) a(y) v', a = chol(R).
+ *  k_rans[ny], omega_rans[ny]   optional (both NULL or both set): RANS
+ *      turbulent kinetic energy and specific dissipation rate of each inlet
+ *      row.  When set, q is not read: each row y takes its own weights
+ *      q^n(y) = E(k_n; y) dk_n / sum_m E(k_m; y) dk_m from the modified von
+ *      Karman spectrum of the STG that Eq. (25) cites,
+ *        E(k) = (k/k_e)^4 / (1 + 2.4 (k/k_e)^2)^(17/6) exp(-(12 k/k_eta)^2)
+ *               exp(-(4 max(k - 0.9 k_cut, 0)/k_cut)^3),
+ *      k_e = 2 pi / min(2 d_w, 3 sqrt(k)/(0.09 omega)), k_eta = 2 pi / eta,
+ *      eta = (nu0^3 / (0.09 k omega))^(1/4), k_cut = pi (l_cut = 2 cells), d_w =
+ *      min(y + 1/2, ny - y - 1/2), dk_n centred differences of kmag (one-sided
+ *      at the ends).  kmag must then be strictly ascending and k, omega
+ *      positive, and the y walls must not be periodic (LBM_ERR_ARG: the
+ *      lattice's y walls, at bind time; the table values, reported by the
+ *      next lbm_sync, with the rows' weights left unspecified).
  *  u_in[3][ny][nz]   (written) inlet velocity plane;  fluct[3][ny][nz] (written,
  *      optional, may be NULL) a(y) v' before the s_b scaling.
  *  1 <= n_modes <= LBM_MAX_MODES.
@@ -140,6 +154,7 @@ typedef struct {
   const double *q, *sigma, *kmag, *d, *phi, *omega;
   const double *u_rans, *R, *amp_bin;
   const int32_t* bin_of_y;
+  const double *k_rans, *omega_rans;
   float* u_in;
   float* fluct;
 } lbm_stg;

@@ -36,7 +36,8 @@ class Stg(C.Structure):
     _fields_ = [("n_modes", C.c_int32), ("n_bins", C.c_int32),
                 ("q", C.c_void_p), ("sigma", C.c_void_p), ("kmag", C.c_void_p), ("d", C.c_void_p),
                 ("phi", C.c_void_p), ("omega", C.c_void_p), ("u_rans", C.c_void_p), ("R", C.c_void_p),
-                ("amp_bin", C.c_void_p), ("bin_of_y", C.c_void_p), ("u_in", C.c_void_p), ("fluct", C.c_void_p)]
+                ("amp_bin", C.c_void_p), ("bin_of_y", C.c_void_p), ("k_rans", C.c_void_p),
+                ("omega_rans", C.c_void_p), ("u_in", C.c_void_p), ("fluct", C.c_void_p)]
 
 
 class LbmError(RuntimeError):

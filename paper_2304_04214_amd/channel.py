@@ -96,10 +96,13 @@ class Channel:
         A.check(A.lib().lbm_inflow_reichardt(self._h, float(u_tau), _ptr(out)), "lbm_inflow_reichardt")
         return out
 
-    def set_stg(self, modes, u_rans, R, amp_bin, bin_of_y, want_fluct=False):
-        """Bind the inlet STG inputs (mode table dict q, sigma, kmag, d, phi, omega)."""
+    def set_stg(self, modes, u_rans, R, amp_bin, bin_of_y, want_fluct=False, k_rans=None, omega_rans=None):
+        """Bind the inlet STG inputs (mode table dict q, sigma, kmag, d, phi, omega).  With RANS
+        k_rans[ny] and omega_rans[ny] every row takes its own spectral weights (q is not read)."""
         dev = self.device
         keep = dict((k, _dev(modes[k], torch.float64, dev)) for k in ("q", "sigma", "kmag", "d", "phi", "omega"))
+        keep["k_rans"] = None if k_rans is None else _dev(k_rans, torch.float64, dev)
+        keep["omega_rans"] = None if omega_rans is None else _dev(omega_rans, torch.float64, dev)
         keep["u_rans"] = _dev(u_rans, torch.float64, dev)
         keep["R"] = _dev(R, torch.float64, dev)
         keep["amp_bin"] = _dev(amp_bin, torch.float64, dev)
@@ -109,7 +112,8 @@ class Channel:
         s = A.Stg()
         s.n_modes = int(keep["q"].numel())
         s.n_bins = int(keep["amp_bin"].numel())
-        for k in ("q", "sigma", "kmag", "d", "phi", "omega", "u_rans", "R", "amp_bin", "bin_of_y", "u_in", "fluct"):
+        for k in ("q", "sigma", "kmag", "d", "phi", "omega", "u_rans", "R", "amp_bin", "bin_of_y", "k_rans",
+                  "omega_rans", "u_in", "fluct"):
             setattr(s, k, None if keep[k] is None else keep[k].data_ptr())
         self._stg_tensors = keep
         self._stg = s

@@ -49,10 +49,11 @@ lbm_status check_config(const lbm_config* c) {
 lbm_status check_stg(const lbm_ctx* h, const lbm_stg* s) {
   if (!s) return LBM_ERR_ARG;
   if (s->n_modes < 1 || s->n_modes > LBM_MAX_MODES || s->n_bins < 1) return LBM_ERR_ARG;
-  if (!s->q || !s->sigma || !s->kmag || !s->d || !s->phi || !s->omega || !s->u_rans || !s->R || !s->amp_bin ||
+  if (!s->sigma || !s->kmag || !s->d || !s->phi || !s->omega || !s->u_rans || !s->R || !s->amp_bin ||
       !s->bin_of_y || !s->u_in)
     return LBM_ERR_ARG;
-  (void)h;
+  if (!s->k_rans != !s->omega_rans) return LBM_ERR_ARG;
+  if (s->k_rans ? h->cfg.ywall == LBM_Y_PERIODIC : !s->q) return LBM_ERR_ARG;
   return LBM_OK;
 }
 
@@ -75,6 +76,7 @@ lbm_status take_error(lbm_ctx* h) {
   }
   if (err & lbm::ERRBIT_NONFINITE) return LBM_ERR_NONFINITE;
   if (err & lbm::ERRBIT_MACH) return LBM_ERR_MACH;
+  if (err & lbm::ERRBIT_STG_TABLE) return LBM_ERR_ARG;
   return LBM_OK;
 }
 
@@ -86,6 +88,7 @@ void free_tables(lbm_ctx* h) {
   if (t.chol) (void)hipFree(t.chol);
   if (t.sb) (void)hipFree(t.sb);
   if (t.urans) (void)hipFree(t.urans);
+  if (t.rowamp_buf) (void)hipFree(t.rowamp_buf);
   t = lbm::StgTables();
 }
 

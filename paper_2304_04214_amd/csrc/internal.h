@@ -14,6 +14,7 @@ namespace lbm {
 // Bits of the device error word.
 constexpr int ERRBIT_MACH = 1;
 constexpr int ERRBIT_NONFINITE = 2;
+constexpr int ERRBIT_STG_TABLE = 4;  // invalid per-row spectrum inputs (kmag order, k, omega)
 
 constexpr int ZT = 64;     // z-lanes per wave (one wave = one (x, y) row segment)
 constexpr int YROWS = 4;   // rows (waves) per collide block
@@ -63,8 +64,10 @@ struct AdjointArgs {
 
 struct StgTables {
   int n_modes = 0;
-  int cap_trigz = 0, cap_amp3 = 0, cap_ky = 0, cap_chol = 0, cap_sb = 0, cap_urans = 0;
-  float* amp3 = nullptr;    // [3][N] sqrt(6 q) sigma
+  int cap_trigz = 0, cap_amp3 = 0, cap_ky = 0, cap_chol = 0, cap_sb = 0, cap_urans = 0, cap_rowamp = 0;
+  float* amp3 = nullptr;    // [3][N] sqrt(6 q) sigma; sigma alone with the per-row spectrum
+  float* rowamp_buf = nullptr;    // [ny][N] allocation behind rowamp
+  const float* rowamp = nullptr;  // [ny][N] sqrt(6 q^n(y)) with the per-row spectrum, else null
   double* ky = nullptr;     // [N] kmag d_y
   float2* trigz = nullptr;  // [N][nz] (cos, sin)(kmag d_z z mod 2 pi)
   float* chol = nullptr;    // [6][ny]

@@ -21,6 +21,7 @@ constexpr double TWO_PI = 6.283185307179586476925286766559;
 constexpr float MACH_LIMIT = 0.17320508075688773f;  // 0.3 c_s, c_s = 1/sqrt(3)
 
 __global__ void stg_bind_kernel(lbm_stg s, StgTables t, int ny, int nz) {
+  const bool rows = s.k_rans != nullptr;  // per-row spectrum: sqrt(6 q^n(y)) lives in rowamp
   const int N = s.n_modes;
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t nzN = (int64_t)N * nz;
@@ -35,7 +36,7 @@ __global__ void stg_bind_kernel(lbm_stg s, StgTables t, int ny, int nz) {
   const int64_t k2 = k - nzN;
   if (k2 < N) {
     const int n = (int)k2;
-    const double a = sqrt(6.0 * s.q[n]);  // Eq. (25): sqrt(6) sqrt(q^n)
+    const double a = rows ? 1.0 : sqrt(6.0 * s.q[n]);  // Eq. (25): sqrt(6) sqrt(q^n)
     for (int c = 0; c < 3; ++c) t.amp3[c * N + n] = (float)(a * s.sigma[c * N + n]);
     t.ky[n] = s.kmag[n] * s.d[N + n];
     return;
@@ -65,6 +66,51 @@ __global__ void stg_bind_kernel(lbm_stg s, StgTables t, int ny, int nz) {
   }
 }
 
+// Per-row weights of the modified von Karman spectrum (Sec. III.A, Eq. (25),
+// the spectrum of the cited STG) from the row's RANS k, omega and wall
+// distance: one block per inlet row; FP64 throughout, the row sum reduced in
+// a fixed order; rowamp[y][n] = sqrt(6 q^n(y)).
+__device__ double spectrum_weight(const lbm_stg& s, int n, double ke, double keta, double kcut) {
+  const int N = s.n_modes;
+  double dk = 1.0;
+  if (N > 1) {
+    const int lo = n > 0 ? n - 1 : 0, hi = n < N - 1 ? n + 1 : N - 1;
+    dk = (s.kmag[hi] - s.kmag[lo]) / (hi - lo);
+  }
+  const double k = s.kmag[n], r = k / ke;
+  const double r2 = r * r;
+  const double a = 12.0 * k / keta, c = 4.0 * fmax(k - 0.9 * kcut, 0.0) / kcut;
+  return r2 * r2 * pow(1.0 + 2.4 * r2, -17.0 / 6.0) * exp(-a * a - c * c * c) * dk;
+}
+
+__global__ __launch_bounds__(256) void stg_spectrum_kernel(lbm_stg s, float* rowamp, int ny, double nu, int* err) {
+  __shared__ double red[256];
+  const int y = blockIdx.x, N = s.n_modes;
+  const double CMU = 0.09, CL = 3.0;
+  const double k = s.k_rans[y], om = s.omega_rans[y];
+  bool bad = !(k > 0.0) || !(om > 0.0) || !isfinite(k) || !isfinite(om);
+  const double dw = fmin(y + 0.5, ny - y - 0.5);
+  const double le = fmin(2.0 * dw, CL * sqrt(k) / (CMU * om));  // energy-containing eddy length
+  const double eta = sqrt(sqrt(nu * nu * nu / (CMU * k * om)));  // Kolmogorov length
+  const double ke = TWO_PI / le, keta = TWO_PI / eta, kcut = TWO_PI / 2.0;  // l_cut = 2 cells
+  double part = 0.0;
+  for (int n = threadIdx.x; n < N; n += 256) {
+    if (n > 0 && !(s.kmag[n] > s.kmag[n - 1])) bad = true;
+    part += spectrum_weight(s, n, ke, keta, kcut);
+  }
+  red[threadIdx.x] = part;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  const double sum = red[0];
+  if (!(sum > 0.0)) bad = true;
+  for (int n = threadIdx.x; n < N; n += 256)
+    rowamp[(int64_t)y * N + n] = (float)sqrt(6.0 * spectrum_weight(s, n, ke, keta, kcut) / sum);
+  if (bad) atomicOr(err, ERRBIT_STG_TABLE);
+}
+
 // One block per (inlet row y, 64 spanwise nodes, step); its four waves each
 // sum a quarter of the modes, and the partial sums are added in a fixed order.
 // Step j = blockIdx.z has time time0 + j.  With ring == nullptr the plane
@@ -89,9 +135,10 @@ __global__ __launch_bounds__(256) void stg_fill_kernel(lbm_stg s, StgTables t, i
     double sn, cs;
     sincos(ph, &sn, &cs);
     rowph[n] = make_float2((float)cs, (float)sn);
-    amp[0][n] = t.amp3[n];
-    amp[1][n] = t.amp3[N + n];
-    amp[2][n] = t.amp3[2 * N + n];
+    const float r = t.rowamp ? t.rowamp[(int64_t)y * N + n] : 1.f;
+    amp[0][n] = t.amp3[n] * r;
+    amp[1][n] = t.amp3[N + n] * r;
+    amp[2][n] = t.amp3[2 * N + n] * r;
   }
   __syncthreads();
   float v0 = 0.f, v1 = 0.f, v2 = 0.f;
@@ -197,8 +244,16 @@ hipError_t launch_stg_bind(lbm_ctx* h, const lbm_stg* s) {
   t.n_modes = N;
   const int64_t total = (int64_t)N * nz + N + ny;
   const int nb = (int)((total + 255) / 256);
+  t.rowamp = nullptr;
   stg_bind_kernel<<<nb, 256, 0, h->stream>>>(*s, t, ny, nz);
-  return hipGetLastError();
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  if (s->k_rans) {
+    if ((e = grow(&t.rowamp_buf, &t.cap_rowamp, ny * N)) != hipSuccess) return e;
+    t.rowamp = t.rowamp_buf;
+    stg_spectrum_kernel<<<ny, 256, 0, h->stream>>>(*s, t.rowamp_buf, ny, (h->cfg.tau0 - 0.5) / 3.0, h->d_err);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 // fluct and u_in, when given, replace the bound outputs (the fluctuation a v'

@@ -14,7 +14,10 @@ no DNS data are involved, so nothing here is a comparison with DNS):
   as an L2 error relative to the prescribed profile;
 * U+ against the Reichardt law at the same planes.
 
-    python -m paper_2304_04214_amd.recovery --re 1000 --h 20
+With --spectrum the STG takes per-row spectral weights from synthetic RANS
+k, omega (the spectrum of the STG that Eq. (25) cites) instead of one table.
+
+    python -m paper_2304_04214_amd.recovery --re 1000 --h 20 [--spectrum]
 """
 import argparse
 import json
@@ -30,7 +33,7 @@ SPONGE_NU = 0.1  # viscosity at the outlet plane of the 1-delta sponge (the pape
 PLANES_DELTA = (0.5, 1, 2, 3, 4, 6, 8, 10, 12, 14, 16, 18)
 
 
-def setup(re_tau, H, storage="f32", n_modes=200, seed=7, device="cuda"):
+def setup(re_tau, H, storage="f32", n_modes=200, seed=7, spectrum=False, device="cuda"):
     delta = H // 2
     nx, ny, nz = 20 * delta, 2 * delta, int(round(1.6 * delta))
     u_tau = S.U_TAU_OF_RE[float(re_tau)]
@@ -40,7 +43,12 @@ def setup(re_tau, H, storage="f32", n_modes=200, seed=7, device="cuda"):
     U = ch.inflow_reichardt(u_tau)
     ab, boy = S.amp_bins(ny)
     R = S.reynolds_stress(ny, u_tau)
-    ch.set_stg(S.mode_table(n_modes, delta, seed_offset=seed), U, R, ab, boy)
+    if spectrum:
+        k, om = S.rans_k_omega(ny, u_tau)
+        ch.set_stg(S.mode_table(n_modes, delta, seed_offset=seed, k_range=S.spectrum_k_range(delta)), U, R, ab, boy,
+                   k_rans=k, omega_rans=om)
+    else:
+        ch.set_stg(S.mode_table(n_modes, delta, seed_offset=seed), U, R, ab, boy)
     g = torch.Generator(device=device)
     g.manual_seed(S.SEED_BASE + seed)
     u = U.float()[:, None, :, None].expand(3, nx, ny, nz).contiguous()
@@ -49,8 +57,8 @@ def setup(re_tau, H, storage="f32", n_modes=200, seed=7, device="cuda"):
     return ch, dict(delta=delta, nx=nx, ny=ny, nz=nz, u_tau=u_tau, nu0=nu0, U=U[0].cpu().numpy(), R12=R[1])
 
 
-def run(re_tau, H, periods=10, stats_from=2, storage="f32", device="cuda"):
-    ch, p = setup(re_tau, H, storage=storage, device=device)
+def run(re_tau, H, periods=10, stats_from=2, storage="f32", spectrum=False, device="cuda"):
+    ch, p = setup(re_tau, H, storage=storage, spectrum=spectrum, device=device)
     delta, nx, ny = p["delta"], p["nx"], p["ny"]
     T = int(round(nx / S.U_C))
     planes = sorted({min(int(round(d * delta)), nx - 1) for d in PLANES_DELTA})
@@ -82,7 +90,7 @@ def run(re_tau, H, periods=10, stats_from=2, storage="f32", device="cuda"):
                              uv_plus_err_l2=float(np.sqrt(((uv - target) ** 2).sum() / (target ** 2).sum())),
                              U_plus_err_max=float(np.abs(U_plus - Ur).max() / np.abs(Ur).max()),
                              uv_plus=[round(float(v), 4) for v in uv]))
-    return dict(re_tau=re_tau, H=H, shape=[nx, ny, p["nz"]], storage=storage, steps=periods * T,
+    return dict(re_tau=re_tau, H=H, shape=[nx, ny, p["nz"]], storage=storage, spectrum=spectrum, steps=periods * T,
                 sampled_steps=n, wall_s=round(wall_s, 2), mlups=round(nx * ny * p["nz"] * periods * T / wall_s / 1e6, 1),
                 u_tau_ratio_x_delta=[round(float(v), 3) for v in x_d[::max(1, delta // 2)]],
                 u_tau_ratio=[round(float(v), 4) for v in ratio[::max(1, delta // 2)]],
@@ -96,10 +104,11 @@ def main():
     ap.add_argument("--h", type=int, nargs="+", default=[20])
     ap.add_argument("--periods", type=int, default=10)
     ap.add_argument("--storage", default="f32")
+    ap.add_argument("--spectrum", action="store_true", help="per-row STG spectrum from synthetic RANS k, omega")
     a = ap.parse_args()
     for re_tau in a.re:
         for H in a.h:
-            print(json.dumps(run(re_tau, H, periods=a.periods, storage=a.storage)), flush=True)
+            print(json.dumps(run(re_tau, H, periods=a.periods, storage=a.storage, spectrum=a.spectrum)), flush=True)
 
 
 if __name__ == "__main__":

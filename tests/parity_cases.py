@@ -23,14 +23,17 @@ class Case:
     def __init__(self, nx, ny, nz, *, ywall="slip", xbc="inflow", wall_model=True, tau0=0.52, cs_smag=0.1,
                  u_tau=0.008369396673286735, n_modes=24, seed=0, storage="f32", g=(0.0, 0.0, 0.0), eps=0.05,
                  du_amp=1e-3, u_conv=0.1, newton_iters=4, amp_scale=1.0, rates=None, sponge_cells=0,
-                 sponge_nu=0.0, outlet="convective", wall_law="reichardt"):
+                 sponge_nu=0.0, outlet="convective", wall_law="reichardt", spectrum=False):
         self.nx, self.ny, self.nz = nx, ny, nz
         self.xbc = xbc
         self.ocfg = O.make_cfg(nx, ny, nz, ywall=YW[ywall], xbc=XB[xbc], wall_model=int(wall_model), tau0=tau0,
                                cs_smag=cs_smag, u_conv=u_conv, g=g, rates=rates, sponge_cells=sponge_cells,
                                sponge_nu=sponge_nu, outlet={"convective": 0, "zero-gradient": 1}[outlet],
                                wall_law={"reichardt": 0, "musker": 1}[wall_law])
-        self.mt = S.mode_table(n_modes, ny / 2, seed_offset=seed)
+        # spectrum: per-row spectral weights from synthetic RANS k, omega (the table's q is then unused)
+        self.mt = S.mode_table(n_modes, ny / 2, seed_offset=seed,
+                               k_range=S.spectrum_k_range(ny / 2) if spectrum else None)
+        self.k_om = S.rans_k_omega(ny, u_tau) if spectrum else (None, None)
         self.R = S.reynolds_stress(ny, u_tau) * amp_scale ** 2
         self.ab, self.boy = S.amp_bins(ny)
         du, dp = S.perturbations(nx, ny, nz, seed_offset=seed)
@@ -40,7 +43,7 @@ class Case:
         self.f_or, self.hist_or = O.init(self.ocfg, u_or, pert=dp, eps=eps)
         mt = self.mt
         self.stg_or = O.StgInputs(mt["q"], mt["sigma"], mt["kmag"], mt["d"], mt["phi"], mt["omega"], U_or,
-                                  self.R, self.ab, self.boy)
+                                  self.R, self.ab, self.boy, k_rans=self.k_om[0], omega_rans=self.k_om[1])
         # ---- HIP side ----
         self.ch = Channel(nx, ny, nz, tau0=tau0, storage=storage, ywall=ywall, xbc=xbc, wall_model=wall_model,
                           cs_smag=cs_smag, u_conv=u_conv, g=g, newton_iters=newton_iters, rates=rates,
@@ -49,7 +52,8 @@ class Case:
         self.U_g = U_g
         u_g = U_g.float()[:, None, :, None] + du_amp * torch.as_tensor(du, dtype=torch.float32, device="cuda")
         if xbc == "inflow":
-            self.ch.set_stg(self.mt, U_g, self.R, self.ab, self.boy, want_fluct=True)
+            self.ch.set_stg(self.mt, U_g, self.R, self.ab, self.boy, want_fluct=True, k_rans=self.k_om[0],
+                            omega_rans=self.k_om[1])
         self.ch.init(u_g, pert=dp, eps=eps)
         self.U_or = U_or
 

@@ -112,6 +112,8 @@ CASES = {
                                               outlet="zero-gradient"), "f32"),
     "slip_inflow_musker_wall_law": (dict(nx=6, ny=8, nz=20, ywall="slip", xbc="inflow", wall_model=True,
                                          wall_law="musker"), "f32"),
+    "slip_inflow_row_spectrum": (dict(nx=6, ny=8, nz=20, ywall="slip", xbc="inflow", wall_model=True,
+                                      spectrum=True), "f32"),
     "f16_slip_inflow_musker_wall_law": (dict(nx=6, ny=8, nz=70, ywall="slip", xbc="inflow", wall_model=True,
                                              wall_law="musker"), "f16dev"),
 }

@@ -70,6 +70,8 @@ PARITY_CASES = {
                                                                   wall_law="musker")),
     "bounceback-inflow-musker-wall-law": dict(shape=(6, 9, 66), kw=dict(ywall="bounceback", xbc="inflow",
                                                                        wall_model=True, wall_law="musker")),
+    "slip-inflow-row-spectrum": dict(shape=(7, 10, 70), kw=dict(ywall="slip", xbc="inflow", wall_model=True,
+                                                               n_modes=120, spectrum=True)),
     "re1000-like": dict(shape=(8, 12, 64), kw=dict(ywall="slip", xbc="inflow", wall_model=True,
                                                   tau0=0.5004270558446486, u_tau=0.004448498381757104,
                                                   n_modes=50)),
@@ -150,9 +152,12 @@ def test_wall_statistics_match_oracle(storage, law):
     assert err <= (1e-5 if storage == "f32" else 2e-3)
 
 
-@pytest.mark.parametrize("t", [0.0, 1.0, 137.0, 5000.0])
-def test_stg_plane_matches_oracle(t):
-    c = Case(4, 10, 70, ywall="slip", xbc="inflow", wall_model=True, n_modes=300, amp_scale=3.0)
+@pytest.mark.parametrize("t,spectrum", [(0.0, False), (1.0, False), (137.0, False), (5000.0, False), (3.0, True),
+                                        (4321.0, True)])
+def test_stg_plane_matches_oracle(t, spectrum):
+    # amplitudes raised to exercise the FP32 mode sum, below the inlet Mach guard
+    c = Case(4, 10, 70, ywall="slip", xbc="inflow", wall_model=True, n_modes=300, amp_scale=2.0 if spectrum else 3.0,
+             spectrum=spectrum)
     u = c.ch.stg_fill(t).cpu().numpy()
     st, ref, fl = O.stg_plane(c.ocfg, c.stg_or, t, want_fluct=True)
     assert st == O.OK
@@ -173,6 +178,26 @@ def test_lattice_tables_match_oracle_tables():
     a, b = lattice_tables(), O.tables()
     assert np.array_equal(a["c"], b["c"]) and np.array_equal(a["opp"], b["opp"])
     assert np.array_equal(a["refl"], b["refl"]) and np.array_equal(a["w"], b["w"])
+
+
+def test_invalid_row_spectrum_is_reported():
+    """Non-ascending wavenumbers with the per-row spectrum: LBM_ERR_ARG at the next sync;
+    a wall-free lattice refuses the spectrum when it is bound."""
+    c = Case(4, 6, 8, ywall="slip", xbc="inflow", wall_model=False, n_modes=16, spectrum=True)
+    c.ch.sync()
+    mt = dict(c.mt)
+    mt["kmag"] = mt["kmag"][::-1].copy()
+    c.ch.set_stg(mt, c.U_g, c.R, c.ab, c.boy, k_rans=c.k_om[0], omega_rans=c.k_om[1])
+    c.ch.stg_fill(1.0)
+    with pytest.raises(A.LbmError) as e:
+        c.ch.sync()
+    assert e.value.status == A.LBM_ERR_ARG
+    c.ch.sync()
+    p = Channel(4, 6, 8, tau0=0.52, ywall="periodic", xbc="inflow", wall_model=False)
+    p.set_stg(c.mt, c.U_g, c.R, c.ab, c.boy, k_rans=c.k_om[0], omega_rans=c.k_om[1])
+    with pytest.raises(A.LbmError) as e:
+        p.stg_fill(1.0)
+    assert e.value.status == A.LBM_ERR_ARG
 
 
 def test_mach_guard_is_reported():

@@ -19,17 +19,19 @@ TOL = 2e-6  # central differences with h = 1e-4 on O(1e-2) directions: truncatio
 
 
 def setup(nx=5, ny=NY, nz=NZ, ywall=2, xbc=1, wm=1, g=(2e-6, 0.0, 0.0), seed=3, n_bins=3, cs=0.1, sponge=0,
-          outlet=0, law=0):
+          outlet=0, law=0, spectrum=False):
     cfg = O.make_cfg(nx, ny, nz, ywall=ywall, xbc=xbc, wall_model=wm, tau0=0.52, cs_smag=cs, g=g,
                      sponge_cells=sponge, sponge_nu=0.02 if sponge else 0.0, outlet=outlet, wall_law=law)
     U = O.reichardt_inflow(cfg, 0.0084)
     du, dp = S.perturbations(nx, ny, nz, seed_offset=seed)
     u = U[:, None, :, None] + 3e-3 * du
     f, hist = O.init(cfg, u, pert=dp, eps=0.05)
-    mt = S.mode_table(12, ny / 2, seed_offset=seed)
+    mt = S.mode_table(12, ny / 2, seed_offset=seed, k_range=S.spectrum_k_range(ny / 2) if spectrum else None)
     R = S.reynolds_stress(ny, 0.0084)
     ab, boy = S.amp_bins(ny, n_bins)
-    stg = O.StgInputs(mt["q"], mt["sigma"], mt["kmag"], mt["d"], mt["phi"], mt["omega"], U, R, ab, boy)
+    k_om = S.rans_k_omega(ny, 0.0084) if spectrum else (None, None)
+    stg = O.StgInputs(mt["q"], mt["sigma"], mt["kmag"], mt["d"], mt["phi"], mt["omega"], U, R, ab, boy,
+                      k_rans=k_om[0], omega_rans=k_om[1])
     return cfg, f, hist, stg
 
 
@@ -49,6 +51,7 @@ CASES = {
     "slip_inflow_wallmodel_sponge": dict(ywall=2, xbc=1, wm=1, nx=8, sponge=4),
     "slip_inflow_zero_gradient_outlet": dict(ywall=2, xbc=1, wm=1, outlet=1),
     "slip_inflow_musker_wall_law": dict(ywall=2, xbc=1, wm=1, law=1),
+    "slip_inflow_row_spectrum": dict(ywall=2, xbc=1, wm=1, spectrum=True),
     "bounceback_inflow_musker_wall_law": dict(ywall=1, xbc=1, wm=1, law=1),
 }
 
@@ -119,9 +122,11 @@ def test_planted_adjoint_mistakes_fail(mutation, part):
     assert errs[part][0] > 10 * TOL, errs
 
 
-def test_amp_bin_gradient_matches_fd():
-    """dL/ds_b = sum over the bin's inlet rows of g_uin . (a v'), checked through the STG."""
-    cfg, f, hist, stg = setup(n_bins=3)
+@pytest.mark.parametrize("spectrum", [False, True])
+def test_amp_bin_gradient_matches_fd(spectrum):
+    """dL/ds_b = sum over the bin's inlet rows of g_uin . (a v'), checked through the STG
+    (one spectral table, or per-row spectra)."""
+    cfg, f, hist, stg = setup(n_bins=3, spectrum=spectrum)
     g = np.random.default_rng(11)
     lam = g.normal(size=f.shape)
     eta = g.normal(size=(5, cfg.ny, cfg.nz))
@@ -130,7 +135,7 @@ def test_amp_bin_gradient_matches_fd():
 
     def J(amp):
         st2 = O.StgInputs(stg.q, stg.sigma, stg.kmag, stg.d, stg.phi, stg.omega, stg.u_rans, stg.R, amp,
-                          stg.bin_of_y)
+                          stg.bin_of_y, k_rans=stg.k_rans, omega_rans=stg.omega_rans)
         st, fo, ho = O.step(cfg, f, hist, 9.0, stg=st2)
         assert st == O.OK
         return (lam * fo).sum() + (eta * ho).sum()
