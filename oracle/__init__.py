@@ -49,7 +49,7 @@ class Cfg(C.Structure):
                 ("newton_tol", C.c_double), ("tau0", C.c_double), ("cs_smag", C.c_double),
                 ("s", C.c_double * 19), ("kappa", C.c_double), ("b_reich", C.c_double),
                 ("y_wall", C.c_double), ("u_conv", C.c_double), ("g", C.c_double * 3), ("sponge_nu", C.c_double),
-                ("outlet", C.c_int32), ("wall_law", C.c_int32)]
+                ("outlet", C.c_int32), ("wall_law", C.c_int32), ("wall_avg", C.c_int32), ("pad_", C.c_int32)]
 
 
 class Stg(C.Structure):
@@ -90,6 +90,7 @@ def lib():
             "oracle_cholesky": (None, [P, P]),
             "oracle_stg_plane": (I, [P, P, D, P, P]),
             "oracle_stg_weights": (I, [P, P, I, P]),
+            "oracle_wall_lines": (I, [P, P, D, P, P, P, P]),
             "oracle_reichardt_inflow": (None, [P, D, P]),
             "oracle_init": (I, [P, P, P, P, D, P, P]),
             "oracle_stream_only": (I, [P, P, P]),
@@ -118,7 +119,8 @@ def _d(a):
 
 def make_cfg(nx, ny, nz, *, ywall=0, xbc=0, wall_model=0, tau0=0.52, cs_smag=0.1, rates=None,
              kappa=0.41, b_reich=7.8, y_wall=0.5, u_conv=0.1, g=(0.0, 0.0, 0.0),
-             newton_max=50, newton_tol=1e-14, sponge_cells=0, sponge_nu=0.0, outlet=0, wall_law=0):
+             newton_max=50, newton_tol=1e-14, sponge_cells=0, sponge_nu=0.0, outlet=0, wall_law=0,
+             wall_avg=0):
     c = Cfg()
     c.nx, c.ny, c.nz = nx, ny, nz
     c.ywall, c.xbc, c.wall_model = ywall, xbc, wall_model
@@ -132,6 +134,7 @@ def make_cfg(nx, ny, nz, *, ywall=0, xbc=0, wall_model=0, tau0=0.52, cs_smag=0.1
     c.sponge_cells, c.sponge_nu = sponge_cells, sponge_nu
     c.outlet = outlet
     c.wall_law = wall_law
+    c.wall_avg = wall_avg
     return c
 
 
@@ -260,6 +263,15 @@ def stg_weights(cfg, stg, y):
     q = np.zeros(stg.c.n_modes)
     st = lib().oracle_stg_weights(C.byref(cfg), C.byref(stg.c), int(y), _p(q))
     return st, q
+
+
+def wall_lines(cfg, f, hist, t_next, stg=None):
+    """Line-averaged wall model (reading R23): (status, signed line u_tau [2][nx], u_hat [2][nx][nz])."""
+    line = np.zeros((2, cfg.nx))
+    uhat = np.zeros((2, cfg.nx, cfg.nz))
+    st = lib().oracle_wall_lines(C.byref(cfg), _ref(None if stg is None else stg.c), float(t_next), _p(_d(f)),
+                                 _p(None if hist is None else _d(hist)), _p(line), _p(uhat))
+    return st, line, uhat
 
 
 def reichardt_inflow(cfg, u_tau):

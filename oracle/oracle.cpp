@@ -69,6 +69,14 @@
  *      q^n(y) = E(k_n) dk_n / sum_m E(k_m) dk_m, C_mu = 0.09, C_l = 3, nu = nu0,
  *      dk_n the centred differences of the ascending k_n (one-sided at the ends).
  *      Without k, omega a single table q^n serves every row.
+ *  R23 plane-averaged friction velocity (Sec. II.C contrasts its local u_tau
+ *      with the plane-averaged one of the works it cites): with wall_avg = 1
+ *      the wall-parallel average runs over the homogeneous direction z of
+ *      each wall line (x, wall) of the inflow channel; u_hat = u_w . e_x
+ *      (Eq. (19), 0 where u_2 has no tangential part) is averaged over z,
+ *      u_tau(x, wall) solves Eq. (20) for |mean u_hat| in the same step, and
+ *      every cell of the line takes F_w = -sign(mean u_hat) rho u_tau^2 e_x with
+ *      its own rho and e_x (Eq. (21)).
  *  R19 outlet sponge (Sec. IV.A names a sponge of thickness delta before the
  *      outlet but not its law): over the last L = sponge_cells planes the
  *      molecular viscosity rises as nu(x) = nu0 + (nu_s - nu0) r^2,
@@ -100,6 +108,8 @@ typedef struct {
   double sponge_nu;    /* molecular viscosity at the outlet plane inside the sponge */
   int32_t outlet;      /* 0 convective (R13), 1 zero gradient (R20) */
   int32_t wall_law;    /* 0 Reichardt (R6), 1 Musker (R21) */
+  int32_t wall_avg;    /* 0 local u_tau (Sec. II.C), 1 z-line average (R23) */
+  int32_t pad_;
 } oracle_cfg;
 
 typedef struct {
@@ -510,21 +520,58 @@ int solve_utau(const R& ua, double y, double nu, const oracle_cfg& cfg, R* out) 
 }
 
 /* ---- Sec. II.C, Eq. (18)-(21): wall force in a first off-wall cell (R10) ---- */
+/* Eq. (18): the wall-parallel unit vector from the tangential part of u_2;
+   false when that part vanishes. */
 template <class R>
-int wall_force(const oracle_cfg& cfg, const R& rho_w, const R uw[3], const R u2[3], int top, R F[3],
-               R* utau_out) {
+bool wall_basis(const R u2[3], int top, R e[3]) {
   using std::sqrt;
   const double n[3] = {0.0, top ? -1.0 : 1.0, 0.0};
-  for (int a = 0; a < 3; ++a) F[a] = 0.0 * rho_w;
-  if (utau_out) *utau_out = 0.0 * rho_w;
   R un = u2[0] * n[0] + u2[1] * n[1] + u2[2] * n[2];
   R tv[3];
   for (int a = 0; a < 3; ++a) tv[a] = u2[a] - un * n[a];
   R tn2 = tv[0] * tv[0] + tv[1] * tv[1] + tv[2] * tv[2];
-  if (val(tn2) == 0.0) return OR_OK;
+  if (val(tn2) == 0.0) return false;
   R tn = sqrt(tn2);
+  for (int a = 0; a < 3; ++a) e[a] = tv[a] / tn;
+  return true;
+}
+
+/* Eq. (19): u_hat = u_w . e_x, 0 where e_x is undefined. */
+template <class R>
+R wall_uhat(const R uw[3], const R u2[3], int top) {
   R e[3];
-  for (int a = 0; a < 3; ++a) e[a] = tv[a] / tn; /* Eq. (18) */
+  if (!wall_basis(u2, top, e)) return 0.0 * uw[0];
+  return uw[0] * e[0] + uw[1] * e[1] + uw[2] * e[2];
+}
+
+/* Reading R23: the signed friction velocity sign(ubar) u_tau of a wall line from the
+   z-mean ubar of u_hat (Eq. (20) for |ubar|); 0 when ubar = 0. */
+template <class R>
+int line_utau(const oracle_cfg& cfg, const R& ubar, R* out) {
+  const double s = val(ubar) > 0.0 ? 1.0 : (val(ubar) < 0.0 ? -1.0 : 0.0);
+  *out = 0.0 * ubar;
+  if (s == 0.0) return OR_OK;
+  R ut;
+  const int st = solve_utau(s * ubar, cfg.y_wall, (cfg.tau0 - 0.5) * CS2, cfg, &ut);
+  *out = s * ut;
+  return st;
+}
+
+template <class R>
+int wall_force(const oracle_cfg& cfg, const R& rho_w, const R uw[3], const R u2[3], int top, R F[3],
+               R* utau_out, const R* line = nullptr) {
+  for (int a = 0; a < 3; ++a) F[a] = 0.0 * rho_w;
+  if (utau_out) *utau_out = 0.0 * rho_w;
+  R e[3];
+  if (line) { /* R23: the line's u_tau, the cell's own rho and e_x */
+    const double s = val(*line) > 0.0 ? 1.0 : (val(*line) < 0.0 ? -1.0 : 0.0);
+    if (utau_out) *utau_out = s * (*line);
+    if (s == 0.0 || !wall_basis(u2, top, e)) return OR_OK;
+    R tauw = rho_w * (*line) * (*line);
+    for (int a = 0; a < 3; ++a) F[a] = -s * tauw * e[a]; /* Eq. (21), A = 1 */
+    return OR_OK;
+  }
+  if (!wall_basis(u2, top, e)) return OR_OK; /* Eq. (18) */
   R uhat = uw[0] * e[0] + uw[1] * e[1] + uw[2] * e[2]; /* Eq. (19) */
   if (val(uhat) == 0.0) return OR_OK;
   const double sgn = val(uhat) > 0.0 ? 1.0 : -1.0;
@@ -670,6 +717,7 @@ struct Ctx {
   const double* uin;   /* [3][ny][nz] inlet velocity at t_{n+1} */
   size_t N;
   int nx, ny, nz;
+  const double* line = nullptr; /* [2][nx] signed line u_tau of the wall lines (R23), or NULL */
   size_t at(int i, int x, int y, int z) const { return (size_t)i * N + ((size_t)x * ny + y) * nz + z; }
 };
 
@@ -788,7 +836,7 @@ bool is_wall_cell(const oracle_cfg& cf, int y) {
  */
 template <class R>
 int node_core(const oracle_cfg& cf, int x, int y, const R f[19], const R f2[19], const R& cs_smag, R out[19],
-              R u_stat[3], R* utau = nullptr) {
+              R u_stat[3], R* utau = nullptr, const R* line = nullptr) {
   R rho, uw[3];
   pre_force_velocity(f, &rho, uw);
   R F[3] = {rho * cf.g[0], rho * cf.g[1], rho * cf.g[2]}; /* R9 */
@@ -798,7 +846,7 @@ int node_core(const oracle_cfg& cf, int x, int y, const R f[19], const R f2[19],
     R rho2, u2[3];
     pre_force_velocity(f2, &rho2, u2);
     R Fw[3];
-    st = wall_force(cf, rho, uw, u2, top, Fw, utau);
+    st = wall_force(cf, rho, uw, u2, top, Fw, utau, line);
     for (int a = 0; a < 3; ++a) F[a] = F[a] + Fw[a];
   }
   R tau;
@@ -823,12 +871,45 @@ int node_update(const Ctx& c, int x, int y, int z, double out[19], double hist_n
     for (int i = 0; i < 19; ++i) f2[i] = 0.0;
   }
   if (utau) *utau = 0.0;
-  int st = node_core(cf, x, y, f, f2, cf.cs_smag, out, u_stat, utau);
+  const double* line = (c.line && is_wall_cell(cf, y)) ? &c.line[(y == cf.ny - 1 ? cf.nx : 0) + x] : nullptr;
+  int st = node_core(cf, x, y, f, f2, cf.cs_smag, out, u_stat, utau, line);
   double rho = 0.0;
   for (int i = 0; i < 19; ++i) rho += f[i];
   if (!(rho > 0.0) || !std::isfinite(rho)) st = OR_ERR_NONFINITE;
   for (int i = 0; i < 19; ++i)
     if (!std::isfinite(out[i])) st = OR_ERR_NONFINITE;
+  return st;
+}
+
+bool line_mode(const oracle_cfg& cf) { return cf.wall_avg == 1 && cf.wall_model == 1 && cf.ywall != 0; }
+
+/* u_hat of the first off-wall cell (x, wall w, z) of a step (Eq. (18)-(19)). */
+double cell_uhat(const Ctx& c, int x, int w, int z) {
+  const oracle_cfg& cf = *c.cfg;
+  const int y = w ? cf.ny - 1 : 0;
+  double f[19], f2[19], h[5], rho, rho2, uw[3], u2[3];
+  bool o;
+  post_boundary(c, x, y, z, f, h, &o);
+  post_boundary(c, x, wall_neighbour_row(cf, y), z, f2, h, &o);
+  pre_force_velocity(f, &rho, uw);
+  pre_force_velocity(f2, &rho2, u2);
+  return wall_uhat(uw, u2, w);
+}
+
+/* Reading R23: the z-mean of u_hat of every wall line of a step, and its
+   signed u_tau, line[w * nx + x]. */
+int wall_lines(const Ctx& c, std::vector<double>& line) {
+  const oracle_cfg& cf = *c.cfg;
+  line.assign(2 * (size_t)cf.nx, 0.0);
+  int st = OR_OK;
+  for (int w = 0; w < 2; ++w)
+    for (int x = 0; x < cf.nx; ++x) {
+      double sum = 0.0;
+      for (int z = 0; z < cf.nz; ++z) sum += cell_uhat(c, x, w, z);
+      const double ubar = sum / (g_mutation == 15 ? cf.nz + 1 : cf.nz);
+      const int s = line_utau(cf, ubar, &line[(size_t)w * cf.nx + x]);
+      if (s != OR_OK) st = s;
+    }
   return st;
 }
 
@@ -840,6 +921,7 @@ bool cfg_ok(const oracle_cfg* cf) {
   if (cf->sponge_cells < 0 || cf->sponge_cells > cf->nx - 1) return false;
   if (cf->outlet != 0 && cf->outlet != 1) return false;
   if (cf->wall_law != 0 && cf->wall_law != 1) return false;
+  if (cf->wall_avg != 0 && cf->wall_avg != 1) return false;
   if (cf->sponge_cells > 0 && (cf->xbc != 1 || !(cf->sponge_nu > 0.0))) return false;
   return true;
 }
@@ -977,6 +1059,11 @@ int step_core(const oracle_cfg* cfg, const double* uin, const double* fin, doubl
   for (int p = 0; p < n_planes; ++p)
     if (planes[p] >= 0 && planes[p] < nx) plane_of[planes[p]] = p;
   int st_err = OR_OK;
+  std::vector<double> line;
+  if (line_mode(*cfg)) {
+    st_err = wall_lines(c, line);
+    c.line = line.data();
+  }
 #pragma omp parallel for collapse(2) schedule(static)
   for (int x = 0; x < nx; ++x)
     for (int y = 0; y < ny; ++y) {
@@ -1080,11 +1167,18 @@ int oracle_adjoint_step(const oracle_cfg* cfg, const oracle_stg* stg, double t_n
   std::vector<int> plane_of(nx, -1);
   for (int p = 0; p < n_planes; ++p)
     if (planes && planes[p] >= 0 && planes[p] < nx) plane_of[planes[p]] = p;
-
-  /* pass 1: dL/d(post-boundary populations) of every node, and dL/dC_s */
-  typedef Dual<39> D1;
-  std::vector<double> G(19 * N, 0.0), gcs_x(nx, 0.0);
   int st_err = OR_OK;
+  const bool lines = line_mode(*cfg);
+  std::vector<double> line, gline(lines ? 2 * (size_t)nx : 0, 0.0);
+  if (lines) {
+    st_err = wall_lines(c, line);
+    c.line = line.data();
+  }
+
+  /* pass 1: dL/d(post-boundary populations) of every node, dL/dC_s and, with
+     line-averaged u_tau, dL/d(line u_tau) (slot 39) */
+  typedef Dual<40> D1;
+  std::vector<double> G(19 * N, 0.0), gcs_x(nx, 0.0);
 #pragma omp parallel for schedule(static)
   for (int x = 0; x < nx; ++x) {
     for (int y = 0; y < ny; ++y)
@@ -1105,7 +1199,9 @@ int oracle_adjoint_step(const oracle_cfg* cfg, const oracle_stg* stg, double t_n
           f2d[i] = wall ? D1::seed(f2[i], 19 + i) : D1(0.0);
         }
         const D1 cs = D1::seed(cfg->cs_smag, 38);
-        int st = node_core(*cfg, x, y, fd, f2d, cs, out, u);
+        const size_t li = (size_t)(y == ny - 1 ? nx : 0) + x;
+        const D1 ld = (lines && wall) ? D1::seed(line[li], 39) : D1(0.0);
+        int st = node_core(*cfg, x, y, fd, f2d, cs, out, u, (D1*)nullptr, (lines && wall) ? &ld : nullptr);
         if (st != OR_OK) {
 #pragma omp critical
           st_err = st;
@@ -1122,12 +1218,51 @@ int oracle_adjoint_step(const oracle_cfg* cfg, const oracle_stg* stg, double t_n
         if (wall && g_mutation != 8)
           for (int i = 0; i < 19; ++i) G[c.at(i, x, y2, z)] += J.d[19 + i];
         gcs_x[x] += J.d[38];
+        if (lines && wall) gline[li] += J.d[39];
         if (is_out && g_mutation != 9)
           for (int k = 0; k < 5; ++k) G[c.at(OUT5[k], x, y, z)] += eta_next[(size_t)k * P + (size_t)y * nz + z];
       }
   }
   if (g_cs)
     for (int x = 0; x < nx; ++x) *g_cs += gcs_x[x];
+
+  /* pass 1b (R23): each line's u_tau depends on the mean u_hat of its cells,
+     so dL/d(line u_tau) goes back to the post-boundary populations of every
+     first and second off-wall cell of the line */
+  if (lines) {
+    typedef Dual<38> D3;
+    typedef Dual<1> D0;
+    for (int w = 0; w < 2; ++w)
+#pragma omp parallel for schedule(static)
+      for (int x = 0; x < nx; ++x) {
+        const double gl = gline[(size_t)w * nx + x];
+        if (gl == 0.0) continue;
+        const int y = w ? ny - 1 : 0, y2 = wall_neighbour_row(*cfg, y);
+        double sum = 0.0;
+        for (int z = 0; z < nz; ++z) sum += cell_uhat(c, x, w, z);
+        D0 l;
+        line_utau(*cfg, D0::seed(sum / nz, 0), &l);
+        const double gu = gl * l.d[0] / nz; /* dL/du_hat of each cell */
+        for (int z = 0; z < nz; ++z) {
+          double f[19], f2[19], h[5];
+          bool o;
+          post_boundary(c, x, y, z, f, h, &o);
+          post_boundary(c, x, y2, z, f2, h, &o);
+          D3 fd[19], f2d[19], rho, rho2, uw[3], u2[3];
+          for (int i = 0; i < 19; ++i) {
+            fd[i] = D3::seed(f[i], i);
+            f2d[i] = D3::seed(f2[i], 19 + i);
+          }
+          pre_force_velocity(fd, &rho, uw);
+          pre_force_velocity(f2d, &rho2, u2);
+          const D3 uh = wall_uhat(uw, u2, w);
+          for (int i = 0; i < 19; ++i) {
+            G[c.at(i, x, y, z)] += gu * uh.d[i];
+            if (g_mutation != 16) G[c.at(i, x, y2, z)] += gu * uh.d[19 + i];
+          }
+        }
+      }
+  }
 
   /* pass 2: through the boundary rules to the pulled sources, history and inlet velocity */
   typedef Dual<32> D2;
@@ -1175,6 +1310,28 @@ int oracle_adjoint_step(const oracle_cfg* cfg, const oracle_stg* stg, double t_n
  * The same update evaluated at a list of nodes only (for comparisons at full
  * lattice sizes): out[19][n_nodes], u_out[3][n_nodes] (force-corrected u).
  */
+/* Reading R23, for the pins: the signed line u_tau line[2][nx] and the u_hat
+   of every first off-wall cell uhat[2][nx][nz] of the step s_n -> s_{n+1}. */
+int oracle_wall_lines(const oracle_cfg* cfg, const oracle_stg* stg, double t_next, const double* fin,
+                      const double* hist_in, double* line, double* uhat) {
+  if (!cfg_ok(cfg) || !fin || cfg->wall_model != 1 || cfg->ywall == 0) return OR_ERR_ARG;
+  if (cfg->xbc == 1 && (!stg || !hist_in)) return OR_ERR_ARG;
+  const int nx = cfg->nx, ny = cfg->ny, nz = cfg->nz;
+  std::vector<double> uin;
+  if (cfg->xbc == 1) {
+    uin.resize((size_t)3 * ny * nz);
+    stg_plane(*cfg, *stg, t_next, uin.data(), nullptr);
+  }
+  Ctx c{cfg, fin, hist_in, uin.empty() ? nullptr : uin.data(), (size_t)nx * ny * nz, nx, ny, nz};
+  std::vector<double> l;
+  const int st = wall_lines(c, l);
+  std::memcpy(line, l.data(), l.size() * sizeof(double));
+  for (int w = 0; w < 2; ++w)
+    for (int x = 0; x < nx; ++x)
+      for (int z = 0; z < nz; ++z) uhat[((size_t)w * nx + x) * nz + z] = cell_uhat(c, x, w, z);
+  return st;
+}
+
 int oracle_step_nodes(const oracle_cfg* cfg, const oracle_stg* stg, double t_next, const double* fin,
                       const double* hist_in, int64_t n_nodes, const int64_t* nodes, double* out, double* u_out) {
   if (!cfg_ok(cfg) || !fin) return OR_ERR_ARG;
@@ -1188,6 +1345,11 @@ int oracle_step_nodes(const oracle_cfg* cfg, const oracle_stg* stg, double t_nex
   }
   Ctx c{cfg, fin, hist_in, uin.empty() ? nullptr : uin.data(), (size_t)nx * ny * nz, nx, ny, nz};
   int st_err = OR_OK;
+  std::vector<double> line;
+  if (line_mode(*cfg)) {
+    st_err = wall_lines(c, line);
+    c.line = line.data();
+  }
 #pragma omp parallel for schedule(dynamic, 64)
   for (long long k = 0; k < (long long)n_nodes; ++k) {
     const int64_t n = nodes[k];

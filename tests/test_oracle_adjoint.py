@@ -19,9 +19,9 @@ TOL = 2e-6  # central differences with h = 1e-4 on O(1e-2) directions: truncatio
 
 
 def setup(nx=5, ny=NY, nz=NZ, ywall=2, xbc=1, wm=1, g=(2e-6, 0.0, 0.0), seed=3, n_bins=3, cs=0.1, sponge=0,
-          outlet=0, law=0, spectrum=False):
+          outlet=0, law=0, spectrum=False, avg=0):
     cfg = O.make_cfg(nx, ny, nz, ywall=ywall, xbc=xbc, wall_model=wm, tau0=0.52, cs_smag=cs, g=g,
-                     sponge_cells=sponge, sponge_nu=0.02 if sponge else 0.0, outlet=outlet, wall_law=law)
+                     sponge_cells=sponge, sponge_nu=0.02 if sponge else 0.0, outlet=outlet, wall_law=law, wall_avg=avg)
     U = O.reichardt_inflow(cfg, 0.0084)
     du, dp = S.perturbations(nx, ny, nz, seed_offset=seed)
     u = U[:, None, :, None] + 3e-3 * du
@@ -38,7 +38,7 @@ def setup(nx=5, ny=NY, nz=NZ, ywall=2, xbc=1, wm=1, g=(2e-6, 0.0, 0.0), seed=3, 
 def with_cs(cfg, cs):
     c = O.make_cfg(cfg.nx, cfg.ny, cfg.nz, ywall=cfg.ywall, xbc=cfg.xbc, wall_model=cfg.wall_model,
                    tau0=cfg.tau0, cs_smag=cs, g=tuple(cfg.g), rates=list(cfg.s), sponge_cells=cfg.sponge_cells,
-                   sponge_nu=cfg.sponge_nu, outlet=cfg.outlet, wall_law=cfg.wall_law)
+                   sponge_nu=cfg.sponge_nu, outlet=cfg.outlet, wall_law=cfg.wall_law, wall_avg=cfg.wall_avg)
     return c
 
 
@@ -52,6 +52,8 @@ CASES = {
     "slip_inflow_zero_gradient_outlet": dict(ywall=2, xbc=1, wm=1, outlet=1),
     "slip_inflow_musker_wall_law": dict(ywall=2, xbc=1, wm=1, law=1),
     "slip_inflow_row_spectrum": dict(ywall=2, xbc=1, wm=1, spectrum=True),
+    "slip_inflow_line_averaged_utau": dict(ywall=2, xbc=1, wm=1, avg=1),
+    "bounceback_periodic_x_line_averaged_utau": dict(ywall=1, xbc=0, wm=1, g=(4e-6, 0.0, 0.0), avg=1),
     "bounceback_inflow_musker_wall_law": dict(ywall=1, xbc=1, wm=1, law=1),
 }
 
@@ -109,11 +111,11 @@ def test_adjoint_dot_product_matches_fd(name):
         assert e < TOL, (name, k, e, fd, a)
 
 
-@pytest.mark.parametrize("mutation,part", [(8, "s"), (9, "hist"), (10, "s")])
-def test_planted_adjoint_mistakes_fail(mutation, part):
+@pytest.mark.parametrize("mutation,part,avg", [(8, "s", 0), (9, "hist", 0), (10, "s", 0), (16, "s", 1)])
+def test_planted_adjoint_mistakes_fail(mutation, part, avg):
     """8: wall-neighbour term dropped; 9: outlet history sensitivity dropped;
-    10: outlet upstream term dropped."""
-    cfg, f, hist, stg = setup()
+    10: outlet upstream term dropped; 16: the line average's second-cell term dropped."""
+    cfg, f, hist, stg = setup(avg=avg)
     O.set_mutation(mutation)
     try:
         errs = dot_test(cfg, f, hist, stg)
