@@ -54,6 +54,7 @@ enum { LBM_Y_PERIODIC = 0, LBM_Y_BOUNCEBACK = 1, LBM_Y_SLIP = 2 };
 enum { LBM_X_PERIODIC = 0, LBM_X_INFLOW = 1 };
 enum { LBM_OUTLET_CONVECTIVE = 0, LBM_OUTLET_ZERO_GRADIENT = 1 };
 enum { LBM_WALL_REICHARDT = 0, LBM_WALL_MUSKER = 1 };
+enum { LBM_WALL_AVG_LOCAL = 0, LBM_WALL_AVG_LINE = 1 };
 enum { LBM_STATS_ATTACH = 1, LBM_STATS_DETACH = 2, LBM_STATS_RESET = 3, LBM_STATS_READ = 4, LBM_STATS_READ_WALL = 5 };
 
 /*
@@ -78,6 +79,17 @@ enum { LBM_STATS_ATTACH = 1, LBM_STATS_DETACH = 2, LBM_STATS_RESET = 3, LBM_STAT
  *              (y+^2 - 8.15y+ + 86)^2) + C, with C = -3.5113 so that u+(0) = 0;
  *              the rounded -3.52 often printed would leave no positive u_tau
  *              below y+ = 0.009).
+ *  wall_avg    LBM_WALL_AVG_LOCAL: u_tau from each cell's own u_hat (Sec. II.C);
+ *              LBM_WALL_AVG_LINE: the plane-averaged u_tau that Sec. II.C
+ *              contrasts with its local one, averaged over the homogeneous
+ *              direction z of each wall line (x, wall): u_hat = u_w . e_x
+ *              (Eq. (19); 0 where u_2 has no tangential part) is averaged over
+ *              z in the same step, Eq. (20) is solved once per line for the
+ *              mean's magnitude, and each cell of the line takes
+ *              F_w = -sign(mean) rho u_tau^2 e_x with its own rho and e_x; the
+ *              wall statistics then report the line's u_tau at every cell.
+ *              Costs one extra launch per step reading the two rows next to
+ *              each wall.  Not supported by lbm_adjoint_step (LBM_ERR_ARG).
  *  wall_model  1: Reichardt wall force in the first off-wall cells (Sec. II.C,
  *              Eq. (16)-(21)), u_tau by newton_iters Newton steps from the
  *              viscous-sublayer estimate (0: 4; in FP32 the iteration reaches
@@ -108,7 +120,7 @@ typedef struct {
   int32_t sponge_cells;
   int32_t outlet;
   int32_t wall_law;
-  int32_t reserved_;           /* 0 */
+  int32_t wall_avg;
   double tau0;
   double cs_smag;
   double s[19];

@@ -11,6 +11,7 @@ Y_PERIODIC, Y_BOUNCEBACK, Y_SLIP = 0, 1, 2
 X_PERIODIC, X_INFLOW = 0, 1
 OUTLET_CONVECTIVE, OUTLET_ZERO_GRADIENT = 0, 1
 WALL_REICHARDT, WALL_MUSKER = 0, 1
+WALL_AVG_LOCAL, WALL_AVG_LINE = 0, 1
 STATS_ATTACH, STATS_DETACH, STATS_RESET, STATS_READ, STATS_READ_WALL = 1, 2, 3, 4, 5
 MAX_MODES = 1024
 
@@ -26,7 +27,7 @@ EXPORTED = [
 class Config(C.Structure):
     _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32), ("storage", C.c_int32),
                 ("ywall", C.c_int32), ("xbc", C.c_int32), ("wall_model", C.c_int32), ("newton_iters", C.c_int32),
-                ("sponge_cells", C.c_int32), ("outlet", C.c_int32), ("wall_law", C.c_int32), ("reserved_", C.c_int32),
+                ("sponge_cells", C.c_int32), ("outlet", C.c_int32), ("wall_law", C.c_int32), ("wall_avg", C.c_int32),
                 ("tau0", C.c_double), ("cs_smag", C.c_double), ("s", C.c_double * 19),
                 ("kappa", C.c_double), ("b_reich", C.c_double), ("y_wall", C.c_double),
                 ("u_conv", C.c_double), ("g", C.c_double * 3), ("sponge_nu", C.c_double)]

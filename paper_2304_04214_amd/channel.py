@@ -39,7 +39,7 @@ class Channel:
     def __init__(self, nx, ny, nz, *, tau0, storage="f32", ywall="slip", xbc="periodic", wall_model=False,
                  cs_smag=0.1, rates=None, kappa=0.41, b_reich=7.8, y_wall=0.5, u_conv=0.1, g=(0.0, 0.0, 0.0),
                  newton_iters=4, sponge_cells=0, sponge_nu=0.0, outlet="convective", wall_law="reichardt",
-                 device=None):
+                 wall_avg="local", device=None):
         self.device = torch.device(device if device is not None else "cuda")
         self.nx, self.ny, self.nz = nx, ny, nz
         self.N = nx * ny * nz
@@ -60,6 +60,7 @@ class Channel:
         cfg.sponge_cells, cfg.sponge_nu = int(sponge_cells), float(sponge_nu)
         cfg.outlet = _OUTLET[outlet]
         cfg.wall_law = _WALL_LAW[wall_law]
+        cfg.wall_avg = {"local": A.WALL_AVG_LOCAL, "line": A.WALL_AVG_LINE}[wall_avg]
         self.cfg = cfg
         dt = torch.float32 if storage == "f32" else torch.float16
         elems = C.c_int64()

@@ -41,6 +41,7 @@ lbm_status check_config(const lbm_config* c) {
   if (c->xbc == LBM_X_INFLOW && !(c->u_conv >= 0.0)) return LBM_ERR_ARG;
   if (c->outlet != LBM_OUTLET_CONVECTIVE && c->outlet != LBM_OUTLET_ZERO_GRADIENT) return LBM_ERR_ARG;
   if (c->wall_law != LBM_WALL_REICHARDT && c->wall_law != LBM_WALL_MUSKER) return LBM_ERR_ARG;
+  if (c->wall_avg != LBM_WALL_AVG_LOCAL && c->wall_avg != LBM_WALL_AVG_LINE) return LBM_ERR_ARG;
   if (c->sponge_cells < 0 || c->sponge_cells > c->nx - 1) return LBM_ERR_ARG;
   if (c->sponge_cells > 0 && (c->xbc != LBM_X_INFLOW || !(c->sponge_nu > 0.0))) return LBM_ERR_ARG;
   return LBM_OK;
@@ -249,6 +250,7 @@ lbm_status lbm_destroy(lbm_handle h) {
   free_tables(h);
   if (h->d_stats) (void)hipFree(h->d_stats);
   if (h->d_wall_acc) (void)hipFree(h->d_wall_acc);
+  if (h->d_wall_line) (void)hipFree(h->d_wall_line);
   if (h->d_plane_of_x) (void)hipFree(h->d_plane_of_x);
   if (h->d_blist_int) (void)hipFree(h->d_blist_int);
   if (h->d_blist_bnd) (void)hipFree(h->d_blist_bnd);
@@ -523,6 +525,7 @@ lbm_status lbm_adjoint_step(lbm_handle h, const lbm_stg* stg, const void* s_n, c
   const bool inflow = h->cfg.xbc == LBM_X_INFLOW;
   if (inflow && (!hist_n || !eta_next || !eta_prev || eta_next == eta_prev)) return LBM_ERR_ARG;
   if (!u_in_next != !fluct_next) return LBM_ERR_ARG;  // the inlet plane is given whole or recomputed
+  if (h->cfg.wall_avg == LBM_WALL_AVG_LINE && h->cfg.wall_model) return LBM_ERR_ARG;  // local u_tau only
   if (stg) {
     lbm_status st = bind_stg(h, stg);
     if (st != LBM_OK) return st;

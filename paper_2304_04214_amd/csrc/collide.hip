@@ -33,15 +33,26 @@ namespace {
 // base vector from the tangential part of u_2, projected speed u_hat, u_tau
 // from a fixed number of Newton steps on u_tau u+(y u_tau / nu0) = |u_hat|,
 // F_w = -sign(u_hat) rho u_tau^2 e_x.  The wall normal is along y.
+//
+// With the line-averaged model (wall_line set) u_tau is the signed value of
+// the cell's wall line, computed by wall_line_kernel from the z-mean of u_hat.
 __device__ __forceinline__ void wall_force(const CollideArgs& a, float rho, float uwx, float uwz, float u2x,
-                                           float u2z, float& fx, float& fz, float& ut_out) {
+                                           float u2z, float& fx, float& fz, float& ut_out, int w, int x) {
   fx = 0.f;
   fz = 0.f;
   ut_out = 0.f;
+  const float line = a.wall_line ? a.wall_line[w * a.nx + x] : 0.f;
+  if (a.wall_line) ut_out = fabsf(line);
   const float tn2 = u2x * u2x + u2z * u2z;
   if (!(tn2 > 0.f)) return;
   const float itn = 1.f / sqrtf(tn2);
   const float ex = u2x * itn, ez = u2z * itn;
+  if (a.wall_line) {
+    const float tw = (line > 0.f ? -1.f : 1.f) * rho * line * line;
+    fx = tw * ex;
+    fz = tw * ez;
+    return;
+  }
   const float uhat = uwx * ex + uwz * ez;
   if (uhat == 0.f) return;
   const float ut = newton_utau(a, fabsf(uhat));
@@ -206,10 +217,11 @@ __device__ __forceinline__ Node decode(const CollideArgs& a) {
 
 // Boundary rules, wall model, collision, store and statistics of one node
 // whose pulled populations are in f (Algorithm 1 for one cell).
+// The outlet and inlet rules of an open channel on the pulled populations f
+// of node (x, y, z); store: write the outlet history of the step.
 template <bool F16>
-__device__ __forceinline__ void node_update(const CollideArgs& a, int x, int y, int z, int lane, int base, int zci,
-                                            bool owned, bool active, const Col& col, float f[Q],
-                                            float (*lds_u2)[2][ZT]) {
+__device__ __forceinline__ void x_rules(const CollideArgs& a, int x, int y, int z, const Col& col, float f[Q],
+                                        bool store) {
   const bool inflow = a.xbc == LBM_X_INFLOW;
   if (inflow && x == a.nx - 1) {  // convective outlet for c_x < 0
     const Geo g2 = make_geo(a, x - 1, y);
@@ -220,10 +232,17 @@ __device__ __forceinline__ void node_update(const CollideArgs& a, int x, int y, 
       const int hidx = (k * a.ny + y) * a.nz + z;
       const float v = a.out_wh * a.hist_in[hidx] + a.out_wu * up;
       f[i] = v;
-      if (active && owned) a.hist_out[hidx] = v;
+      if (store) a.hist_out[hidx] = v;
     }
   }
   if (inflow && x == 0) inlet_regularize(a, y, z, f);
+}
+
+template <bool F16>
+__device__ __forceinline__ void node_update(const CollideArgs& a, int x, int y, int z, int lane, int base, int zci,
+                                            bool owned, bool active, const Col& col, float f[Q],
+                                            float (*lds_u2)[2][ZT]) {
+  x_rules<F16>(a, x, y, z, col, f, active && owned);
 
   // density and momentum before the force (Eq. (10)-(11))
   const Pairs pr = make_pairs(f);
@@ -256,7 +275,7 @@ __device__ __forceinline__ void node_update(const CollideArgs& a, int x, int y, 
       if (wb || wt) {
         const int w = wb ? 0 : 1;
         float fwx, fwz, ut;
-        wall_force(a, rho, jx * ir, jz * ir, lds_u2[w][0][lane], lds_u2[w][1][lane], fwx, fwz, ut);
+        wall_force(a, rho, jx * ir, jz * ir, lds_u2[w][0][lane], lds_u2[w][1][lane], fwx, fwz, ut, w, x);
         Fx += fwx;
         Fz += fwz;
         force = true;
@@ -397,6 +416,66 @@ __global__ __launch_bounds__(BLOCK) void collide_general_kernel(CollideArgs a, c
   node_update<F16>(a, x, y, z, lane, base, zci, owned, active, col, f, lds_u2);
 }
 
+// Pre-force velocity (u_x, u_z) of node (x, y, z) after streaming and the
+// boundary rules, as node_update forms it.
+template <bool F16>
+__device__ __forceinline__ void pre_force_uxz(const CollideArgs& a, int x, int y, int z, const Col& col, float& ux,
+                                              float& uz) {
+  const Geo g = make_geo(a, x, y);
+  typename Pop<F16>::Raw r[Q];
+  issue_pulls<F16>(a, g, col, r);
+  float f[Q];
+  convert_pulls<F16>(a, g, r, f);
+  x_rules<F16>(a, x, y, z, col, f, false);
+  const Pairs pr = make_pairs(f);
+  const float rho = pr.A + pr.Bx + f[9];
+  const float jx = (pr.d[3] + pr.d[7]) - (pr.d[1] + pr.d[5] + pr.d[8]);
+  const float jz = -(pr.d[0] + pr.d[1] + pr.d[2] + pr.d[3] + pr.d[4]);
+  const float ir = 1.f / rho;
+  ux = jx * ir;
+  uz = jz * ir;
+}
+
+// Line-averaged wall model: one block per wall line (x, wall).  Its four
+// waves sum u_hat = u_w . e_x (Eq. (19), 0 where u_2 has no tangential part)
+// over z in FP64 in a fixed order; the line's u_tau solves Eq. (20) for the
+// mean's magnitude and is stored with the mean's sign.
+template <bool F16>
+__global__ __launch_bounds__(BLOCK) void wall_line_kernel(CollideArgs a, float* line) {
+  __shared__ double part[BLOCK / ZT];
+  const int x = blockIdx.x, w = blockIdx.y;
+  const int yw = w ? a.ny - 1 : 0, y2 = w ? a.ny - 2 : 1;
+  const int lane = threadIdx.x & (ZT - 1), wave = uni(threadIdx.x >> 6);
+  double acc = 0.0;
+  for (int zci = wave; zci < a.zc; zci += BLOCK / ZT) {
+    const int zraw = zci * ZT + lane;
+    const bool active = zraw < a.nz;
+    const int z = active ? zraw : a.nz - 1;
+    const Col col = make_col<F16>(a, z);
+    float uwx, uwz, u2x, u2z;
+    pre_force_uxz<F16>(a, x, yw, z, col, uwx, uwz);
+    pre_force_uxz<F16>(a, x, y2, z, col, u2x, u2z);
+    const float tn2 = u2x * u2x + u2z * u2z;
+    float uh = 0.f;
+    if (tn2 > 0.f) {
+      const float itn = 1.f / sqrtf(tn2);
+      uh = uwx * (u2x * itn) + uwz * (u2z * itn);
+    }
+    acc += active ? (double)uh : 0.0;
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, ZT);
+  if (lane == 0) part[wave] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double s = 0.0;
+    for (int k = 0; k < BLOCK / ZT; ++k) s += part[k];
+    const float ub = (float)(s / a.nz);
+    const float ut = ub != 0.f ? newton_utau(a, fabsf(ub)) : 0.f;
+    line[w * a.nx + x] = ub > 0.f ? ut : -ut;
+  }
+}
+
 // Pull with the wall rules only (debug map); unset populations are -1.
 __global__ __launch_bounds__(BLOCK) void stream_only_kernel(CollideArgs a) {
   const Node nd = decode(a);
@@ -477,6 +556,7 @@ void fill_args(lbm_ctx* h, CollideArgs& a, int src, int dst) {
   a.u_in = h->stg_bound ? h->stg.u_in : nullptr;
   a.stats = h->d_stats;
   a.wall_acc = h->stats_on ? h->d_wall_acc : nullptr;
+  a.wall_line = nullptr;
   a.plane_of_x = h->d_plane_of_x;
   a.err = h->d_err;
   a.nx = c.nx;
@@ -520,11 +600,31 @@ void fill_args(lbm_ctx* h, CollideArgs& a, int src, int dst) {
 }
 
 
+// The line-averaged u_tau of the step a describes, into h->d_wall_line (a
+// no-op unless that model is configured); a.wall_line then points there.
+hipError_t launch_wall_line(lbm_ctx* h, CollideArgs& a, hipStream_t stream) {
+  const lbm_config& c = h->cfg;
+  if (c.wall_avg != LBM_WALL_AVG_LINE || !c.wall_model || c.ywall == LBM_Y_PERIODIC) return hipSuccess;
+  if (!h->d_wall_line) {
+    hipError_t e = hipMalloc(&h->d_wall_line, sizeof(float) * 2 * c.nx);
+    if (e != hipSuccess) return e;
+  }
+  dim3 grid(c.nx, 2);
+  if (c.storage == LBM_STORE_F16DEV)
+    wall_line_kernel<true><<<grid, BLOCK, 0, stream>>>(a, h->d_wall_line);
+  else
+    wall_line_kernel<false><<<grid, BLOCK, 0, stream>>>(a, h->d_wall_line);
+  a.wall_line = h->d_wall_line;
+  return hipGetLastError();
+}
+
 hipError_t launch_boundary(lbm_ctx* h, int src, int dst, hipStream_t stream, const float* u_in) {
   if (h->n_bnd == 0) return hipSuccess;
   CollideArgs a;
   fill_args(h, a, src, dst);
   if (u_in) a.u_in = u_in;
+  hipError_t e = launch_wall_line(h, a, stream);
+  if (e != hipSuccess) return e;
   if (h->cfg.storage == LBM_STORE_F16DEV)
     collide_general_kernel<true><<<h->n_bnd, BLOCK, 0, stream>>>(a, h->d_blist_bnd);
   else
@@ -546,6 +646,8 @@ hipError_t launch_step_explicit(lbm_ctx* h, const void* src, void* dst, const fl
   a.stats_on = 0;
   a.wall_acc = nullptr;
   const bool f16 = h->cfg.storage == LBM_STORE_F16DEV;
+  hipError_t e = launch_wall_line(h, a, stream);
+  if (e != hipSuccess) return e;
   if (h->n_bnd > 0) {
     if (f16)
       collide_general_kernel<true><<<h->n_bnd, BLOCK, 0, stream>>>(a, h->d_blist_bnd);

@@ -32,6 +32,7 @@ struct CollideArgs {
   const float* u_in;      // [3][ny][nz]
   double* stats;          // [n_planes][ny][zc][9]
   double* wall_acc;       // [2][nx][zc] sums of u_tau in the first off-wall rows, or null
+  const float* wall_line; // [2][nx] signed u_tau of each wall line (line-averaged model), or null
   const int* plane_of_x;  // [nx], -1 when not sampled
   int* err;
   int nx, ny, nz, zc, yg, nblocks;
@@ -101,6 +102,7 @@ struct lbm_ctx {
   bool split = false;
   double* d_stats = nullptr;
   double* d_wall_acc = nullptr;  // [2][nx][zc], with the wall model
+  float* d_wall_line = nullptr;  // [2][nx] line-averaged u_tau of the current step
   int n_planes = 0;
   std::vector<int> plane_of_x;  // host copy of d_plane_of_x
   int stats_on = 0;

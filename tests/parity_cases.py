@@ -23,13 +23,15 @@ class Case:
     def __init__(self, nx, ny, nz, *, ywall="slip", xbc="inflow", wall_model=True, tau0=0.52, cs_smag=0.1,
                  u_tau=0.008369396673286735, n_modes=24, seed=0, storage="f32", g=(0.0, 0.0, 0.0), eps=0.05,
                  du_amp=1e-3, u_conv=0.1, newton_iters=4, amp_scale=1.0, rates=None, sponge_cells=0,
-                 sponge_nu=0.0, outlet="convective", wall_law="reichardt", spectrum=False):
+                 sponge_nu=0.0, outlet="convective", wall_law="reichardt", spectrum=False,
+                 wall_avg="local"):
         self.nx, self.ny, self.nz = nx, ny, nz
         self.xbc = xbc
         self.ocfg = O.make_cfg(nx, ny, nz, ywall=YW[ywall], xbc=XB[xbc], wall_model=int(wall_model), tau0=tau0,
                                cs_smag=cs_smag, u_conv=u_conv, g=g, rates=rates, sponge_cells=sponge_cells,
                                sponge_nu=sponge_nu, outlet={"convective": 0, "zero-gradient": 1}[outlet],
-                               wall_law={"reichardt": 0, "musker": 1}[wall_law])
+                               wall_law={"reichardt": 0, "musker": 1}[wall_law],
+                               wall_avg={"local": 0, "line": 1}[wall_avg])
         # spectrum: per-row spectral weights from synthetic RANS k, omega (the table's q is then unused)
         self.mt = S.mode_table(n_modes, ny / 2, seed_offset=seed,
                                k_range=S.spectrum_k_range(ny / 2) if spectrum else None)
@@ -47,7 +49,8 @@ class Case:
         # ---- HIP side ----
         self.ch = Channel(nx, ny, nz, tau0=tau0, storage=storage, ywall=ywall, xbc=xbc, wall_model=wall_model,
                           cs_smag=cs_smag, u_conv=u_conv, g=g, newton_iters=newton_iters, rates=rates,
-                          sponge_cells=sponge_cells, sponge_nu=sponge_nu, outlet=outlet, wall_law=wall_law)
+                          sponge_cells=sponge_cells, sponge_nu=sponge_nu, outlet=outlet, wall_law=wall_law,
+                          wall_avg=wall_avg)
         U_g = self.ch.inflow_reichardt(u_tau)
         self.U_g = U_g
         u_g = U_g.float()[:, None, :, None] + du_amp * torch.as_tensor(du, dtype=torch.float32, device="cuda")

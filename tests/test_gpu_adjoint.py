@@ -144,6 +144,11 @@ def test_adjoint_rejects_bad_arguments():
     with pytest.raises(A.LbmError):  # open channel without eta buffers
         ch.adjoint_step(f_cur, h_cur, 1.0, lam, ch.new_field())
     ch.sync()
+    line = Case(6, 8, 16, wall_avg="line").ch  # the adjoint covers the local u_tau only
+    f_cur, h_cur = line.state()
+    with pytest.raises(A.LbmError):
+        line.adjoint_step(f_cur, h_cur, 1.0, line.new_field(), line.new_field(), eta, torch.zeros_like(eta))
+    line.sync()
 
 
 def test_multistep_statistics_gradient_matches_oracle():
@@ -191,11 +196,12 @@ def loss_grad(m, U_t, R12_t):
     return d
 
 
-@pytest.mark.parametrize("storage", ["f32", "f16dev"])
-def test_step_record_matches_step(storage):
+@pytest.mark.parametrize("storage,avg", [("f32", "local"), ("f16dev", "local"), ("f32", "line"), ("f16dev", "line")])
+def test_step_record_matches_step(storage, avg):
     """The recompute entry point reproduces lbm_step bit for bit (same kernels,
     caller buffers) and keeps the inlet plane of every step."""
-    case = Case(8, 8, 70, ywall="slip", xbc="inflow", wall_model=True, storage=storage, g=(2e-6, 0.0, 0.0))
+    case = Case(8, 8, 70, ywall="slip", xbc="inflow", wall_model=True, storage=storage, g=(2e-6, 0.0, 0.0),
+                wall_avg=avg)
     ch = case.ch
     f0, h0 = [t.clone() for t in ch.state()]
     t0 = ch.time

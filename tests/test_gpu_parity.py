@@ -72,6 +72,11 @@ PARITY_CASES = {
                                                                        wall_model=True, wall_law="musker")),
     "slip-inflow-row-spectrum": dict(shape=(7, 10, 70), kw=dict(ywall="slip", xbc="inflow", wall_model=True,
                                                                n_modes=120, spectrum=True)),
+    "slip-inflow-line-averaged-utau": dict(shape=(7, 10, 70), kw=dict(ywall="slip", xbc="inflow", wall_model=True,
+                                                                     wall_avg="line")),
+    "bounceback-periodic-line-averaged-utau": dict(shape=(5, 9, 66), kw=dict(ywall="bounceback", xbc="periodic",
+                                                                            wall_model=True, g=(1e-5, 0.0, 0.0),
+                                                                            wall_avg="line")),
     "re1000-like": dict(shape=(8, 12, 64), kw=dict(ywall="slip", xbc="inflow", wall_model=True,
                                                   tau0=0.5004270558446486, u_tau=0.004448498381757104,
                                                   n_modes=50)),
@@ -135,10 +140,13 @@ def test_statistics_match_oracle():
     assert err <= TOL32
 
 
-@pytest.mark.parametrize("storage,law", [("f32", "reichardt"), ("f16dev", "reichardt"), ("f32", "musker")])
-def test_wall_statistics_match_oracle(storage, law):
+@pytest.mark.parametrize("storage,law,avg", [("f32", "reichardt", "local"), ("f16dev", "reichardt", "local"),
+                                            ("f32", "musker", "local"), ("f32", "reichardt", "line"),
+                                            ("f16dev", "reichardt", "line")])
+def test_wall_statistics_match_oracle(storage, law, avg):
     """Mean over z and steps of the wall law's u_tau at every x, both walls."""
-    c = Case(9, 10, 70, ywall="slip", xbc="inflow", wall_model=True, n_modes=30, storage=storage, wall_law=law)
+    c = Case(9, 10, 70, ywall="slip", xbc="inflow", wall_model=True, n_modes=30, storage=storage, wall_law=law,
+             wall_avg=avg)
     c.ch.stats_attach([4])
     c.ch.step(12)
     wall, n = c.ch.stats_read_wall()
@@ -225,7 +233,7 @@ def test_nonfinite_density_is_reported():
 
 
 @pytest.mark.parametrize("name", ["slip-inflow-wallmodel", "periodic-smag-force", "slip-inflow-wallmodel-sponge",
-                                  "slip-inflow-musker-wall-law"])
+                                  "slip-inflow-musker-wall-law", "slip-inflow-line-averaged-utau"])
 def test_fp16_deviation_storage_matches_oracle(name):
     spec = PARITY_CASES[name]
     _say("fp16 parity", name)
