@@ -89,7 +89,7 @@ enum { LBM_STATS_ATTACH = 1, LBM_STATS_DETACH = 2, LBM_STATS_RESET = 3, LBM_STAT
  *              F_w = -sign(mean) rho u_tau^2 e_x with its own rho and e_x; the
  *              wall statistics then report the line's u_tau at every cell.
  *              Costs one extra launch per step reading the two rows next to
- *              each wall.  Not supported by lbm_adjoint_step (LBM_ERR_ARG).
+ *              each wall (lbm_adjoint_step: two, over the wall blocks).
  *  wall_model  1: Reichardt wall force in the first off-wall cells (Sec. II.C,
  *              Eq. (16)-(21)), u_tau by newton_iters Newton steps from the
  *              viscous-sublayer estimate (0: 4; in FP32 the iteration reaches

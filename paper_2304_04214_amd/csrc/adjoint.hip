@@ -14,6 +14,11 @@
 // from.  Couplings between nodes beyond the pull:
 //  * wall model: a first off-wall cell reads the velocity of the next row;
 //    its sensitivity goes back to that row through LDS (the block holds both);
+//  * line-averaged wall model: every first off-wall cell of a wall line
+//    (x, wall) takes the line's u_tau, a function of the z-mean of u_hat over
+//    the line.  A first launch over the wall blocks stops each wall cell's
+//    adjoint at dL/d(line u_tau) and sums it per line chunk; the main launch
+//    then gives every cell of the line its share through the mean;
 //  * convective outlet: the outlet node at x = nx-1 reads the pulled values of
 //    the node at nx-2.  The thread of node (nx-2, y, z) does the outlet node
 //    (nx-1, y, z) first, stores dL/dhist_n and adds the outlet node's
@@ -168,7 +173,10 @@ struct AdjLds {
 // comment).  gup: on the outlet plane (x = nx-1) receives U_c dL/dhist_n of the
 // c_x < 0 populations; on the plane x = nx-2 it is added to them.  csb: the
 // node's dL/dC_s is added.  Block-uniform x; contains __syncthreads.
-template <bool F16>
+//
+// PROBE (line-averaged model only): stop after the wall force and store the
+// wave's sum of dL/d(line u_tau) of the wall rows in A.line_part.
+template <bool F16, bool PROBE = false>
 __device__ __forceinline__ void node_adjoint(const AdjointArgs& A, AdjLds& L, int x, int y, int z, int lane,
                                              int base, int zci, bool own, bool active, float gup[5], float& csb) {
   const CollideArgs& a = A.c;
@@ -212,8 +220,8 @@ __device__ __forceinline__ void node_adjoint(const AdjointArgs& A, AdjLds& L, in
   const bool wrow = wblock && ((bot && y == 0) || (top && y == a.ny - 1));
   const bool nrow = wblock && ((bot && y == 1) || (top && y == a.ny - 2));
   const int wslot = (bot && y <= 1) ? 0 : 1;
-  bool wact = false;
-  float wex = 0.f, wez = 0.f, witn = 0.f, wtw = 0.f, wut = 1.f, wdg = 1.f, wsg = 0.f;
+  bool wact = false, wbas = false;  // force applied; base vector defined
+  float wex = 0.f, wez = 0.f, witn = 0.f, wtw = 0.f, wut = 1.f, wdg = 1.f, wsg = 0.f, wline = 0.f;
   if (wblock) {
     if (nrow) {
       L.u2[wslot][0][lane] = jx * iw;
@@ -223,7 +231,26 @@ __device__ __forceinline__ void node_adjoint(const AdjointArgs& A, AdjLds& L, in
     if (wrow) {
       const float u2x = L.u2[wslot][0][lane], u2z = L.u2[wslot][1][lane];
       const float tn2 = u2x * u2x + u2z * u2z;
-      if (tn2 > 0.f) {
+      if (tn2 > 0.f && a.wall_line) {  // line-averaged: the line's signed u_tau
+        wbas = true;
+        witn = 1.f / sqrtf(tn2);
+        wex = u2x * witn;
+        wez = u2z * witn;
+        wline = a.wall_line[wslot * a.nx + x];
+        if (wline != 0.f) {
+          wact = true;
+          wut = fabsf(wline);
+          wsg = wline > 0.f ? 1.f : -1.f;
+          wtw = -wsg * rho * wline * wline;
+          Fx += wtw * wex;
+          Fz += wtw * wez;
+          const float yp = a.y_wall * wut * a.inv_nu0;
+          float up, dup;
+          wall_law(a, yp, up, dup);
+          wdg = up + yp * dup;  // d(u_tau u+)/du_tau at the line's root
+        }
+      } else if (tn2 > 0.f) {
+        wbas = true;
         witn = 1.f / sqrtf(tn2);
         wex = u2x * witn;
         wez = u2z * witn;
@@ -357,7 +384,42 @@ __device__ __forceinline__ void node_adjoint(const AdjointArgs& A, AdjLds& L, in
   // ---- reverse: wall force F_w = -sign(u_hat) rho u_tau^2 e ----
   if (wblock) {
     float u2xb = 0.f, u2zb = 0.f;
-    if (wact) {
+    if (a.wall_line) {
+      float exb = 0.f, ezb = 0.f, uhb = 0.f, lb = 0.f;
+      if (wact) {  // rho and e_x of the cell itself; u_tau of the line
+        const float twb = Fxb * wex + Fzb * wez;
+        exb = wtw * Fxb;
+        ezb = wtw * Fzb;
+        rhob += twb * wtw * iw;
+        lb = twb * 2.f * wtw / wline;  // d tw / d line = 2 tw / line
+      }
+      if constexpr (PROBE) {
+        if (wrow) {  // wave-uniform: the whole wave reduces
+          double v = (active && wact) ? (double)lb : 0.0;
+#pragma unroll
+          for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, ZT);
+          if (lane == 0) A.line_part[((size_t)wslot * a.nx + x) * a.zc + zci] = v;
+        }
+        return;
+      }
+      if (wact) {
+        double s = 0.0;  // dL/d(line u_tau): the line's chunks in order
+        for (int k = 0; k < a.zc; ++k) s += A.line_part[((size_t)wslot * a.nx + x) * a.zc + k];
+        uhb = (float)s / (wdg * (float)a.nz);  // d line / d mean = 1 / wdg; d mean / d u_hat = 1 / nz
+      }
+      if (wbas) {  // u_hat = u_w . e_x of this cell entered the line's mean
+        const float uwx = jx * iw, uwz = jz * iw;
+        exb += uhb * uwx;
+        ezb += uhb * uwz;
+        const float uwxb = uhb * wex, uwzb = uhb * wez;
+        jxb += uwxb * iw;
+        jzb += uwzb * iw;
+        rhob -= (uwxb * uwx + uwzb * uwz) * iw;
+        const float ed = wex * exb + wez * ezb;  // e = t / |t|
+        u2xb = (exb - wex * ed) * witn;
+        u2zb = (ezb - wez * ed) * witn;
+      }
+    } else if (wact) {
       const float twb = Fxb * wex + Fzb * wez;
       float exb = wtw * Fxb, ezb = wtw * Fzb;
       rhob += twb * wtw * iw;
@@ -386,6 +448,7 @@ __device__ __forceinline__ void node_adjoint(const AdjointArgs& A, AdjLds& L, in
       rhob -= (gx * jx + gz * jz) * iw * iw;
     }
   }
+  if constexpr (PROBE) return;
 
   // ---- dL/d(post-boundary populations) = lambda + M^T nu ----
   nu[0] = rhob;
@@ -503,6 +566,28 @@ __global__ __launch_bounds__(BLOCK) void adjoint_kernel(AdjointArgs A) {
   if (threadIdx.x == 0) A.cs_part[e] += ((L.part[0] + L.part[1]) + L.part[2]) + L.part[3];  // one writer per step
 }
 
+// Line-averaged wall model: the wall blocks (y-groups 0 and yg-1 of every
+// (x, z-chunk)) store dL/d(line u_tau) per wall-line chunk; every chunk of
+// every line is written, so the main launch reads no stale sums.
+template <bool F16>
+__global__ __launch_bounds__(BLOCK) void adjoint_line_probe_kernel(AdjointArgs A) {
+  __shared__ AdjLds L;
+  const CollideArgs& a = A.c;
+  const int ng = a.yg > 1 ? 2 : 1;
+  const int b = (int)blockIdx.x;
+  const int k = b % ng, zci = (b / ng) % a.zc, x = b / (ng * a.zc);
+  const int gy = k == 0 ? 0 : a.yg - 1;
+  const int lane = threadIdx.x & (ZT - 1);
+  const int base = min(YROWS * gy, a.ny - YROWS);
+  const int y = base + uni(threadIdx.x >> 6);
+  const int zraw = zci * ZT + lane;
+  const bool active = zraw < a.nz;
+  const int z = active ? zraw : a.nz - 1;
+  float gup[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
+  float csb = 0.f;
+  node_adjoint<F16, true>(A, L, x, y, z, lane, base, zci, row_owned(a, y, gy, base), active, gup, csb);
+}
+
 // grad[n_bins] += the accumulated per-block dL/dC_s (fixed-order tree), and
 // grad[b] += the accumulated inlet-row partial sums of bin b (rows, then
 // z-chunks, in order).  The accumulators are cleared for the next sweep.
@@ -555,14 +640,30 @@ int adjoint_blocks(const lbm_ctx* h) {
 
 // One launch over all block entries of adjoint_blocks(); the inlet plane at
 // t_next, unless given, is computed first.
+// With the line-averaged wall model the step's line u_tau is recomputed from
+// s_n and the inlet plane, and the probe launch runs before the main one.
 hipError_t launch_adjoint(lbm_ctx* h, const AdjointArgs& args, int storage_f16, double t_next, bool fill_inlet,
                           float* u_in, float* fluct) {
   hipError_t e;
   if (fill_inlet && (e = launch_stg_fill(h, t_next, h->stream, fluct, u_in)) != hipSuccess) return e;
+  AdjointArgs A = args;
+  if ((e = launch_wall_line(h, A.c, h->stream)) != hipSuccess) return e;
+  if (A.c.wall_line) {
+    const lbm_config& c = h->cfg;
+    if (!h->d_line_part && (e = hipMalloc(&h->d_line_part, sizeof(double) * 2 * c.nx * h->zc)) != hipSuccess)
+      return e;
+    A.line_part = h->d_line_part;
+    const int nprobe = c.nx * h->zc * (h->yg > 1 ? 2 : 1);
+    if (storage_f16)
+      adjoint_line_probe_kernel<true><<<nprobe, BLOCK, 0, h->stream>>>(A);
+    else
+      adjoint_line_probe_kernel<false><<<nprobe, BLOCK, 0, h->stream>>>(A);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
   if (storage_f16)
-    adjoint_kernel<true><<<adjoint_blocks(h), BLOCK, 0, h->stream>>>(args);
+    adjoint_kernel<true><<<adjoint_blocks(h), BLOCK, 0, h->stream>>>(A);
   else
-    adjoint_kernel<false><<<adjoint_blocks(h), BLOCK, 0, h->stream>>>(args);
+    adjoint_kernel<false><<<adjoint_blocks(h), BLOCK, 0, h->stream>>>(A);
   return hipGetLastError();
 }
 

@@ -251,6 +251,7 @@ lbm_status lbm_destroy(lbm_handle h) {
   if (h->d_stats) (void)hipFree(h->d_stats);
   if (h->d_wall_acc) (void)hipFree(h->d_wall_acc);
   if (h->d_wall_line) (void)hipFree(h->d_wall_line);
+  if (h->d_line_part) (void)hipFree(h->d_line_part);
   if (h->d_plane_of_x) (void)hipFree(h->d_plane_of_x);
   if (h->d_blist_int) (void)hipFree(h->d_blist_int);
   if (h->d_blist_bnd) (void)hipFree(h->d_blist_bnd);
@@ -525,7 +526,6 @@ lbm_status lbm_adjoint_step(lbm_handle h, const lbm_stg* stg, const void* s_n, c
   const bool inflow = h->cfg.xbc == LBM_X_INFLOW;
   if (inflow && (!hist_n || !eta_next || !eta_prev || eta_next == eta_prev)) return LBM_ERR_ARG;
   if (!u_in_next != !fluct_next) return LBM_ERR_ARG;  // the inlet plane is given whole or recomputed
-  if (h->cfg.wall_avg == LBM_WALL_AVG_LINE && h->cfg.wall_model) return LBM_ERR_ARG;  // local u_tau only
   if (stg) {
     lbm_status st = bind_stg(h, stg);
     if (st != LBM_OK) return st;
@@ -561,6 +561,7 @@ lbm_status lbm_adjoint_step(lbm_handle h, const lbm_stg* stg, const void* s_n, c
   A.g_uin = inflow ? (g_uin ? g_uin : h->d_guin) : nullptr;
   A.cs_part = h->d_cs_part;
   A.amp_part = h->d_amp_part;
+  A.line_part = nullptr;  // set by launch_adjoint with the line-averaged wall model
   A.dsmag = (float)(36.0 * std::sqrt(2.0) * h->cfg.cs_smag);  // d(18 sqrt(2) C_s^2)/dC_s
   float* fluct = inflow ? (h->stg.fluct ? h->stg.fluct : h->d_fluct) : nullptr;
   A.fluct = fluct_next ? fluct_next : fluct;

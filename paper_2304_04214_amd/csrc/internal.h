@@ -60,6 +60,7 @@ struct AdjointArgs {
   const float* fluct;     // a v' of the inlet plane [3][ny][nz]
   double* cs_part;        // [blocks] per-block dL/dC_s
   double* amp_part;       // [ny][zc] per inlet-row-chunk sum of g_uin . fluct
+  double* line_part;      // [2][nx][zc] per wall-line chunk dL/d(line u_tau) (line-averaged model)
   float dsmag;            // d(18 sqrt(2) C_s^2)/dC_s
 };
 
@@ -103,6 +104,7 @@ struct lbm_ctx {
   double* d_stats = nullptr;
   double* d_wall_acc = nullptr;  // [2][nx][zc], with the wall model
   float* d_wall_line = nullptr;  // [2][nx] line-averaged u_tau of the current step
+  double* d_line_part = nullptr; // [2][nx][zc] adjoint partial sums of the line model
   int n_planes = 0;
   std::vector<int> plane_of_x;  // host copy of d_plane_of_x
   int stats_on = 0;
@@ -136,6 +138,7 @@ hipError_t launch_export(lbm_ctx* h, float* out);
 hipError_t launch_import(lbm_ctx* h, const float* in);
 hipError_t launch_copy(const void* src, void* dst, int64_t bytes, hipStream_t s);
 void fill_args(lbm_ctx* h, CollideArgs& a, int src, int dst);
+hipError_t launch_wall_line(lbm_ctx* h, CollideArgs& a, hipStream_t stream);
 hipError_t launch_field_export(lbm_ctx* h, const float* bricks, float* soa);
 hipError_t launch_field_import(lbm_ctx* h, const float* soa, float* bricks);
 // adjoint.hip
