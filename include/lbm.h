@@ -218,11 +218,10 @@ lbm_status stg_inlet_fill(lbm_handle h, const lbm_stg* stg, double t);
  * Advance nsteps time steps (Algorithm 1): for each step n -> n+1 the inlet
  * plane is filled for t = n+1 (when xbc = LBM_X_INFLOW), then one fused
  * pull-stream / boundary / wall-model / MRT-Smagorinsky collision runs over
- * all nodes.  With LBM_STORE_F16DEV the interior blocks run in a lean kernel on
- * the handle's stream, concurrently with the inlet plane and a general kernel
- * for boundary blocks on an internal stream of default priority that the
- * handle's stream joins; with LBM_STORE_F32 one general kernel covers all
- * blocks.
+ * all nodes, on the handle's stream.  With LBM_STORE_F16DEV the blocks away
+ * from the inlet, outlet and statistics planes (wall rows included) run in a
+ * lean kernel after a general kernel for the other blocks; with LBM_STORE_F32
+ * one general kernel covers all blocks.
  * stg: bound when non-NULL; required (now or earlier) with LBM_X_INFLOW.
  * Asynchronous on the handle's stream.
  */
@@ -334,7 +333,7 @@ const char* lbm_status_str(lbm_status s);
 
 /* When enabled, every launch of the dominant collide-stream kernel (with
    LBM_STORE_F32 the single kernel over all nodes, with LBM_STORE_F16DEV the
-   interior kernel over nodes away from walls, inlet, outlet and statistics
+   bulk kernel over the nodes away from the inlet, outlet and statistics
    planes) is bracketed by HIP events on the handle's stream; *total_ms and
    *launches report the summed kernel time since the last reset, and
    *nodes_per_launch the nodes one launch updates (reading synchronises).

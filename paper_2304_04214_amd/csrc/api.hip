@@ -93,11 +93,11 @@ void free_tables(lbm_ctx* h) {
   t = lbm::StgTables();
 }
 
-// The timed collide launch (the interior kernel with FP16 storage, the
-// single general kernel with FP32 storage), bracketed by events when enabled.
+// The timed collide launch (the bulk kernel with FP16 storage, the single
+// general kernel with FP32 storage), bracketed by events when enabled.
 hipError_t timed_launch(lbm_ctx* h, int src, int dst, const float* u_in = nullptr) {
   auto launch = [&]() {
-    return h->split ? lbm::launch_interior(h, src, dst, h->stream)
+    return h->split ? lbm::launch_bulk(h, src, dst, h->stream)
                     : lbm::launch_boundary(h, src, dst, h->stream, u_in);
   };
   if (!h->timing) return launch();
@@ -115,27 +115,6 @@ hipError_t timed_launch(lbm_ctx* h, int src, int dst, const float* u_in = nullpt
   r = hipEventRecord(h->ev[2 * h->ev_used + 1], h->stream);
   if (r != hipSuccess) return r;
   ++h->ev_used;
-  return hipSuccess;
-}
-
-void destroy_streams(lbm_ctx* h) {
-  if (h->side) (void)hipStreamDestroy(h->side);
-  if (h->ev_fork) (void)hipEventDestroy(h->ev_fork);
-  for (int k = 0; k < 2; ++k) {
-    if (h->ev_int[k]) (void)hipEventDestroy(h->ev_int[k]);
-    if (h->ev_bnd[k]) (void)hipEventDestroy(h->ev_bnd[k]);
-  }
-  h->side = nullptr;
-}
-
-hipError_t create_streams(lbm_ctx* h) {
-  hipError_t e = hipStreamCreateWithFlags(&h->side, hipStreamNonBlocking);  // default priority
-  if (e != hipSuccess) return e;
-  if ((e = hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming)) != hipSuccess) return e;
-  for (int k = 0; k < 2; ++k) {
-    if ((e = hipEventCreateWithFlags(&h->ev_int[k], hipEventDisableTiming)) != hipSuccess) return e;
-    if ((e = hipEventCreateWithFlags(&h->ev_bnd[k], hipEventDisableTiming)) != hipSuccess) return e;
-  }
   return hipSuccess;
 }
 
@@ -231,15 +210,6 @@ lbm_status lbm_create(const lbm_config* cfg, void* f_a, void* f_b, float* hist_a
     return LBM_ERR_HIP;
   }
   h->plane_of_x = none;
-  if (create_streams(h) != hipSuccess) {
-    destroy_streams(h);
-    (void)hipFree(h->d_err);
-    (void)hipFree(h->d_plane_of_x);
-    (void)hipFree(h->d_blist_int);
-    (void)hipFree(h->d_blist_bnd);
-    delete h;
-    return LBM_ERR_HIP;
-  }
   *out = h;
   return LBM_OK;
 }
@@ -263,7 +233,6 @@ lbm_status lbm_destroy(lbm_handle h) {
   if (h->d_uin_ring) (void)hipFree(h->d_uin_ring);
   if (h->d_fl_ring) (void)hipFree(h->d_fl_ring);
   for (hipEvent_t e : h->ev) (void)hipEventDestroy(e);
-  destroy_streams(h);
   delete h;
   return LBM_OK;
 }
@@ -334,38 +303,19 @@ lbm_status lbm_step(lbm_handle h, const lbm_stg* stg, int32_t nsteps) {
                                       h->stg.fluct ? h->d_fl_ring : nullptr, n + nb == nsteps ? nb - 1 : -1);
   };
   auto ring_plane = [&](int32_t n) { return inflow ? h->d_uin_ring + plane * (size_t)(n % lbm::STG_BATCH) : nullptr; };
-  if (!h->split) {
-    for (int32_t n = 0; n < nsteps; ++n) {
-      if (inflow && n % lbm::STG_BATCH == 0) HIPCHK(fill_batch(n, h->stream));
-      HIPCHK(timed_launch(h, h->cur, 1 - h->cur, ring_plane(n)));
-      h->cur = 1 - h->cur;
-      ++h->time;
-      if (h->stats_on) ++h->n_samples;
-    }
-    return LBM_OK;
-  }
-
-  // Step n: the side stream fills the inlet plane and runs the boundary
-  // blocks while the caller's stream runs the interior blocks.  Both read s_n
-  // and write disjoint nodes of s_{n+1}; step n+1 on either stream waits for
-  // step n on the other (ping-pong events), and the caller's stream joins the
-  // side stream at the end.
-  HIPCHK(hipEventRecord(h->ev_fork, h->stream));
-  HIPCHK(hipStreamWaitEvent(h->side, h->ev_fork, 0));
+  // Everything on the handle's stream.  FP32 storage: one kernel per step.
+  // FP16 storage: the boundary blocks (with the line-averaged wall model the
+  // line kernel first), then the bulk blocks; both read s_n and write
+  // disjoint nodes of s_{n+1}.  (Running the boundary blocks concurrently on
+  // a second stream cost more in cross-stream waits than it hid.)
   for (int32_t n = 0; n < nsteps; ++n) {
-    const int src = h->cur, dst = 1 - h->cur;
-    if (n > 0) HIPCHK(hipStreamWaitEvent(h->side, h->ev_int[(n - 1) & 1], 0));
-    if (inflow && n % lbm::STG_BATCH == 0) HIPCHK(fill_batch(n, h->side));
-    HIPCHK(lbm::launch_boundary(h, src, dst, h->side, ring_plane(n)));
-    HIPCHK(hipEventRecord(h->ev_bnd[n & 1], h->side));
-    if (n > 0) HIPCHK(hipStreamWaitEvent(h->stream, h->ev_bnd[(n - 1) & 1], 0));
-    HIPCHK(timed_launch(h, src, dst));
-    HIPCHK(hipEventRecord(h->ev_int[n & 1], h->stream));
-    h->cur = dst;
+    if (inflow && n % lbm::STG_BATCH == 0) HIPCHK(fill_batch(n, h->stream));
+    if (h->split) HIPCHK(lbm::launch_boundary(h, h->cur, 1 - h->cur, h->stream, ring_plane(n)));
+    HIPCHK(timed_launch(h, h->cur, 1 - h->cur, ring_plane(n)));
+    h->cur = 1 - h->cur;
     ++h->time;
     if (h->stats_on) ++h->n_samples;
   }
-  HIPCHK(hipStreamWaitEvent(h->stream, h->ev_bnd[(nsteps - 1) & 1], 0));
   return LBM_OK;
 }
 

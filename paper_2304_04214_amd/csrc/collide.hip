@@ -244,12 +244,16 @@ __device__ __forceinline__ void node_update(const CollideArgs& a, int x, int y, 
                                             float (*lds_u2)[2][ZT]) {
   x_rules<F16>(a, x, y, z, col, f, active && owned);
 
-  // density and momentum before the force (Eq. (10)-(11))
-  const Pairs pr = make_pairs(f);
-  const float rho = pr.A + pr.Bx + f[9];
-  const float jx = (pr.d[3] + pr.d[7]) - (pr.d[1] + pr.d[5] + pr.d[8]);
-  const float jy = pr.d[4] - (pr.d[0] + pr.d[5] + pr.d[6] + pr.d[7]);
-  const float jz = -(pr.d[0] + pr.d[1] + pr.d[2] + pr.d[3] + pr.d[4]);
+  // density and momentum before the force (Eq. (10)-(11)), summed directly
+  // so that the collision's pair sums are not live across the wall force
+  float rho = 0.f, jx = 0.f, jy = 0.f, jz = 0.f;
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    rho += f[i];
+    if (CX[i]) jx += CX[i] * f[i];
+    if (CY[i]) jy += CY[i] * f[i];
+    if (CZ[i]) jz += CZ[i] * f[i];
+  }
 
   float Fx = 0.f, Fy = 0.f, Fz = 0.f;
   bool force = a.has_g != 0;
@@ -291,6 +295,7 @@ __device__ __forceinline__ void node_update(const CollideArgs& a, int x, int y, 
 
   float ux, uy, uz;
   const Tau0 t0 = tau0_of_x(a, x);
+  const Pairs pr = make_pairs(f);
   if (force)
     collide<true>(a, t0, f, pr, rho, jx, jy, jz, Fx, Fy, Fz, ux, uy, uz);
   else
@@ -332,22 +337,23 @@ __device__ __forceinline__ void node_update(const CollideArgs& a, int x, int y, 
   }
 }
 
-// The collide-stream step runs as two kernels over disjoint block sets (a
-// block = 4 consecutive y rows of one (x, z-chunk)):
-//  * interior blocks, whose 3 x 3 source rows are all inside the lattice and
-//    which carry no statistics plane: a lean kernel with no boundary code, so
-//    it keeps few registers and many waves in flight to hide HBM latency;
-//  * boundary blocks (wall row groups, inlet and outlet planes, sampled
-//    statistics planes): the general kernel with every rule of Algorithm 1.
-// Both read s_n and write disjoint nodes of s_{n+1}.  Each walks a block list
-// (x, z-chunk, y-group) in memory order.
+// With FP16 storage the collide-stream step runs as two kernels over
+// disjoint block sets (a block = 4 consecutive y rows of one (x, z-chunk)):
+//  * bulk blocks (every block away from the inlet, outlet and statistics
+//    planes): interior blocks, whose 3 x 3 source rows all lie inside the
+//    lattice, and the y-groups holding a wall row, in one lean kernel that
+//    keeps few registers and many waves in flight to hide HBM latency;
+//  * boundary blocks (inlet and outlet planes, sampled statistics planes):
+//    the general kernel with every rule of Algorithm 1.
+// With FP32 storage the general kernel takes every block.  All read s_n and
+// write disjoint nodes of s_{n+1}.  Each walks a block list (x, z-chunk,
+// y-group) in memory order.
 
+// A block whose 3 x 3 source rows all lie inside the lattice (see the
+// block lists): plain shifted pulls, no boundary rule.
 template <bool F16, bool FORCE>
-__global__ __launch_bounds__(BLOCK) void collide_interior_kernel(CollideArgs a, const int* __restrict__ blist) {
-  const int e = blist[blockIdx.x];
-  if (e < 0) return;  // padding of the XCD-ordered list
-  int x, zci, gy;
-  block_coords(a, e, x, zci, gy);
+__device__ __forceinline__ void plain_block(const CollideArgs& a, int x, int zci, int gy) {
+
   const int lane = threadIdx.x & (ZT - 1);
   const int base = min(YROWS * gy, a.ny - YROWS);
   const int y = base + uni(threadIdx.x >> 6);
@@ -391,6 +397,99 @@ __global__ __launch_bounds__(BLOCK) void collide_interior_kernel(CollideArgs a, 
         Pop<F16>::stp(p + i * ZT * Pop<F16>::ES, i, col.b0, f[i]);
     }
   }
+}
+
+// A y-group holding a wall row, away from the inlet, outlet and statistics
+// planes: the plain block's data flow plus the wall rules of the pull and
+// the wall model (the wall row's neighbour velocity through LDS).  Density
+// and momentum are summed directly so that the pair sums of the collision
+// are not live across the Newton solve (fewer registers).
+template <bool F16>
+__device__ __forceinline__ void wall_block(const CollideArgs& a, int x, int zci, int gy, float (*lds_u2)[2][ZT]) {
+
+  const int lane = threadIdx.x & (ZT - 1);
+  const int base = min(YROWS * gy, a.ny - YROWS);
+  const int y = base + uni(threadIdx.x >> 6);
+  const bool owned = y >= YROWS * gy;
+  const int zraw = zci * ZT + lane;
+  const bool active = zraw < a.nz;
+  const int z = active ? zraw : a.nz - 1;
+  const Col col = make_col<F16>(a, z);
+  const Geo g = make_geo(a, x, y);
+  typename Pop<F16>::Raw r[Q];
+  issue_pulls<F16>(a, g, col, r);  // every x source exists; the y walls redirect
+  float f[Q];
+#pragma unroll
+  for (int i = 0; i < Q; ++i) f[i] = F16 ? Pop<true>::cvt_dev(r[i]) : Pop<F16>::cvt(i, r[i]);
+  // density and momentum first; the pair sums of the collision are formed
+  // after the wall force, so they are not live across the Newton solve
+  float rhoh = 0.f, jx = 0.f, jy = 0.f, jz = 0.f;
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    rhoh += f[i];
+    if (CX[i]) jx += CX[i] * f[i];
+    if (CY[i]) jy += CY[i] * f[i];
+    if (CZ[i]) jz += CZ[i] * f[i];
+  }
+  const float rho = F16 ? 1.f + rhoh : rhoh;
+  float Fx = rho * a.g[0], Fy = rho * a.g[1], Fz = rho * a.g[2];
+  if (a.wall_model) {
+    const bool bot = base == 0, top = base == a.ny - YROWS;
+    const float ir = 1.f / rho;
+    if (bot && y == 1) {
+      lds_u2[0][0][lane] = jx * ir;
+      lds_u2[0][1][lane] = jz * ir;
+    }
+    if (top && y == a.ny - 2) {
+      lds_u2[1][0][lane] = jx * ir;
+      lds_u2[1][1][lane] = jz * ir;
+    }
+    __syncthreads();
+    const bool wb = bot && y == 0, wt = top && y == a.ny - 1;
+    if (wb || wt) {
+      const int w = wb ? 0 : 1;
+      float fwx, fwz, ut;
+      wall_force(a, rho, jx * ir, jz * ir, lds_u2[w][0][lane], lds_u2[w][1][lane], fwx, fwz, ut, w, x);
+      Fx += fwx;
+      Fz += fwz;
+      if (a.wall_acc) {
+        double v = active ? (double)ut : 0.0;
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, ZT);
+        if (lane == 0) a.wall_acc[((size_t)w * a.nx + x) * a.zc + zci] += v;
+      }
+    }
+  }
+  float ux, uy, uz;
+  const Pairs pr = make_pairs(f);
+  collide<true, F16>(a, tau0_of_x(a, x), f, pr, rho, jx, jy, jz, Fx, Fy, Fz, ux, uy, uz, rhoh);
+  if (!(rho > 0.f && rho < 1e30f)) atomicOr(a.err, ERRBIT_NONFINITE);
+  if (active && owned) {
+    char* p = const_cast<char*>(row_ptr<F16>(a.dst, rowpart(a, x, y)));
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+      if (F16)
+        Pop<true>::stp_dev(p + i * ZT * Pop<F16>::ES, col.b0, f[i]);
+      else
+        Pop<F16>::stp(p + i * ZT * Pop<F16>::ES, i, col.b0, f[i]);
+    }
+  }
+}
+
+// Interior and wall blocks (block-uniform choice): the lean kernel, so it
+// keeps few registers and many waves in flight to hide HBM latency.
+template <bool F16, bool FORCE>
+__global__ __launch_bounds__(BLOCK) void collide_bulk_kernel(CollideArgs a, const int* __restrict__ blist) {
+  __shared__ float lds_u2[2][2][ZT];
+  const int e = blist[blockIdx.x];
+  if (e < 0) return;  // padding of the XCD-ordered list (whole block: no barrier is skipped by part of it)
+  int x, zci, gy;
+  block_coords(a, e, x, zci, gy);
+  const int base = min(YROWS * gy, a.ny - YROWS);
+  if (a.ywall != LBM_Y_PERIODIC && (base == 0 || base == a.ny - YROWS))
+    wall_block<F16>(a, x, zci, gy, lds_u2);
+  else
+    plain_block<F16, FORCE>(a, x, zci, gy);
 }
 
 template <bool F16>
@@ -618,6 +717,17 @@ hipError_t launch_wall_line(lbm_ctx* h, CollideArgs& a, hipStream_t stream) {
   return hipGetLastError();
 }
 
+// The general blocks of one step.
+void launch_edge_kernels(lbm_ctx* h, const CollideArgs& a, hipStream_t stream) {
+  const bool f16 = h->cfg.storage == LBM_STORE_F16DEV;
+  if (h->n_bnd > 0) {
+    if (f16)
+      collide_general_kernel<true><<<h->n_bnd, BLOCK, 0, stream>>>(a, h->d_blist_bnd);
+    else
+      collide_general_kernel<false><<<h->n_bnd, BLOCK, 0, stream>>>(a, h->d_blist_bnd);
+  }
+}
+
 hipError_t launch_boundary(lbm_ctx* h, int src, int dst, hipStream_t stream, const float* u_in) {
   if (h->n_bnd == 0) return hipSuccess;
   CollideArgs a;
@@ -625,15 +735,12 @@ hipError_t launch_boundary(lbm_ctx* h, int src, int dst, hipStream_t stream, con
   if (u_in) a.u_in = u_in;
   hipError_t e = launch_wall_line(h, a, stream);
   if (e != hipSuccess) return e;
-  if (h->cfg.storage == LBM_STORE_F16DEV)
-    collide_general_kernel<true><<<h->n_bnd, BLOCK, 0, stream>>>(a, h->d_blist_bnd);
-  else
-    collide_general_kernel<false><<<h->n_bnd, BLOCK, 0, stream>>>(a, h->d_blist_bnd);
+  launch_edge_kernels(h, a, stream);
   return hipGetLastError();
 }
 
 // One step between caller buffers (statistics off), on one stream: the
-// boundary and interior block lists with FP16 storage, the single list with FP32.
+// boundary and bulk block lists with FP16 storage, the single list with FP32.
 hipError_t launch_step_explicit(lbm_ctx* h, const void* src, void* dst, const float* hist_in, float* hist_out,
                                 const float* u_in, hipStream_t stream) {
   CollideArgs a;
@@ -648,39 +755,38 @@ hipError_t launch_step_explicit(lbm_ctx* h, const void* src, void* dst, const fl
   const bool f16 = h->cfg.storage == LBM_STORE_F16DEV;
   hipError_t e = launch_wall_line(h, a, stream);
   if (e != hipSuccess) return e;
-  if (h->n_bnd > 0) {
-    if (f16)
-      collide_general_kernel<true><<<h->n_bnd, BLOCK, 0, stream>>>(a, h->d_blist_bnd);
-    else
-      collide_general_kernel<false><<<h->n_bnd, BLOCK, 0, stream>>>(a, h->d_blist_bnd);
-  }
+  launch_edge_kernels(h, a, stream);
   if (h->n_int > 0) {
     if (f16 && a.has_g)
-      collide_interior_kernel<true, true><<<h->n_int, BLOCK, 0, stream>>>(a, h->d_blist_int);
+      collide_bulk_kernel<true, true><<<h->n_int, BLOCK, 0, stream>>>(a, h->d_blist_int);
     else if (f16)
-      collide_interior_kernel<true, false><<<h->n_int, BLOCK, 0, stream>>>(a, h->d_blist_int);
+      collide_bulk_kernel<true, false><<<h->n_int, BLOCK, 0, stream>>>(a, h->d_blist_int);
     else if (a.has_g)
-      collide_interior_kernel<false, true><<<h->n_int, BLOCK, 0, stream>>>(a, h->d_blist_int);
+      collide_bulk_kernel<false, true><<<h->n_int, BLOCK, 0, stream>>>(a, h->d_blist_int);
     else
-      collide_interior_kernel<false, false><<<h->n_int, BLOCK, 0, stream>>>(a, h->d_blist_int);
+      collide_bulk_kernel<false, false><<<h->n_int, BLOCK, 0, stream>>>(a, h->d_blist_int);
   }
   return hipGetLastError();
 }
 
-hipError_t launch_interior(lbm_ctx* h, int src, int dst, hipStream_t stream) {
+// The bulk blocks of one step.  With the line-averaged wall model the step's
+// line u_tau must already be in h->d_wall_line on this stream (launch_boundary).
+hipError_t launch_bulk(lbm_ctx* h, int src, int dst, hipStream_t stream) {
   if (h->n_int == 0) return hipSuccess;
   CollideArgs a;
   fill_args(h, a, src, dst);
+  if (h->cfg.wall_avg == LBM_WALL_AVG_LINE && h->cfg.wall_model && h->cfg.ywall != LBM_Y_PERIODIC)
+    a.wall_line = h->d_wall_line;
   if (h->cfg.storage == LBM_STORE_F16DEV) {
     if (a.has_g)
-      collide_interior_kernel<true, true><<<h->n_int, BLOCK, 0, stream>>>(a, h->d_blist_int);
+      collide_bulk_kernel<true, true><<<h->n_int, BLOCK, 0, stream>>>(a, h->d_blist_int);
     else
-      collide_interior_kernel<true, false><<<h->n_int, BLOCK, 0, stream>>>(a, h->d_blist_int);
+      collide_bulk_kernel<true, false><<<h->n_int, BLOCK, 0, stream>>>(a, h->d_blist_int);
   } else {
     if (a.has_g)
-      collide_interior_kernel<false, true><<<h->n_int, BLOCK, 0, stream>>>(a, h->d_blist_int);
+      collide_bulk_kernel<false, true><<<h->n_int, BLOCK, 0, stream>>>(a, h->d_blist_int);
     else
-      collide_interior_kernel<false, false><<<h->n_int, BLOCK, 0, stream>>>(a, h->d_blist_int);
+      collide_bulk_kernel<false, false><<<h->n_int, BLOCK, 0, stream>>>(a, h->d_blist_int);
   }
   return hipGetLastError();
 }
@@ -690,13 +796,19 @@ hipError_t launch_interior(lbm_ctx* h, int src, int dst, hipStream_t stream) {
 // The only cache lines two blocks share are the edge lines of the +-1 z
 // shifts between z-neighbouring bricks of one (x, y-group) column, so every
 // column is given to one XCD and its z-chunks run back to back there.
-// Columns go to XCDs in turn; queues are padded with -1 (empty block).
-std::vector<int> xcd_order(const std::vector<int>& entries, int zc) {
+// Columns go to XCDs in turn, each class of column (heavy[c]: wall groups,
+// whose blocks take longer) with its own turn, so that every XCD gets its
+// share of both; queues are padded with -1 (empty block).
+std::vector<int> xcd_order(const std::vector<int>& entries, int zc, const std::vector<char>* heavy = nullptr) {
   constexpr int NX = 8;
   std::vector<std::vector<int>> q(NX);
   const size_t ncol = entries.size() / zc;
-  for (size_t c = 0; c < ncol; ++c)
-    for (int k = 0; k < zc; ++k) q[c % NX].push_back(entries[c * zc + k]);
+  size_t turn[2] = {0, 0};
+  for (size_t c = 0; c < ncol; ++c) {
+    const int k = heavy ? ((*heavy)[c] ? 1 : 0) : 0;
+    const size_t xcd = turn[k]++ % NX;
+    for (int j = 0; j < zc; ++j) q[xcd].push_back(entries[c * zc + j]);
+  }
   size_t len = 0;
   for (auto& v : q) len = std::max(len, v.size());
   std::vector<int> out(len * NX, -1);
@@ -705,11 +817,12 @@ std::vector<int> xcd_order(const std::vector<int>& entries, int zc) {
   return out;
 }
 
-// Split the blocks (x, z-chunk, y-group) into interior and boundary lists,
-// each ordered by xcd_order (see collide_interior_kernel / collide_general_kernel).
+// Split the blocks (x, z-chunk, y-group) into bulk and boundary lists,
+// each ordered by xcd_order (see collide_bulk_kernel / collide_general_kernel).
 hipError_t build_block_lists(lbm_ctx* h, const std::vector<int>& plane_of_x) {
   const lbm_config& c = h->cfg;
   std::vector<int> in, bd;
+  std::vector<char> in_heavy;  // per bulk column: a wall group
   in.reserve((size_t)c.nx * h->zc * h->yg);
   int64_t int_nodes = 0;
   const bool split = h->split;
@@ -718,12 +831,12 @@ hipError_t build_block_lists(lbm_ctx* h, const std::vector<int>& plane_of_x) {
     const bool xb = (c.xbc == LBM_X_INFLOW && (x == 0 || x == c.nx - 1)) || (h->stats_on && plane_of_x[x] >= 0);
     for (int gy = 0; gy < h->yg; ++gy) {
       const int base = std::min(YROWS * gy, c.ny - YROWS);
-      const bool yb = c.ywall != LBM_Y_PERIODIC && (base == 0 || base + YROWS - 1 == c.ny - 1);
-      const bool interior_block = split && !xb && !yb;
+      const bool bulk_block = split && !xb;  // wall groups take the bulk kernel's wall branch
+      if (bulk_block) in_heavy.push_back(c.ywall != LBM_Y_PERIODIC && (base == 0 || base == c.ny - YROWS));
       for (int zc = 0; zc < h->zc; ++zc) {
         const int e = (x * h->zc + zc) * h->yg + gy;
-        (interior_block ? in : bd).push_back(e);
-        if (interior_block) {
+        (bulk_block ? in : bd).push_back(e);
+        if (bulk_block) {
           const int owned_rows = YROWS - (YROWS * gy - base);
           const int lanes = std::min(ZT, c.nz - ZT * zc);
           int_nodes += (int64_t)owned_rows * lanes;
@@ -731,7 +844,7 @@ hipError_t build_block_lists(lbm_ctx* h, const std::vector<int>& plane_of_x) {
       }
     }
   }
-  in = xcd_order(in, h->zc);
+  in = xcd_order(in, h->zc, &in_heavy);
   bd = xcd_order(bd, h->zc);
   hipError_t err;
   for (int k = 0; k < 2; ++k) {

@@ -82,8 +82,6 @@ struct StgTables {
 struct lbm_ctx {
   lbm_config cfg{};
   hipStream_t stream = nullptr;  // caller's stream: every call's work is ordered on it
-  hipStream_t side = nullptr;    // inlet plane + boundary blocks, concurrent with the interior kernel
-  hipEvent_t ev_fork = nullptr, ev_int[2] = {nullptr, nullptr}, ev_bnd[2] = {nullptr, nullptr};
   int device = 0;
   void* f[2] = {nullptr, nullptr};
   float* hist[2] = {nullptr, nullptr};
@@ -93,13 +91,13 @@ struct lbm_ctx {
   int zc = 0, yg = 0, nblocks = 0;
   int* d_err = nullptr;
   int* d_plane_of_x = nullptr;
-  int* d_blist_int = nullptr;  // interior / boundary collide block lists
+  int* d_blist_int = nullptr;  // bulk / boundary collide block lists
   int* d_blist_bnd = nullptr;
   int n_int = 0, n_bnd = 0, cap_int = 0, cap_bnd = 0;
-  int64_t int_nodes = 0;  // nodes updated by one interior launch
-  // FP16 storage: interior blocks in a lean kernel, boundary blocks (and the
-  // inlet plane) concurrently on the side stream.  FP32 storage is HBM-bound
-  // with the general kernel alone: one launch over all blocks.
+  int64_t int_nodes = 0;  // nodes updated by one bulk launch
+  // FP16 storage: boundary blocks in the general kernel, then the bulk blocks
+  // in a lean kernel.  FP32 storage is HBM-bound with the general kernel
+  // alone: one launch over all blocks.
   bool split = false;
   double* d_stats = nullptr;
   double* d_wall_acc = nullptr;  // [2][nx][zc], with the wall model
@@ -130,7 +128,7 @@ namespace lbm {
 // collide.hip
 // u_in, when given, replaces the bound inlet plane.
 hipError_t launch_boundary(lbm_ctx* h, int src, int dst, hipStream_t stream, const float* u_in = nullptr);
-hipError_t launch_interior(lbm_ctx* h, int src, int dst, hipStream_t stream);
+hipError_t launch_bulk(lbm_ctx* h, int src, int dst, hipStream_t stream);
 hipError_t build_block_lists(lbm_ctx* h, const std::vector<int>& plane_of_x);
 hipError_t launch_stream_only(lbm_ctx* h, int src, int dst);
 hipError_t launch_init(lbm_ctx* h, const float* rho, const float* u, const float* pert, float eps);
