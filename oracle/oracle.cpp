@@ -47,6 +47,9 @@
  *      c_x < 0 at x = nx-1, f(x-1) the post-streaming value of the same step.
  *  R14 inlet and wall rules both apply at inlet/wall corner cells
  *      (Algorithm 1 has two independent branches).
+ *  R24 the Smagorinsky tau_eff (Algorithm 1 step 8, listed inside the inlet
+ *      branch) applies at every cell: Sec. II.B gives it as the closure of
+ *      the whole LES-LBM system.
  *  R20 "pressure-free" outlet, alternative reading: zero gradient,
  *      f_i = f_i(x-1) for c_x < 0 at x = nx-1 (the limit U_c -> infinity of R13).
  *  R21 Musker's law of the wall (Sec. II.C names it as the alternative to the
