@@ -7,7 +7,8 @@
  *  - Every call returns lbm_status (0 = LBM_OK).  Nothing throws or aborts
  *    across the ABI.  Argument and shape errors are returned synchronously;
  *    errors detected on the device (non-finite or non-positive density, inlet
- *    Mach limit) are latched in a device word and returned by lbm_sync() or
+ *    Mach limit, invalid per-row spectrum inputs of a bound lbm_stg) are
+ *    latched in a device word and returned by lbm_sync() or
  *    lbm_stats(LBM_STATS_READ).
  *  - Pointers named "device" are HIP device pointers.  Population and
  *    outlet-history buffers are CALLER-OWNED: the library never frees them,
