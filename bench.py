@@ -27,7 +27,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "MLUPS & HBM GB/s (FP32 vs FP16-store) + adjoint-step MLUPS at stated error"
 HBM_PEAK_GBS = 8000.0
-BYTES_PER_NODE = {"f32": 152, "f16dev": 76}  # 19 populations read + 19 written
+BYTES_PER_NODE = {"f32": 152, "f16dev": 76, "f16ref": 76}  # 19 populations read + 19 written
 
 
 def log(*a):
@@ -38,16 +38,20 @@ SPONGE_NU = 0.1  # viscosity at the outlet plane of the 1-delta sponge (the pape
 
 
 def make_channel(name, storage, device, sponge=False):
+    """storage: "f32", "f16dev" (half deviations from the weights) or "f16ref" (half
+    deviations from the equilibrium at the mean inflow profile)."""
     import torch
     from paper_2304_04214_amd import synthetic as S
     from paper_2304_04214_amd.channel import Channel
     w = S.WORKLOADS[name]
     nx, ny, nz = w["nx"], w["ny"], w["nz"]
     delta = ny / 2
-    ch = Channel(nx, ny, nz, tau0=w["tau0"], storage=storage, ywall="slip", xbc="inflow", wall_model=True,
-                 cs_smag=S.CS_SMAG, u_conv=S.U_C, device=device, sponge_cells=int(delta) if sponge else 0,
-                 sponge_nu=SPONGE_NU if sponge else 0.0)
+    ch = Channel(nx, ny, nz, tau0=w["tau0"], storage="f16dev" if storage == "f16ref" else storage, ywall="slip",
+                 xbc="inflow", wall_model=True, cs_smag=S.CS_SMAG, u_conv=S.U_C, device=device,
+                 sponge_cells=int(delta) if sponge else 0, sponge_nu=SPONGE_NU if sponge else 0.0)
     U = ch.inflow_reichardt(w["u_tau"])
+    if storage == "f16ref":
+        ch.set_reference(U)
     k = int(name[1])
     mt = S.mode_table(w["n_modes"], delta, seed_offset=k)
     ab, boy = S.amp_bins(ny)
@@ -262,14 +266,16 @@ def main():
         return
     log("bench: c2 f32")
     main_r = time_channel("c2", "f32", args.steps, args.warmup, device)
-    log("bench: c2 f16dev")
+    log("bench: c2 f16dev / f16ref")
     r16 = time_channel("c2", "f16dev", args.steps, args.warmup, device)
+    r16r = time_channel("c2", "f16ref", args.steps, args.warmup, device)
     log("bench: c2 f32 with the outlet sponge")
     rsp = time_channel("c2", "f32", args.steps, args.warmup, device, sponge=True)
     log("bench: c3 f32 / f16dev")
     c3_steps = max(10, args.steps // 5)
     r3 = time_channel("c3", "f32", c3_steps, max(5, args.warmup // 5), device)
     r3h = time_channel("c3", "f16dev", c3_steps, max(5, args.warmup // 5), device)
+    r3r = time_channel("c3", "f16ref", c3_steps, max(5, args.warmup // 5), device)
     log("bench: c5 f32 1536x256x384")
     r5 = time_channel("c5", "f32", max(10, args.steps // 10), max(3, args.warmup // 10), device)
     log("bench: adjoint 256x64x64")
@@ -308,6 +314,10 @@ def main():
         "fp16dev": {"mlups": round(r16["mlups"], 1), "ms_per_step": round(r16["ms_per_step"], 5),
                     "kernel_gbs": round(r16["kernel_gbs"], 1), "vs_fp32": round(r16["mlups"] / main_r["mlups"], 3),
                     "status": r16["status"]},
+        "fp16ref": {"storage": "half deviations from the equilibrium at the mean inflow profile",
+                    "mlups": round(r16r["mlups"], 1), "ms_per_step": round(r16r["ms_per_step"], 5),
+                    "kernel_gbs": round(r16r["kernel_gbs"], 1), "vs_fp32": round(r16r["mlups"] / main_r["mlups"], 3),
+                    "status": r16r["status"]},
         "with_outlet_sponge": {"mlups": round(rsp["mlups"], 1), "vs_no_sponge": round(rsp["mlups"] / main_r["mlups"], 3),
                                "sponge": "last 32 planes (1 delta), nu 1.4e-4 -> %g" % SPONGE_NU,
                                "status": rsp["status"]},
@@ -315,7 +325,10 @@ def main():
                                 "f16dev_mlups": round(r3h["mlups"], 1),
                                 "f16dev_kernel_gbs": round(r3h["kernel_gbs"], 1),
                                 "f16dev_vs_f32": round(r3h["mlups"] / r3["mlups"], 3),
-                                "status": [r3["status"], r3h["status"]]},
+                                "f16ref_mlups": round(r3r["mlups"], 1),
+                                "f16ref_kernel_gbs": round(r3r["kernel_gbs"], 1),
+                                "f16ref_vs_f32": round(r3r["mlups"] / r3["mlups"], 3),
+                                "status": [r3["status"], r3h["status"], r3r["status"]]},
         "re5200_1536x256x384_f32": {"mlups": round(r5["mlups"], 1), "kernel_gbs": round(r5["kernel_gbs"], 1),
                                     "frac": round(r5["kernel_gbs"] / HBM_PEAK_GBS, 4),
                                     "ms_per_step": round(r5["ms_per_step"], 5), "status": r5["status"]},

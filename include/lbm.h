@@ -242,6 +242,19 @@ lbm_status lbm_export_f32(lbm_handle h, float* out);
 lbm_status lbm_import_f32(lbm_handle h, const float* in);
 
 /*
+ * LBM_STORE_F16DEV only: store the populations as half deviations from a
+ * per-row reference equilibrium instead of the weights,
+ *   h_i = f_i - w_i - r_i(y),  r_i(y) = f_eq_i(1, u_ref(y)) - w_i
+ * (second-order equilibrium, Eq. (27) with rho = 1), u_ref: device double
+ * [3][ny] reference velocity profile (e.g. the mean inflow), or NULL for
+ * r = 0 (deviations from the weights, the default).  With u_ref near the
+ * mean flow the stored deviations, and so their rounding, shrink by about
+ * |u'| / |U|.  The arithmetic is unchanged (FP32); the current state is
+ * re-encoded in place (one more rounding).  Synchronises the handle's stream.
+ */
+lbm_status lbm_set_reference(lbm_handle h, const double* u_ref);
+
+/*
  * Plane statistics (Sec. IV.A: statistics over a time window).  For each x
  * in x_planes (host array), per row y, the sums over z and over steps of
  * u, v, w, uu, vv, ww, uv, uw, vw of the force-corrected velocity

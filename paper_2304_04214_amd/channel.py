@@ -198,6 +198,20 @@ class Channel:
         A.check(A.lib().lbm_import_f32(self._h, _ptr(f)), "lbm_import_f32")
         self._keep_import = f
 
+    def set_reference(self, u_ref):
+        """FP16 storage: store deviations from the second-order equilibrium at the per-row
+        reference velocity u_ref ([3, ny] or the streamwise [ny]; None: the weights).  The
+        current state is re-encoded."""
+        if u_ref is not None:
+            u = _dev(u_ref, torch.float64, self.device)
+            if u.dim() == 1:
+                u = torch.stack([u, torch.zeros_like(u), torch.zeros_like(u)])
+            u = u.reshape(3, self.ny).contiguous()
+        else:
+            u = None
+        A.check(A.lib().lbm_set_reference(self._h, _ptr(u)), "lbm_set_reference")
+        self._reference = u
+
     def point_state(self, f_a, f_b, hist_a, hist_b, time):
         """Point the handle at caller buffers (no copy): the state is in f_a / hist_a at `time`,
         the next step writes f_b / hist_b."""

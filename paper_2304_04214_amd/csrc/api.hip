@@ -222,6 +222,7 @@ lbm_status lbm_destroy(lbm_handle h) {
   if (h->d_wall_acc) (void)hipFree(h->d_wall_acc);
   if (h->d_wall_line) (void)hipFree(h->d_wall_line);
   if (h->d_line_part) (void)hipFree(h->d_line_part);
+  if (h->d_dref) (void)hipFree(h->d_dref);
   if (h->d_plane_of_x) (void)hipFree(h->d_plane_of_x);
   if (h->d_blist_int) (void)hipFree(h->d_blist_int);
   if (h->d_blist_bnd) (void)hipFree(h->d_blist_bnd);
@@ -336,6 +337,12 @@ lbm_status lbm_export_f32(lbm_handle h, float* out) {
 lbm_status lbm_import_f32(lbm_handle h, const float* in) {
   if (!h || !in) return LBM_ERR_ARG;
   HIPCHK(lbm::launch_import(h, in));
+  return LBM_OK;
+}
+
+lbm_status lbm_set_reference(lbm_handle h, const double* u_ref) {
+  if (!h || h->cfg.storage != LBM_STORE_F16DEV) return LBM_ERR_ARG;
+  HIPCHK(lbm::launch_set_reference(h, u_ref));
   return LBM_OK;
 }
 

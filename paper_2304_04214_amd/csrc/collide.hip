@@ -306,7 +306,7 @@ __device__ __forceinline__ void node_update(const CollideArgs& a, int x, int y, 
   if (active && owned) {
     char* p = const_cast<char*>(row_ptr<F16>(a.dst, rowpart(a, x, y)));
 #pragma unroll
-    for (int i = 0; i < Q; ++i) Pop<F16>::stp(p + i * ZT * Pop<F16>::ES, i, col.b0, f[i]);
+    for (int i = 0; i < Q; ++i) Pop<F16>::stp(p + i * ZT * Pop<F16>::ES, i, col.b0, f[i], ref_off(a, i, y));
   }
 
   if (a.stats_on) {
@@ -351,9 +351,11 @@ __device__ __forceinline__ void node_update(const CollideArgs& a, int x, int y, 
 
 // A block whose 3 x 3 source rows all lie inside the lattice (see the
 // block lists): plain shifted pulls, no boundary rule.
-template <bool F16, bool FORCE>
-__device__ __forceinline__ void plain_block(const CollideArgs& a, int x, int zci, int gy) {
-
+// dref / dpull: the reference offsets (REF), passed as restrict kernel
+// arguments so that their loads need not be ordered after the stores.
+template <bool F16, bool FORCE, bool REF>
+__device__ __forceinline__ void plain_block(const CollideArgs& a, int x, int zci, int gy,
+                                            const float* __restrict__ dref, const float* __restrict__ dpull) {
   const int lane = threadIdx.x & (ZT - 1);
   const int base = min(YROWS * gy, a.ny - YROWS);
   const int y = base + uni(threadIdx.x >> 6);
@@ -373,7 +375,14 @@ __device__ __forceinline__ void plain_block(const CollideArgs& a, int x, int zci
   // load or subtracted on store); FP32 storage on the populations.
   float f[Q];
 #pragma unroll
-  for (int i = 0; i < Q; ++i) f[i] = F16 ? Pop<true>::cvt_dev(r[i]) : Pop<F16>::cvt(i, r[i]);
+  for (int i = 0; i < Q; ++i) {
+    if (!F16)
+      f[i] = Pop<F16>::cvt(i, r[i], 0.f);
+    else if (REF)
+      f[i] = Pop<true>::cvt_dev(r[i], dpull[y * Q + i]);  // wave-uniform row: scalar loads
+    else
+      f[i] = Pop<true>::cvt_dev(r[i]);
+  }
   const Pairs pr = make_pairs(f);
   const float rhoh = pr.A + pr.Bx + f[9];  // sum of h (F16) or rho (F32)
   const float rho = F16 ? 1.f + rhoh : rhoh;
@@ -391,10 +400,12 @@ __device__ __forceinline__ void plain_block(const CollideArgs& a, int x, int zci
     char* p = const_cast<char*>(row_ptr<F16>(a.dst, rowpart(a, x, y)));
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
-      if (F16)
+      if (F16 && REF)
+        Pop<true>::stp_dev(p + i * ZT * Pop<F16>::ES, col.b0, f[i], dref[y * Q + i]);
+      else if (F16)
         Pop<true>::stp_dev(p + i * ZT * Pop<F16>::ES, col.b0, f[i]);
       else
-        Pop<F16>::stp(p + i * ZT * Pop<F16>::ES, i, col.b0, f[i]);
+        Pop<F16>::stp(p + i * ZT * Pop<F16>::ES, i, col.b0, f[i], 0.f);
     }
   }
 }
@@ -404,8 +415,9 @@ __device__ __forceinline__ void plain_block(const CollideArgs& a, int x, int zci
 // the wall model (the wall row's neighbour velocity through LDS).  Density
 // and momentum are summed directly so that the pair sums of the collision
 // are not live across the Newton solve (fewer registers).
-template <bool F16>
-__device__ __forceinline__ void wall_block(const CollideArgs& a, int x, int zci, int gy, float (*lds_u2)[2][ZT]) {
+template <bool F16, bool REF>
+__device__ __forceinline__ void wall_block(const CollideArgs& a, int x, int zci, int gy, float (*lds_u2)[2][ZT],
+                                           const float* __restrict__ dref) {
 
   const int lane = threadIdx.x & (ZT - 1);
   const int base = min(YROWS * gy, a.ny - YROWS);
@@ -420,7 +432,14 @@ __device__ __forceinline__ void wall_block(const CollideArgs& a, int x, int zci,
   issue_pulls<F16>(a, g, col, r);  // every x source exists; the y walls redirect
   float f[Q];
 #pragma unroll
-  for (int i = 0; i < Q; ++i) f[i] = F16 ? Pop<true>::cvt_dev(r[i]) : Pop<F16>::cvt(i, r[i]);
+  for (int i = 0; i < Q; ++i) {
+    if (!F16)
+      f[i] = Pop<F16>::cvt(i, r[i], 0.f);
+    else if (REF)
+      f[i] = Pop<true>::cvt_dev(r[i], pull_ref(a, g, i));
+    else
+      f[i] = Pop<true>::cvt_dev(r[i]);
+  }
   // density and momentum first; the pair sums of the collision are formed
   // after the wall force, so they are not live across the Newton solve
   float rhoh = 0.f, jx = 0.f, jy = 0.f, jz = 0.f;
@@ -468,18 +487,22 @@ __device__ __forceinline__ void wall_block(const CollideArgs& a, int x, int zci,
     char* p = const_cast<char*>(row_ptr<F16>(a.dst, rowpart(a, x, y)));
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
-      if (F16)
+      if (F16 && REF)
+        Pop<true>::stp_dev(p + i * ZT * Pop<F16>::ES, col.b0, f[i], dref[y * Q + i]);
+      else if (F16)
         Pop<true>::stp_dev(p + i * ZT * Pop<F16>::ES, col.b0, f[i]);
       else
-        Pop<F16>::stp(p + i * ZT * Pop<F16>::ES, i, col.b0, f[i]);
+        Pop<F16>::stp(p + i * ZT * Pop<F16>::ES, i, col.b0, f[i], 0.f);
     }
   }
 }
 
 // Interior and wall blocks (block-uniform choice): the lean kernel, so it
 // keeps few registers and many waves in flight to hide HBM latency.
-template <bool F16, bool FORCE>
-__global__ __launch_bounds__(BLOCK) void collide_bulk_kernel(CollideArgs a, const int* __restrict__ blist) {
+template <bool F16, bool FORCE, bool REF>
+__global__ __launch_bounds__(BLOCK) void collide_bulk_kernel(CollideArgs a, const int* __restrict__ blist,
+                                                             const float* __restrict__ dref,
+                                                             const float* __restrict__ dpull) {
   __shared__ float lds_u2[2][2][ZT];
   const int e = blist[blockIdx.x];
   if (e < 0) return;  // padding of the XCD-ordered list (whole block: no barrier is skipped by part of it)
@@ -487,9 +510,9 @@ __global__ __launch_bounds__(BLOCK) void collide_bulk_kernel(CollideArgs a, cons
   block_coords(a, e, x, zci, gy);
   const int base = min(YROWS * gy, a.ny - YROWS);
   if (a.ywall != LBM_Y_PERIODIC && (base == 0 || base == a.ny - YROWS))
-    wall_block<F16>(a, x, zci, gy, lds_u2);
+    wall_block<F16, REF>(a, x, zci, gy, lds_u2, dref);
   else
-    plain_block<F16, FORCE>(a, x, zci, gy);
+    plain_block<F16, FORCE, REF>(a, x, zci, gy, dref, dpull);
 }
 
 template <bool F16>
@@ -583,7 +606,7 @@ __global__ __launch_bounds__(BLOCK) void stream_only_kernel(CollideArgs a) {
   const Geo g = make_geo(a, nd.x, nd.y);
   const uint32_t row = rowpart(a, nd.x, nd.y);
 #pragma unroll
-  for (int i = 0; i < Q; ++i) Pop<false>::st_plain(a.dst, i, row + (uint32_t)i * ZT + col.c0, pull_dir<false>(a, g, i, col, -1.f));
+  for (int i = 0; i < Q; ++i) Pop<false>::st_plain(a.dst, i, row + (uint32_t)i * ZT + col.c0, pull_dir<false>(a, g, i, col, -1.f), 0.f);
 }
 
 // f_i = f_eq_i(rho, u) + eps w_i pert_i from SoA node fields [.][N], N = (x ny + y) nz + z.
@@ -603,7 +626,7 @@ __global__ __launch_bounds__(BLOCK) void init_kernel(CollideArgs a, float* hist,
     const float cu = CX[i] * ux + CY[i] * uy + CZ[i] * uz;
     float v = (float)WD[i] * r * (1.f + 3.f * cu + 4.5f * cu * cu - uu15);
     if (pert) v += eps * (float)WD[i] * pert[(size_t)i * N + n];
-    Pop<F16>::st_plain(a.dst, i, e0 + (uint32_t)i * ZT, v);
+    Pop<F16>::st_plain(a.dst, i, e0 + (uint32_t)i * ZT, v, ref_off(a, i, nd.y));
     if (hist && nd.x == a.nx - 1) {
 #pragma unroll
       for (int k = 0; k < 5; ++k)
@@ -621,7 +644,7 @@ __global__ __launch_bounds__(BLOCK) void export_kernel(CollideArgs a, float* out
   const size_t n = ((size_t)nd.x * a.ny + nd.y) * a.nz + nd.z;
   const uint32_t e0 = rowpart(a, nd.x, nd.y) + colpart(a, nd.z);
 #pragma unroll
-  for (int i = 0; i < Q; ++i) out[(size_t)i * N + n] = Pop<F16>::ld_plain(a.src, i, e0 + (uint32_t)i * ZT);
+  for (int i = 0; i < Q; ++i) out[(size_t)i * N + n] = Pop<F16>::ld_plain(a.src, i, e0 + (uint32_t)i * ZT, ref_off(a, i, nd.y));
 }
 
 // Float SoA [19][N] -> state (bricks), rounded to the storage type.
@@ -633,7 +656,43 @@ __global__ __launch_bounds__(BLOCK) void import_kernel(CollideArgs a, const floa
   const size_t n = ((size_t)nd.x * a.ny + nd.y) * a.nz + nd.z;
   const uint32_t e0 = rowpart(a, nd.x, nd.y) + colpart(a, nd.z);
 #pragma unroll
-  for (int i = 0; i < Q; ++i) Pop<F16>::st_plain(a.dst, i, e0 + (uint32_t)i * ZT, in[(size_t)i * N + n]);
+  for (int i = 0; i < Q; ++i)
+    Pop<F16>::st_plain(a.dst, i, e0 + (uint32_t)i * ZT, in[(size_t)i * N + n], ref_off(a, i, nd.y));
+}
+
+// FP16 storage reference offsets r_i(y) = f_eq_i(1, u_ref(y)) - w_i (second-order
+// equilibrium, FP64, stored as float); u_ref == nullptr gives r = 0.
+__device__ double dref_value(const double* u_ref, int ny, int y, int i) {
+#pragma clang fp contract(off)  // plain multiplies and adds: reproducible off the device
+  const double ux = u_ref[y], uy = u_ref[ny + y], uz = u_ref[2 * ny + y];
+  const double cu = CX[i] * ux + CY[i] * uy + CZ[i] * uz;
+  return WD[i] * (3.0 * cu + 4.5 * cu * cu - 1.5 * (ux * ux + uy * uy + uz * uz));
+}
+
+// dref[y][i] = r_i(y); dpull[y][i] = r_i of the row a plain pull of direction i
+// reads into row y (y - c_y, periodic in y like the plain pull rows).
+__global__ void dref_kernel(const double* u_ref, int ny, float* dref, float* dpull) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= ny * Q) return;
+  const int y = k / Q, i = k % Q;
+  const int ys = (y - CY[i] + ny) % ny;
+  dref[k] = (float)dref_value(u_ref, ny, y, i);
+  dpull[k] = (float)dref_value(u_ref, ny, ys, i);
+}
+
+// The current FP16 state re-encoded in place from offsets dold to dnew (either
+// may be null: 0).
+__global__ __launch_bounds__(BLOCK) void recode_kernel(CollideArgs a, _Float16* state, const float* dold,
+                                                       const float* dnew) {
+  const Node nd = decode(a);
+  if (!nd.active || !nd.owned) return;
+  const uint32_t e0 = rowpart(a, nd.x, nd.y) + colpart(a, nd.z);
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    const float ro = dold ? dold[nd.y * Q + i] : 0.f, rn = dnew ? dnew[nd.y * Q + i] : 0.f;
+    _Float16& h = state[e0 + (uint32_t)i * ZT];
+    h = (_Float16)(((float)h + ro) - rn);
+  }
 }
 
 // One 16-byte vector per thread, streamed (the bandwidth reference of the benchmark).
@@ -656,6 +715,8 @@ void fill_args(lbm_ctx* h, CollideArgs& a, int src, int dst) {
   a.stats = h->d_stats;
   a.wall_acc = h->stats_on ? h->d_wall_acc : nullptr;
   a.wall_line = nullptr;
+  a.dref = h->d_dref;
+  a.dpull = h->d_dpull;
   a.plane_of_x = h->d_plane_of_x;
   a.err = h->d_err;
   a.nx = c.nx;
@@ -717,6 +778,29 @@ hipError_t launch_wall_line(lbm_ctx* h, CollideArgs& a, hipStream_t stream) {
   return hipGetLastError();
 }
 
+// The bulk kernel variant for the storage, the body force and the FP16
+// reference offsets.
+void launch_bulk_kernel(lbm_ctx* h, const CollideArgs& a, bool f16, hipStream_t stream) {
+  const int n = h->n_int;
+  const int* bl = h->d_blist_int;
+  if (!f16) {
+    if (a.has_g)
+      collide_bulk_kernel<false, true, false><<<n, BLOCK, 0, stream>>>(a, bl, a.dref, a.dpull);
+    else
+      collide_bulk_kernel<false, false, false><<<n, BLOCK, 0, stream>>>(a, bl, a.dref, a.dpull);
+  } else if (a.dref) {
+    if (a.has_g)
+      collide_bulk_kernel<true, true, true><<<n, BLOCK, 0, stream>>>(a, bl, a.dref, a.dpull);
+    else
+      collide_bulk_kernel<true, false, true><<<n, BLOCK, 0, stream>>>(a, bl, a.dref, a.dpull);
+  } else {
+    if (a.has_g)
+      collide_bulk_kernel<true, true, false><<<n, BLOCK, 0, stream>>>(a, bl, a.dref, a.dpull);
+    else
+      collide_bulk_kernel<true, false, false><<<n, BLOCK, 0, stream>>>(a, bl, a.dref, a.dpull);
+  }
+}
+
 // The general blocks of one step.
 void launch_edge_kernels(lbm_ctx* h, const CollideArgs& a, hipStream_t stream) {
   const bool f16 = h->cfg.storage == LBM_STORE_F16DEV;
@@ -756,16 +840,7 @@ hipError_t launch_step_explicit(lbm_ctx* h, const void* src, void* dst, const fl
   hipError_t e = launch_wall_line(h, a, stream);
   if (e != hipSuccess) return e;
   launch_edge_kernels(h, a, stream);
-  if (h->n_int > 0) {
-    if (f16 && a.has_g)
-      collide_bulk_kernel<true, true><<<h->n_int, BLOCK, 0, stream>>>(a, h->d_blist_int);
-    else if (f16)
-      collide_bulk_kernel<true, false><<<h->n_int, BLOCK, 0, stream>>>(a, h->d_blist_int);
-    else if (a.has_g)
-      collide_bulk_kernel<false, true><<<h->n_int, BLOCK, 0, stream>>>(a, h->d_blist_int);
-    else
-      collide_bulk_kernel<false, false><<<h->n_int, BLOCK, 0, stream>>>(a, h->d_blist_int);
-  }
+  if (h->n_int > 0) launch_bulk_kernel(h, a, f16, stream);
   return hipGetLastError();
 }
 
@@ -777,17 +852,7 @@ hipError_t launch_bulk(lbm_ctx* h, int src, int dst, hipStream_t stream) {
   fill_args(h, a, src, dst);
   if (h->cfg.wall_avg == LBM_WALL_AVG_LINE && h->cfg.wall_model && h->cfg.ywall != LBM_Y_PERIODIC)
     a.wall_line = h->d_wall_line;
-  if (h->cfg.storage == LBM_STORE_F16DEV) {
-    if (a.has_g)
-      collide_bulk_kernel<true, true><<<h->n_int, BLOCK, 0, stream>>>(a, h->d_blist_int);
-    else
-      collide_bulk_kernel<true, false><<<h->n_int, BLOCK, 0, stream>>>(a, h->d_blist_int);
-  } else {
-    if (a.has_g)
-      collide_bulk_kernel<false, true><<<h->n_int, BLOCK, 0, stream>>>(a, h->d_blist_int);
-    else
-      collide_bulk_kernel<false, false><<<h->n_int, BLOCK, 0, stream>>>(a, h->d_blist_int);
-  }
+  launch_bulk_kernel(h, a, h->cfg.storage == LBM_STORE_F16DEV, stream);
   return hipGetLastError();
 }
 
@@ -902,6 +967,28 @@ hipError_t launch_import(lbm_ctx* h, const float* in) {
   else
     import_kernel<false><<<h->nblocks, BLOCK, 0, h->stream>>>(a, in);
   return hipGetLastError();
+}
+
+// Replace the FP16 storage reference (u_ref: device double [3][ny], or null
+// for none) and re-encode the current state.  Synchronises the stream.
+hipError_t launch_set_reference(lbm_ctx* h, const double* u_ref) {
+  const int ny = h->cfg.ny;
+  float* dnew = nullptr;  // [ny][19] offsets, then [ny][19] pull offsets
+  hipError_t e;
+  if (u_ref) {
+    if ((e = hipMalloc(&dnew, sizeof(float) * 2 * ny * Q)) != hipSuccess) return e;
+    dref_kernel<<<(ny * Q + 255) / 256, 256, 0, h->stream>>>(u_ref, ny, dnew, dnew + ny * Q);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  CollideArgs a;
+  fill_args(h, a, h->cur, h->cur);
+  recode_kernel<<<h->nblocks, BLOCK, 0, h->stream>>>(a, static_cast<_Float16*>(h->f[h->cur]), h->d_dref, dnew);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  if ((e = hipStreamSynchronize(h->stream)) != hipSuccess) return e;
+  if (h->d_dref && (e = hipFree(h->d_dref)) != hipSuccess) return e;
+  h->d_dref = dnew;
+  h->d_dpull = dnew ? dnew + ny * Q : nullptr;
+  return hipSuccess;
 }
 
 // Float bricks <-> float SoA [19][N] for adjoint fields (always FP32).

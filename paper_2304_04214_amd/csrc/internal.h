@@ -33,6 +33,8 @@ struct CollideArgs {
   double* stats;          // [n_planes][ny][zc][9]
   double* wall_acc;       // [2][nx][zc] sums of u_tau in the first off-wall rows, or null
   const float* wall_line; // [2][nx] signed u_tau of each wall line (line-averaged model), or null
+  const float* dref;      // [ny][19] FP16 storage reference offsets r_i(y), or null (r = 0)
+  const float* dpull;     // [ny][19] r of the value a plain (wall-free) pull of direction i reads into row y
   const int* plane_of_x;  // [nx], -1 when not sampled
   int* err;
   int nx, ny, nz, zc, yg, nblocks;
@@ -103,6 +105,8 @@ struct lbm_ctx {
   double* d_wall_acc = nullptr;  // [2][nx][zc], with the wall model
   float* d_wall_line = nullptr;  // [2][nx] line-averaged u_tau of the current step
   double* d_line_part = nullptr; // [2][nx][zc] adjoint partial sums of the line model
+  float* d_dref = nullptr;       // [ny][19] FP16 storage reference offsets (null: none)
+  float* d_dpull = nullptr;      // [ny][19] the same, of the plain pulls' source rows
   int n_planes = 0;
   std::vector<int> plane_of_x;  // host copy of d_plane_of_x
   int stats_on = 0;
@@ -134,6 +138,7 @@ hipError_t launch_stream_only(lbm_ctx* h, int src, int dst);
 hipError_t launch_init(lbm_ctx* h, const float* rho, const float* u, const float* pert, float eps);
 hipError_t launch_export(lbm_ctx* h, float* out);
 hipError_t launch_import(lbm_ctx* h, const float* in);
+hipError_t launch_set_reference(lbm_ctx* h, const double* u_ref);
 hipError_t launch_copy(const void* src, void* dst, int64_t bytes, hipStream_t s);
 void fill_args(lbm_ctx* h, CollideArgs& a, int src, int dst);
 hipError_t launch_wall_line(lbm_ctx* h, CollideArgs& a, hipStream_t stream);

@@ -23,7 +23,11 @@ namespace lbm {
 
 __device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
-// Population storage: float, or half deviations h_i = f_i - w_i.
+// Population storage: float, or half deviations h_i = f_i - w_i - r_i(y),
+// where r_i(y) is the optional per-row reference offset of the storage
+// (f_eq(1, U(y)) - w_i for a reference velocity profile U(y); 0 without one).
+// The `ref` arguments carry r of the stored plane and row; float storage
+// ignores them.
 template <bool F16>
 struct Pop;
 // Loads take a wave-uniform element offset `row` (scalar) and a per-lane byte
@@ -35,22 +39,22 @@ struct Pop<false> {
   __device__ static __forceinline__ Raw raw(const char* p, uint32_t off) {
     return *reinterpret_cast<const float*>(p + off);
   }
-  __device__ static __forceinline__ float cvt(int, Raw r) { return r; }
+  __device__ static __forceinline__ float cvt(int, Raw r, float) { return r; }
   // p: wave-uniform byte pointer; off: per-lane byte offset (+ a constant)
-  __device__ static __forceinline__ float ldp(const char* p, int, uint32_t off) {
+  __device__ static __forceinline__ float ldp(const char* p, int, uint32_t off, float) {
     return *reinterpret_cast<const float*>(p + off);
   }
-  __device__ static __forceinline__ void stp(char* p, int, uint32_t off, float v) {
+  __device__ static __forceinline__ void stp(char* p, int, uint32_t off, float v, float) {
 #if LBM_EXP_F32_NT
     __builtin_nontemporal_store(v, reinterpret_cast<float*>(p + off));  // streamed once, not re-read
 #else
     *reinterpret_cast<float*>(p + off) = v;
 #endif
   }
-  __device__ static __forceinline__ void st_plain(void* base, int, uint32_t e, float v) {
+  __device__ static __forceinline__ void st_plain(void* base, int, uint32_t e, float v, float) {
     static_cast<float*>(base)[e] = v;
   }
-  __device__ static __forceinline__ float ld_plain(const void* base, int, uint32_t e) {
+  __device__ static __forceinline__ float ld_plain(const void* base, int, uint32_t e, float) {
     return static_cast<const float*>(base)[e];
   }
 };
@@ -61,26 +65,27 @@ struct Pop<true> {
   __device__ static __forceinline__ Raw raw(const char* p, uint32_t off) {
     return *reinterpret_cast<const unsigned short*>(p + off);
   }
-  __device__ static __forceinline__ float cvt(int i, Raw r) {
-    return (float)WD[i] + (float)__builtin_bit_cast(_Float16, (unsigned short)r);
+  __device__ static __forceinline__ float cvt(int i, Raw r, float ref) {
+    return ((float)WD[i] + ref) + (float)__builtin_bit_cast(_Float16, (unsigned short)r);
   }
-  // f = w_i + h_i
-  __device__ static __forceinline__ float ldp(const char* p, int i, uint32_t off) {
-    return (float)WD[i] + (float)*reinterpret_cast<const _Float16*>(p + off);
+  // f = w_i + r_i + h_i
+  __device__ static __forceinline__ float ldp(const char* p, int i, uint32_t off, float ref) {
+    return ((float)WD[i] + ref) + (float)*reinterpret_cast<const _Float16*>(p + off);
   }
-  // h_i = f - w_i rounded to nearest even half
-  __device__ static __forceinline__ void stp(char* p, int i, uint32_t off, float v) {
-    const uint32_t hb = __builtin_bit_cast(unsigned short, (_Float16)(v - (float)WD[i]));
+  // h_i = f - w_i - r_i rounded to nearest even half
+  __device__ static __forceinline__ void stp(char* p, int i, uint32_t off, float v, float ref) {
+    const uint32_t hb = __builtin_bit_cast(unsigned short, (_Float16)((v - (float)WD[i]) - ref));
 #if LBM_EXP_F16_NT
     __builtin_nontemporal_store((unsigned short)hb, reinterpret_cast<unsigned short*>(p + off));
 #else
     *reinterpret_cast<unsigned short*>(p + off) = (unsigned short)hb;
 #endif
   }
-  // The deviation h_i itself (kernels that compute on deviations).
-  __device__ static __forceinline__ float cvt_dev(Raw r) {
-    return (float)__builtin_bit_cast(_Float16, (unsigned short)r);
-  }
+  // The deviation from the weights f_i - w_i = h_i + r_i (kernels that compute
+  // on deviations).
+  __device__ static __forceinline__ float cvt_dev(Raw r) { return (float)__builtin_bit_cast(_Float16, (unsigned short)r); }
+  __device__ static __forceinline__ float cvt_dev(Raw r, float ref) { return cvt_dev(r) + ref; }
+  __device__ static __forceinline__ void stp_dev(char* p, uint32_t off, float h, float ref) { stp_dev(p, off, h - ref); }
   __device__ static __forceinline__ void stp_dev(char* p, uint32_t off, float h) {
     const uint32_t hb = __builtin_bit_cast(unsigned short, (_Float16)h);
 #if LBM_EXP_F16_NT
@@ -89,13 +94,19 @@ struct Pop<true> {
     *reinterpret_cast<unsigned short*>(p + off) = (unsigned short)hb;
 #endif
   }
-  __device__ static __forceinline__ void st_plain(void* base, int i, uint32_t e, float v) {
-    static_cast<_Float16*>(base)[e] = (_Float16)(v - (float)WD[i]);
+  __device__ static __forceinline__ void st_plain(void* base, int i, uint32_t e, float v, float ref) {
+    static_cast<_Float16*>(base)[e] = (_Float16)((v - (float)WD[i]) - ref);
   }
-  __device__ static __forceinline__ float ld_plain(const void* base, int i, uint32_t e) {
-    return (float)WD[i] + (float)static_cast<const _Float16*>(base)[e];
+  __device__ static __forceinline__ float ld_plain(const void* base, int i, uint32_t e, float ref) {
+    return ((float)WD[i] + ref) + (float)static_cast<const _Float16*>(base)[e];
   }
 };
+
+// Reference offset r_j(y) of stored plane j in row y (wave-uniform: a scalar
+// load), 0 without a reference profile.
+__device__ __forceinline__ float ref_off(const CollideArgs& a, int j, int y) {
+  return a.dref ? a.dref[y * Q + j] : 0.f;
+}
 
 // Byte pointer to the start of the (x, y) brick row of a buffer (wave-uniform).
 template <bool F16>
@@ -189,7 +200,7 @@ __device__ __forceinline__ float pull_dir(const CollideArgs& a, const Geo& g, in
     ok = bb ? true : ok;
   }
   const char* p = row_ptr<F16>(a.src, rowpart(a, xsrc, ysrc) + (uint32_t)plane * ZT);
-  const float v = Pop<F16>::ldp(p, i, csrc);
+  const float v = Pop<F16>::ldp(p, i, csrc, ref_off(a, plane, ysrc));
   return ok ? v : unset;
 }
 
@@ -238,16 +249,35 @@ __device__ __forceinline__ void issue_pulls(const CollideArgs& a, const Geo& g, 
   }
 }
 
+// Stored plane and source row of the pull of direction i into row g (the
+// wall rules of issue_pulls); wave-uniform.
+__device__ __forceinline__ void pull_plane_row(const CollideArgs& a, const Geo& g, int i, int& plane, int& ysrc) {
+  const int cy = CY[i];
+  plane = i;
+  ysrc = g.ys[cy + 1];
+  if (cy != 0 && g.yout[cy + 1]) {
+    plane = a.ywall == LBM_Y_BOUNCEBACK ? opp(i) : REFLY[i];
+    ysrc = g.y;
+  }
+}
+
+// Reference offset of the value the pull of direction i reads.
+__device__ __forceinline__ float pull_ref(const CollideArgs& a, const Geo& g, int i) {
+  int plane, ysrc;
+  pull_plane_row(a, g, i, plane, ysrc);
+  return ref_off(a, plane, ysrc);
+}
+
 // Populations from the raw loads; sources outside the x range give 0.
 template <bool F16>
 __device__ __forceinline__ void convert_pulls(const CollideArgs& a, const Geo& g, const typename Pop<F16>::Raw r[Q],
                                               float f[Q]) {
   if (interior(g)) {
 #pragma unroll
-    for (int i = 0; i < Q; ++i) f[i] = Pop<F16>::cvt(i, r[i]);
+    for (int i = 0; i < Q; ++i) f[i] = Pop<F16>::cvt(i, r[i], ref_off(a, i, g.ys[CY[i] + 1]));
   } else {
 #pragma unroll
-    for (int i = 0; i < Q; ++i) f[i] = pull_ok(a, g, i) ? Pop<F16>::cvt(i, r[i]) : 0.f;
+    for (int i = 0; i < Q; ++i) f[i] = pull_ok(a, g, i) ? Pop<F16>::cvt(i, r[i], pull_ref(a, g, i)) : 0.f;
   }
 }
 

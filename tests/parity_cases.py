@@ -19,12 +19,23 @@ def rel_linf(a, b):
     return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
 
 
+def reference_offsets(u_ref):
+    """FP16 storage reference offsets r_i(y) = f_eq_i(1, u_ref(y)) - w_i, float32 [19, ny]
+    (the library's definition, evaluated in float64 without fused operations)."""
+    t = O.tables()
+    c, w = t["c"].astype(np.float64), t["w"]
+    u = np.asarray(u_ref, dtype=np.float64)
+    cu = c[:, 0:1] * u[0] + c[:, 1:2] * u[1] + c[:, 2:3] * u[2]
+    uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2]
+    return (w[:, None] * (3.0 * cu + 4.5 * cu * cu - 1.5 * uu)).astype(np.float32)
+
+
 class Case:
     def __init__(self, nx, ny, nz, *, ywall="slip", xbc="inflow", wall_model=True, tau0=0.52, cs_smag=0.1,
                  u_tau=0.008369396673286735, n_modes=24, seed=0, storage="f32", g=(0.0, 0.0, 0.0), eps=0.05,
                  du_amp=1e-3, u_conv=0.1, newton_iters=4, amp_scale=1.0, rates=None, sponge_cells=0,
                  sponge_nu=0.0, outlet="convective", wall_law="reichardt", spectrum=False,
-                 wall_avg="local"):
+                 wall_avg="local", reference=False):
         self.nx, self.ny, self.nz = nx, ny, nz
         self.xbc = xbc
         self.ocfg = O.make_cfg(nx, ny, nz, ywall=YW[ywall], xbc=XB[xbc], wall_model=int(wall_model), tau0=tau0,
@@ -54,6 +65,11 @@ class Case:
         U_g = self.ch.inflow_reichardt(u_tau)
         self.U_g = U_g
         u_g = U_g.float()[:, None, :, None] + du_amp * torch.as_tensor(du, dtype=torch.float32, device="cuda")
+        # FP16 storage as deviations from the equilibrium at the mean inflow profile
+        self.dref = None
+        if reference:
+            self.ch.set_reference(U_g)
+            self.dref = reference_offsets(U_g.cpu().numpy())
         if xbc == "inflow":
             self.ch.set_stg(self.mt, U_g, self.R, self.ab, self.boy, want_fluct=True, k_rans=self.k_om[0],
                             omega_rans=self.k_om[1])

@@ -28,14 +28,16 @@ TOL_FIELD = 5e-6
 TOL_PARAM = 3e-4
 
 
-def storage_round(f, storage):
-    """Values the HIP side holds after importing f (float32, or half deviations)."""
+def storage_round(f, storage, ref=None):
+    """Values the HIP side holds after importing f (float32, or half deviations from the
+    weights plus the optional per-row reference offsets ref [19, ny])."""
     w = O.tables()["w"].astype(np.float32)[:, None, None, None]
     f32 = np.asarray(f, dtype=np.float32)
     if storage == "f32":
         return f32.astype(np.float64)
-    h = (f32 - w).astype(np.float16)
-    return (w + h.astype(np.float32)).astype(np.float64)
+    r = np.zeros((1, 1, 1, 1), np.float32) if ref is None else np.asarray(ref, np.float32)[:, None, :, None]
+    h = ((f32 - w) - r).astype(np.float16)
+    return ((w + r) + h.astype(np.float32)).astype(np.float64)
 
 
 def to_numpy(t):
@@ -47,7 +49,7 @@ def single_step(case, storage="f32", seed=7, planes=(1, 3), t_next=5.0):
     nx, ny, nz = case.nx, case.ny, case.nz
     open_ = case.xbc == "inflow"
     g = np.random.default_rng(seed)
-    s = storage_round(case.f_or, storage)
+    s = storage_round(case.f_or, storage, case.dref)
     hist = np.asarray(case.hist_or, dtype=np.float32).astype(np.float64)
     lam = g.normal(size=(19, nx, ny, nz)).astype(np.float32).astype(np.float64)
     eta = g.normal(size=(5, ny, nz)).astype(np.float32).astype(np.float64)
@@ -121,6 +123,8 @@ CASES = {
                                                                wall_avg="line"), "f32"),
     "f16_slip_inflow_line_averaged_utau": (dict(nx=6, ny=8, nz=70, ywall="slip", xbc="inflow", wall_model=True,
                                                 wall_avg="line"), "f16dev"),
+    "f16ref_slip_inflow_wallmodel": (dict(nx=6, ny=8, nz=70, ywall="slip", xbc="inflow", wall_model=True,
+                                          reference=True), "f16dev"),
     "f16_slip_inflow_musker_wall_law": (dict(nx=6, ny=8, nz=70, ywall="slip", xbc="inflow", wall_model=True,
                                              wall_law="musker"), "f16dev"),
 }
@@ -199,12 +203,13 @@ def loss_grad(m, U_t, R12_t):
     return d
 
 
-@pytest.mark.parametrize("storage,avg", [("f32", "local"), ("f16dev", "local"), ("f32", "line"), ("f16dev", "line")])
-def test_step_record_matches_step(storage, avg):
+@pytest.mark.parametrize("storage,avg,ref", [("f32", "local", False), ("f16dev", "local", False), ("f32", "line", False),
+                                            ("f16dev", "line", False), ("f16dev", "local", True)])
+def test_step_record_matches_step(storage, avg, ref):
     """The recompute entry point reproduces lbm_step bit for bit (same kernels,
     caller buffers) and keeps the inlet plane of every step."""
     case = Case(8, 8, 70, ywall="slip", xbc="inflow", wall_model=True, storage=storage, g=(2e-6, 0.0, 0.0),
-                wall_avg=avg)
+                wall_avg=avg, reference=ref)
     ch = case.ch
     f0, h0 = [t.clone() for t in ch.state()]
     t0 = ch.time
