@@ -21,7 +21,7 @@ import torch
 import oracle as O
 from paper_2304_04214_amd import synthetic as S
 from paper_2304_04214_amd.channel import Channel
-from parity_cases import rel_linf
+from parity_cases import reference_offsets, rel_linf
 from test_gpu_adjoint import TOL_FIELD, TOL_PARAM, storage_round
 
 pytestmark = pytest.mark.gpu
@@ -32,7 +32,8 @@ def _say(*a):
 
 
 def workload(name, storage, full_pert=True):
-    """Oracle and HIP sides of a benchmark workload from the same raw synthetic inputs."""
+    """Oracle and HIP sides of a benchmark workload from the same raw synthetic inputs.
+    storage "f16ref": FP16 deviations from the equilibrium at the mean inflow profile."""
     w = S.WORKLOADS[name]
     nx, ny, nz = w["nx"], w["ny"], w["nz"]
     k = int(name[1])
@@ -47,11 +48,16 @@ def workload(name, storage, full_pert=True):
         du = S.rng(1000 + k).uniform(-1.0, 1.0, (3, nx, ny, nz)).astype(np.float32)
     f, hist = O.init(cfg, U[:, None, :, None] + 1e-3 * du, pert=dp, eps=0.05)
     del du, dp
-    f = storage_round(f, storage)
+    ch = Channel(nx, ny, nz, tau0=w["tau0"], storage="f16dev" if storage == "f16ref" else storage, ywall="slip",
+                 xbc="inflow", wall_model=True, cs_smag=S.CS_SMAG, u_conv=S.U_C)
+    U_g = ch.inflow_reichardt(w["u_tau"])
+    dref = None
+    if storage == "f16ref":
+        ch.set_reference(U_g)
+        dref = reference_offsets(U_g.cpu().numpy())
+    f = storage_round(f, "f16dev" if storage == "f16ref" else storage, dref)
     hist = hist.astype(np.float32).astype(np.float64)
-    ch = Channel(nx, ny, nz, tau0=w["tau0"], storage=storage, ywall="slip", xbc="inflow", wall_model=True,
-                 cs_smag=S.CS_SMAG, u_conv=S.U_C)
-    ch.set_stg(mt, ch.inflow_reichardt(w["u_tau"]), R, ab, boy)
+    ch.set_stg(mt, U_g, R, ab, boy)
     ch.load_populations(torch.as_tensor(f.astype(np.float32)))
     ch.state()[1].copy_(torch.as_tensor(hist, dtype=torch.float32))
     delta = ny // 2
@@ -70,8 +76,9 @@ def sample_nodes(nx, ny, nz, planes, seed, n_random=3000):
     return np.unique(np.asarray(nodes, dtype=np.int64))
 
 
-@pytest.mark.parametrize("name,storage,tol", [("c2", "f32", 1e-5), ("c2", "f16dev", 2e-4), ("c3", "f32", 1e-5),
-                                              ("c3", "f16dev", 2e-4), ("c5", "f32", 1e-5)])
+@pytest.mark.parametrize("name,storage,tol", [("c2", "f32", 1e-5), ("c2", "f16dev", 2e-4), ("c2", "f16ref", 2e-4),
+                                              ("c3", "f32", 1e-5), ("c3", "f16dev", 2e-4), ("c3", "f16ref", 2e-4),
+                                              ("c5", "f32", 1e-5)])
 def test_full_size_one_step_sampled(name, storage, tol):
     _say("full size", name, storage)
     cfg, stg, f, hist, ch, planes = workload(name, storage, full_pert=(name == "c2"))
