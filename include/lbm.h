@@ -250,7 +250,9 @@ lbm_status lbm_import_f32(lbm_handle h, const float* in);
  * r = 0 (deviations from the weights, the default).  With u_ref near the
  * mean flow the stored deviations, and so their rounding, shrink by about
  * |u'| / |U|.  The arithmetic is unchanged (FP32); the current state is
- * re-encoded in place (one more rounding).  Synchronises the handle's stream.
+ * re-encoded in place (one more rounding); population buffers saved earlier
+ * (checkpoints, the other buffer) keep the old encoding.  Synchronises the
+ * handle's stream.  On a HIP error the old reference stays in force.
  */
 lbm_status lbm_set_reference(lbm_handle h, const double* u_ref);
 

@@ -973,18 +973,25 @@ hipError_t launch_import(lbm_ctx* h, const float* in) {
 // for none) and re-encode the current state.  Synchronises the stream.
 hipError_t launch_set_reference(lbm_ctx* h, const double* u_ref) {
   const int ny = h->cfg.ny;
+  if (!u_ref && !h->d_dref) return hipSuccess;  // no reference before or after
   float* dnew = nullptr;  // [ny][19] offsets, then [ny][19] pull offsets
-  hipError_t e;
+  hipError_t e = hipSuccess;
   if (u_ref) {
     if ((e = hipMalloc(&dnew, sizeof(float) * 2 * ny * Q)) != hipSuccess) return e;
     dref_kernel<<<(ny * Q + 255) / 256, 256, 0, h->stream>>>(u_ref, ny, dnew, dnew + ny * Q);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
+    e = hipGetLastError();
   }
-  CollideArgs a;
-  fill_args(h, a, h->cur, h->cur);
-  recode_kernel<<<h->nblocks, BLOCK, 0, h->stream>>>(a, static_cast<_Float16*>(h->f[h->cur]), h->d_dref, dnew);
-  if ((e = hipGetLastError()) != hipSuccess) return e;
-  if ((e = hipStreamSynchronize(h->stream)) != hipSuccess) return e;
+  if (e == hipSuccess) {
+    CollideArgs a;
+    fill_args(h, a, h->cur, h->cur);
+    recode_kernel<<<h->nblocks, BLOCK, 0, h->stream>>>(a, static_cast<_Float16*>(h->f[h->cur]), h->d_dref, dnew);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+  if (e != hipSuccess) {  // the handle keeps its old reference
+    if (dnew) (void)hipFree(dnew);
+    return e;
+  }
   if (h->d_dref && (e = hipFree(h->d_dref)) != hipSuccess) return e;
   h->d_dref = dnew;
   h->d_dpull = dnew ? dnew + ny * Q : nullptr;
