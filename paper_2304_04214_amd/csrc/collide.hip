@@ -812,13 +812,14 @@ void launch_edge_kernels(lbm_ctx* h, const CollideArgs& a, hipStream_t stream) {
   }
 }
 
+// The step's line u_tau (line-averaged wall model; also when no general block
+// exists, e.g. a periodic channel with FP16 storage) and the general blocks.
 hipError_t launch_boundary(lbm_ctx* h, int src, int dst, hipStream_t stream, const float* u_in) {
-  if (h->n_bnd == 0) return hipSuccess;
   CollideArgs a;
   fill_args(h, a, src, dst);
   if (u_in) a.u_in = u_in;
   hipError_t e = launch_wall_line(h, a, stream);
-  if (e != hipSuccess) return e;
+  if (e != hipSuccess || h->n_bnd == 0) return e;
   launch_edge_kernels(h, a, stream);
   return hipGetLastError();
 }

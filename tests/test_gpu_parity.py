@@ -233,7 +233,9 @@ def test_nonfinite_density_is_reported():
 
 
 @pytest.mark.parametrize("name", ["slip-inflow-wallmodel", "periodic-smag-force", "slip-inflow-wallmodel-sponge",
-                                  "slip-inflow-musker-wall-law", "slip-inflow-line-averaged-utau"])
+                                  "slip-inflow-musker-wall-law", "slip-inflow-line-averaged-utau",
+                                  "bounceback-wallmodel", "bounceback-inflow-ny4", "slip-inflow-nz1",
+                                  "bounceback-periodic-line-averaged-utau"])
 def test_fp16_deviation_storage_matches_oracle(name):
     spec = PARITY_CASES[name]
     _say("fp16 parity", name)
