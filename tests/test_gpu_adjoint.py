@@ -125,6 +125,11 @@ CASES = {
                                                 wall_avg="line"), "f16dev"),
     "f16ref_slip_inflow_wallmodel": (dict(nx=6, ny=8, nz=70, ywall="slip", xbc="inflow", wall_model=True,
                                           reference=True), "f16dev"),
+    "f16ref_bounceback_periodic_force": (dict(nx=5, ny=9, nz=66, ywall="bounceback", xbc="periodic",
+                                              wall_model=True, g=(4e-6, 0.0, 0.0), reference=True), "f16dev"),
+    "f16_bounceback_periodic_line_averaged_utau": (dict(nx=5, ny=9, nz=66, ywall="bounceback", xbc="periodic",
+                                                        wall_model=True, g=(4e-6, 0.0, 0.0), wall_avg="line"),
+                                                   "f16dev"),
     "f16_slip_inflow_musker_wall_law": (dict(nx=6, ny=8, nz=70, ywall="slip", xbc="inflow", wall_model=True,
                                              wall_law="musker"), "f16dev"),
 }

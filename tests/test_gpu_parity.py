@@ -249,7 +249,8 @@ def test_fp16_deviation_storage_matches_oracle(name):
     assert err <= TOL16
 
 
-@pytest.mark.parametrize("name", ["slip-inflow-wallmodel", "bounceback-wallmodel", "periodic-smag-force"])
+@pytest.mark.parametrize("name", ["slip-inflow-wallmodel", "bounceback-wallmodel", "periodic-smag-force",
+                                  "slip-inflow-zero-gradient-outlet", "slip-inflow-line-averaged-utau"])
 def test_fp16_reference_storage_matches_oracle(name):
     """FP16 deviations from the equilibrium at the mean inflow profile (lbm_set_reference):
     20 steps against the oracle, with a smaller error than deviations from the weights
