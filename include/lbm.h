@@ -228,6 +228,17 @@ lbm_status stg_inlet_fill(lbm_handle h, const lbm_stg* stg, double t);
  */
 lbm_status lbm_step(lbm_handle h, const lbm_stg* stg, int32_t nsteps);
 
+/*
+ * enable = 1: lbm_step runs whole batches of 32 steps as a replayed HIP graph
+ * (captured once per state parity and reused until a call changes a kernel
+ * argument: lbm_set_state, a new lbm_stg, lbm_stats ATTACH / DETACH,
+ * lbm_set_cs_smag, lbm_set_reference), the rest of a call as plain
+ * launches; the results are identical.  It removes the per-launch host cost,
+ * which dominates on small lattices.  Not used while lbm_kernel_timing is
+ * enabled.  enable = 0 (default): plain launches only.
+ */
+lbm_status lbm_set_graphs(lbm_handle h, int32_t enable);
+
 /* Streaming with the wall rules only, current buffer -> other buffer, no
    collision; populations with no source (outside the x range) are set to -1.
    The state then lives in the other buffer (time index unchanged).

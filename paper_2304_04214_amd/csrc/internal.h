@@ -106,6 +106,14 @@ struct lbm_ctx {
   float* d_wall_line = nullptr;  // [2][nx] line-averaged u_tau of the current step
   double* d_line_part = nullptr; // [2][nx][zc] adjoint partial sums of the line model
   float* d_dref = nullptr;       // [ny][19] FP16 storage reference offsets (null: none)
+  // Replayed step graphs (lbm_set_graphs): one per state parity, valid while
+  // gen (bumped by every call that changes a kernel argument) is unchanged.
+  int graphs = 0;
+  uint64_t gen = 1;
+  hipGraphExec_t gexec[2] = {nullptr, nullptr};
+  uint64_t ggen[2] = {0, 0};
+  hipStream_t cap = nullptr;  // capture stream (default priority); graphs run on `stream`
+  double* d_time0 = nullptr;  // start time of a replayed graph
   float* d_dpull = nullptr;      // [ny][19] the same, of the plain pulls' source rows
   int n_planes = 0;
   std::vector<int> plane_of_x;  // host copy of d_plane_of_x
@@ -153,7 +161,8 @@ hipError_t launch_adjoint_reduce(lbm_ctx* h, double* grad);
 // stg.hip
 hipError_t launch_stg_bind(lbm_ctx* h, const lbm_stg* s);
 hipError_t launch_stg_fill(lbm_ctx* h, double t, hipStream_t stream, float* fluct = nullptr, float* u_in = nullptr);
+hipError_t launch_set_time(double* p, double v, hipStream_t stream);
 hipError_t launch_stg_fill_batch(lbm_ctx* h, double time0, int nb, hipStream_t stream, float* ring, float* fring,
-                                 int last_j);
+                                 int last_j, const double* time_base = nullptr);
 hipError_t launch_inflow_reichardt(lbm_ctx* h, double u_tau, double* u_rans);
 }  // namespace lbm

@@ -113,11 +113,13 @@ __global__ __launch_bounds__(256) void stg_spectrum_kernel(lbm_stg s, float* row
 
 // One block per (inlet row y, 64 spanwise nodes, step); its four waves each
 // sum a quarter of the modes, and the partial sums are added in a fixed order.
-// Step j = blockIdx.z has time time0 + j.  With ring == nullptr the plane
-// goes to s.u_in / s.fluct; otherwise to plane j of ring / fring, and the
-// plane of step last_j also to s.u_in / s.fluct.
+// Step j = blockIdx.z has time time0 + j (plus *time_base when given: a
+// replayed graph reads its start time from device memory).  With ring ==
+// nullptr the plane goes to s.u_in / s.fluct; otherwise to plane j of ring /
+// fring, and the plane of step last_j also to s.u_in / s.fluct.
 __global__ __launch_bounds__(256) void stg_fill_kernel(lbm_stg s, StgTables t, int ny, int nz, double time0,
-                                                       int* err, float* ring, float* fring, int last_j) {
+                                                       int* err, float* ring, float* fring, int last_j,
+                                                       const double* time_base) {
   __shared__ float2 rowph[LBM_MAX_MODES];
   __shared__ float amp[3][LBM_MAX_MODES];
   __shared__ float part[3][3][64];
@@ -128,7 +130,7 @@ __global__ __launch_bounds__(256) void stg_fill_kernel(lbm_stg s, StgTables t, i
   const int z = zr < nz ? zr : nz - 1;
   const int N = s.n_modes;
   const int j = blockIdx.z;
-  const double time = time0 + j;
+  const double time = (time_base ? *time_base : 0.0) + time0 + j;
   // (y, t)-dependent phase of every mode, FP64 then reduced to [0, 2 pi)
   for (int n = threadIdx.x; n < N; n += 256) {
     const double ph = fmod(t.ky[n] * (y + 0.5) + s.omega[n] * time + s.phi[n], TWO_PI);
@@ -264,7 +266,7 @@ hipError_t launch_stg_fill(lbm_ctx* h, double time, hipStream_t stream, float* f
   lbm_stg s = h->stg;
   if (fluct) s.fluct = fluct;
   if (u_in) s.u_in = u_in;
-  stg_fill_kernel<<<grid, 256, 0, stream>>>(s, h->tab, ny, nz, time, h->d_err, nullptr, nullptr, -1);
+  stg_fill_kernel<<<grid, 256, 0, stream>>>(s, h->tab, ny, nz, time, h->d_err, nullptr, nullptr, -1, nullptr);
   return hipGetLastError();
 }
 
@@ -272,10 +274,20 @@ hipError_t launch_stg_fill(lbm_ctx* h, double time, hipStream_t stream, float* f
 // one launch, into plane j of ring (and fring); the plane of step last_j
 // (-1: none) also goes to the bound u_in / fluct.
 hipError_t launch_stg_fill_batch(lbm_ctx* h, double time0, int nb, hipStream_t stream, float* ring, float* fring,
-                                 int last_j) {
+                                 int last_j, const double* time_base) {
   const int ny = h->cfg.ny, nz = h->cfg.nz;
   dim3 grid((nz + 63) / 64, ny, nb);
-  stg_fill_kernel<<<grid, 256, 0, stream>>>(h->stg, h->tab, ny, nz, time0, h->d_err, ring, fring, last_j);
+  stg_fill_kernel<<<grid, 256, 0, stream>>>(h->stg, h->tab, ny, nz, time0, h->d_err, ring, fring, last_j, time_base);
+  return hipGetLastError();
+}
+
+__global__ void set_time_kernel(double* p, double v) {
+  if (threadIdx.x == 0) *p = v;
+}
+
+// *p = v on the stream (the start time of a replayed step graph).
+hipError_t launch_set_time(double* p, double v, hipStream_t stream) {
+  set_time_kernel<<<1, 64, 0, stream>>>(p, v);
   return hipGetLastError();
 }
 
