@@ -244,7 +244,7 @@ def main():
     ap.add_argument("--adj-steps", type=int, default=400, help="steps of the adjoint workload (loss horizon)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py: this build runs on one GPU only (the path shards over x-slabs by design, "
+        print("bench.py: the library runs on one GPU only (the path shards over x-slabs by design, "
               "not implemented here); use --gpus 1", file=sys.stderr)
         sys.exit(2)
     import torch
