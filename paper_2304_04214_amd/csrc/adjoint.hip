@@ -31,6 +31,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <vector>
 
 #include "internal.h"
 #include "stream.h"
@@ -525,21 +526,18 @@ __device__ __forceinline__ void node_adjoint(const AdjointArgs& A, AdjLds& L, in
   }
 }
 
-// One thread per node; a block is 4 consecutive y rows of one (x, z-chunk).
-// With an open channel the grid starts with the blocks of the planes x = 0
-// and x = nx-2 (dispatched first, so their longer work overlaps the bulk):
-// each block at nx-2 first does the outlet node of its (y, z) (x = nx-1),
-// whose dL/dhist feeds its own c_x < 0 values.  The bulk blocks follow in
-// memory order (x = 1 .. nx-3; every block of a periodic channel).
+// One thread per node; a block is 4 consecutive y rows of one (x, z-chunk),
+// the block entry blist[blockIdx.x] (adjoint_list: the planes x = 0 and
+// x = nx-2 of an open channel first, so that their longer work overlaps the
+// rest; -1 pads).  Each block at nx-2 first does the outlet node of its
+// (y, z) (x = nx-1), whose dL/dhist feeds its own c_x < 0 values.
 template <bool F16>
-__global__ __launch_bounds__(BLOCK) void adjoint_kernel(AdjointArgs A) {
+__global__ __launch_bounds__(BLOCK) void adjoint_kernel(AdjointArgs A, const int* __restrict__ blist) {
   __shared__ AdjLds L;
   const CollideArgs& a = A.c;
-  const int per_x = a.zc * a.yg;
-  const int b = (int)blockIdx.x;
+  const int e = blist[blockIdx.x];
+  if (e < 0) return;  // block-uniform
   const bool open = a.xbc == LBM_X_INFLOW;
-  int e = b;
-  if (open) e = b < per_x ? b : (b < 2 * per_x ? (a.nx - 3) * per_x + b : b - per_x);
   int x0, zci, gy;
   block_coords(a, e, x0, zci, gy);
   const int lane = threadIdx.x & (ZT - 1);
@@ -638,8 +636,40 @@ int adjoint_blocks(const lbm_ctx* h) {
   return h->cfg.xbc == LBM_X_INFLOW ? (h->cfg.nx - 1) * h->zc * h->yg : h->nblocks;
 }
 
-// One launch over all block entries of adjoint_blocks(); the inlet plane at
-// t_next, unless given, is computed first.
+// Dispatch order of the adjoint's block entries, built on the first adjoint
+// step: the open channel's planes x = 0 and x = nx-2, then the other columns
+// (x, y-group) dealt to the XCDs by xcd_order, the y-groups holding a wall row
+// (longer work) with their own turn.  Columns whole on one XCD also keep the
+// partial cache lines of the +-1 z scatters of neighbouring z-chunks in one L2.
+hipError_t adjoint_list(lbm_ctx* h) {
+  if (h->d_ablist) return hipSuccess;
+  const lbm_config& c = h->cfg;
+  const bool open = c.xbc == LBM_X_INFLOW;
+  const bool walls = c.ywall != LBM_Y_PERIODIC;
+  std::vector<int> ends, rest;
+  std::vector<char> heavy;
+  for (int x = 0; x < (open ? c.nx - 1 : c.nx); ++x) {
+    const bool end = open && (x == 0 || x == c.nx - 2);
+    for (int gy = 0; gy < h->yg; ++gy) {
+      if (!end) heavy.push_back(walls && (gy == 0 || gy == h->yg - 1));
+      for (int zci = 0; zci < h->zc; ++zci) (end ? ends : rest).push_back((x * h->zc + zci) * h->yg + gy);
+    }
+  }
+  rest = xcd_order(rest, h->zc, &heavy);
+  ends.insert(ends.end(), rest.begin(), rest.end());
+  hipError_t err;
+  if ((err = hipMalloc(&h->d_ablist, sizeof(int) * ends.size())) != hipSuccess) return err;
+  if ((err = hipMemcpy(h->d_ablist, ends.data(), sizeof(int) * ends.size(), hipMemcpyHostToDevice)) != hipSuccess) {
+    (void)hipFree(h->d_ablist);
+    h->d_ablist = nullptr;
+    return err;
+  }
+  h->n_ablist = (int)ends.size();
+  return hipSuccess;
+}
+
+// One launch over all block entries of adjoint_blocks() (in adjoint_list's
+// order); the inlet plane at t_next, unless given, is computed first.
 // With the line-averaged wall model the step's line u_tau is recomputed from
 // s_n and the inlet plane, and the probe launch runs before the main one.
 hipError_t launch_adjoint(lbm_ctx* h, const AdjointArgs& args, int storage_f16, double t_next, bool fill_inlet,
@@ -660,10 +690,11 @@ hipError_t launch_adjoint(lbm_ctx* h, const AdjointArgs& args, int storage_f16, 
       adjoint_line_probe_kernel<false><<<nprobe, BLOCK, 0, h->stream>>>(A);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
+  if ((e = adjoint_list(h)) != hipSuccess) return e;
   if (storage_f16)
-    adjoint_kernel<true><<<adjoint_blocks(h), BLOCK, 0, h->stream>>>(A);
+    adjoint_kernel<true><<<h->n_ablist, BLOCK, 0, h->stream>>>(A, h->d_ablist);
   else
-    adjoint_kernel<false><<<adjoint_blocks(h), BLOCK, 0, h->stream>>>(A);
+    adjoint_kernel<false><<<h->n_ablist, BLOCK, 0, h->stream>>>(A, h->d_ablist);
   return hipGetLastError();
 }
 

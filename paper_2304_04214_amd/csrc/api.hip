@@ -234,6 +234,7 @@ lbm_status lbm_destroy(lbm_handle h) {
   if (h->d_guin) (void)hipFree(h->d_guin);
   if (h->d_uin_ring) (void)hipFree(h->d_uin_ring);
   if (h->d_fl_ring) (void)hipFree(h->d_fl_ring);
+  if (h->d_ablist) (void)hipFree(h->d_ablist);
   if (h->d_time0) (void)hipFree(h->d_time0);
   for (int p = 0; p < 2; ++p)
     if (h->gexec[p]) (void)hipGraphExecDestroy(h->gexec[p]);

@@ -865,7 +865,7 @@ hipError_t launch_bulk(lbm_ctx* h, int src, int dst, hipStream_t stream) {
 // Columns go to XCDs in turn, each class of column (heavy[c]: wall groups,
 // whose blocks take longer) with its own turn, so that every XCD gets its
 // share of both; queues are padded with -1 (empty block).
-std::vector<int> xcd_order(const std::vector<int>& entries, int zc, const std::vector<char>* heavy = nullptr) {
+std::vector<int> xcd_order(const std::vector<int>& entries, int zc, const std::vector<char>* heavy) {
   constexpr int NX = 8;
   std::vector<std::vector<int>> q(NX);
   const size_t ncol = entries.size() / zc;

@@ -129,6 +129,8 @@ struct lbm_ctx {
   float* d_guin = nullptr;      // [3][ny][nz], when the caller passes no g_uin
   float* d_uin_ring = nullptr;  // [STG_BATCH][3][ny][nz] inlet planes of the steps of one batch
   float* d_fl_ring = nullptr;   // the same for a v', when the bound STG inputs keep it
+  int* d_ablist = nullptr;      // [n_ablist] adjoint block entries in dispatch order (-1 pads)
+  int n_ablist = 0;
   int timing = 0;
   std::vector<hipEvent_t> ev;  // pairs (start, stop) of timed launches
   int64_t ev_used = 0;
@@ -150,6 +152,9 @@ hipError_t launch_set_reference(lbm_ctx* h, const double* u_ref);
 hipError_t launch_copy(const void* src, void* dst, int64_t bytes, hipStream_t s);
 void fill_args(lbm_ctx* h, CollideArgs& a, int src, int dst);
 hipError_t launch_wall_line(lbm_ctx* h, CollideArgs& a, hipStream_t stream);
+// Entries of columns (x, y-group) of zc z-chunks each, in column order, dealt
+// to the 8 XCDs column by column; -1 pads the result.
+std::vector<int> xcd_order(const std::vector<int>& entries, int zc, const std::vector<char>* heavy = nullptr);
 hipError_t launch_field_export(lbm_ctx* h, const float* bricks, float* soa);
 hipError_t launch_field_import(lbm_ctx* h, const float* soa, float* bricks);
 // adjoint.hip
