@@ -196,6 +196,37 @@ def _stg(ny, n_modes, seed, u_rans=None, R=None):
     return O.StgInputs(mt["q"], mt["sigma"], mt["kmag"], mt["d"], mt["phi"], mt["omega"], u_rans, R, ab, boy)
 
 
+def test_stg_single_mode_is_the_closed_form():
+    """Eq. (22)-(25) with one mode (q = 1): u_in(y, z, t) = U(y) + s_b a(y) sqrt(6) sigma
+    cos(k (d_y y_c + d_z z) + omega t + phi), y_c = iy + 1/2 and z = iz (lattice units), a the
+    lower Cholesky factor of R(y) (numpy's), with a full R (R31, R32 != 0) and per-row s_b."""
+    ny, nz, t = 8, 6, 37.0
+    cfg = O.make_cfg(4, ny, nz, ywall=2, xbc=1, tau0=0.52)
+    d = np.array([0.48, -0.6, 0.64])
+    d /= np.linalg.norm(d)
+    sigma = np.cross(d, [0.0, 0.0, 1.0])
+    sigma /= np.linalg.norm(sigma)
+    k, phi, omega = 0.7, 1.3, 0.021
+    eta = (np.arange(ny) + 0.5) / (ny / 2) - 1
+    R = np.stack([1.0 + 3 * eta ** 2, eta, 0.5 + 0.5 * eta ** 2, 0.2 * eta, -0.1 + 0.05 * eta, 0.7 + 0.8 * eta ** 2])
+    R *= 1e-4
+    U = np.zeros((3, ny))
+    U[0] = 0.05 + 0.01 * eta ** 2
+    amp_bin = np.array([1.0, 0.5, 2.0])
+    bin_of_y = np.array([0, 0, 1, 1, 2, 2, 0, 1], dtype=np.int32)
+    stg = O.StgInputs([1.0], sigma[:, None], [k], d[:, None], [phi], [omega], U, R, amp_bin, bin_of_y)
+    st, uin = O.stg_plane(cfg, stg, t)
+    assert st == O.OK
+    ref = np.zeros((3, ny, nz))
+    for y in range(ny):
+        Ry = np.array([[R[0, y], R[1, y], R[3, y]], [R[1, y], R[2, y], R[4, y]], [R[3, y], R[4, y], R[5, y]]])
+        a = np.linalg.cholesky(Ry)
+        for z in range(nz):
+            v = np.sqrt(6.0) * sigma * np.cos(k * (d[1] * (y + 0.5) + d[2] * z) + omega * t + phi)
+            ref[:, y, z] = U[:, y] + amp_bin[bin_of_y[y]] * (a @ v)
+    assert np.abs(uin - ref).max() <= 1e-14
+
+
 def test_stg_ensemble_covariance_converges_to_R():
     """Eq. (25): with |sigma| = 1, sigma . d = 0, sum q = 1 and random phases the
     fluctuation has E[v v^T] = I, so E[u' u'^T] = a a^T = R (reading R12)."""
