@@ -228,9 +228,24 @@ def cpu_baseline(target_s=15.0):
     st, f, h = O.run(cfg, f, h, 0, steps, stg=stg)
     dt = time.perf_counter() - t0
     N = nx * ny * nz
-    return dict(value=N * steps / dt / 1e6, unit="MLUPS", cores=O.num_threads(), kind="oracle",
+    cores = O.num_threads()
+    # the same slab on one thread, about a third of the time budget
+    O.set_num_threads(1)
+    try:
+        t0 = time.perf_counter()
+        O.run(cfg, f, h, 0, 1, stg=stg)
+        per1 = time.perf_counter() - t0
+        steps1 = max(2, min(100, int(target_s / 3 / max(per1, 1e-6))))
+        t0 = time.perf_counter()
+        O.run(cfg, f, h, 0, steps1, stg=stg)
+        dt1 = time.perf_counter() - t0
+    finally:
+        O.set_num_threads(cores)
+    return dict(value=N * steps / dt / 1e6, unit="MLUPS", cores=cores, kind="oracle",
+                single_thread_value=N * steps1 / dt1 / 1e6,
                 sample="x-slab %dx%dx%d of the 768x64x192 Re_tau=1000 workload (same boundaries, STG N=200), "
-                       "%d steps, %.1f s" % (nx, ny, nz, steps, dt))
+                       "%d steps, %.1f s on %d threads; %d steps, %.1f s on one thread" % (
+                           nx, ny, nz, steps, dt, cores, steps1, dt1))
 
 
 def main():

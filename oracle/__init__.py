@@ -101,6 +101,7 @@ def lib():
             "oracle_macro": (None, [P, P, P, P]),
             "oracle_run": (I, [P, P, D, I, P, P, P, I, P, P]),
             "oracle_num_threads": (I, []),
+            "oracle_set_num_threads": (None, [I]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(_lib, name)
@@ -421,3 +422,8 @@ def macro(cfg, f):
 def num_threads():
     """OpenMP threads the oracle's parallel loops use."""
     return int(lib().oracle_num_threads())
+
+
+def set_num_threads(n):
+    """Set the OpenMP threads of the oracle's parallel loops (n >= 1)."""
+    lib().oracle_set_num_threads(int(n))

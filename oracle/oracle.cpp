@@ -1416,3 +1416,12 @@ extern "C" int oracle_num_threads(void) {
   return 1;
 #endif
 }
+
+/* Threads of the following parallel loops (n >= 1); no effect without OpenMP. */
+extern "C" void oracle_set_num_threads(int n) {
+#ifdef _OPENMP
+  if (n >= 1) omp_set_num_threads(n);
+#else
+  (void)n;
+#endif
+}
