@@ -168,18 +168,20 @@ struct AdjLds {
   float u2[2][2][ZT];  // forward: (u_x, u_z) of rows 1 and ny-2
   float g2[2][2][ZT];  // reverse: dL/d(u_x, u_z) of those rows, from the wall rows
   double part[YROWS];
+  float gup[5][BLOCK];  // outlet node's U_c dL/dhist_n, for the node upstream of it
 };
 
 // The adjoint of one node (x, y, z) of the calling thread (see the file
-// comment).  gup: on the outlet plane (x = nx-1) receives U_c dL/dhist_n of the
-// c_x < 0 populations; on the plane x = nx-2 it is added to them.  csb: the
-// node's dL/dC_s is added.  Block-uniform x; contains __syncthreads.
+// comment).  L.gup (the thread's slot): on the outlet plane (x = nx-1)
+// receives U_c dL/dhist_n of the c_x < 0 populations; on the plane x = nx-2 it
+// is added to them.  csb: the node's dL/dC_s is added.  Block-uniform x;
+// contains __syncthreads.
 //
 // PROBE (line-averaged model only): stop after the wall force and store the
 // wave's sum of dL/d(line u_tau) of the wall rows in A.line_part.
 template <bool F16, bool PROBE = false>
 __device__ __forceinline__ void node_adjoint(const AdjointArgs& A, AdjLds& L, int x, int y, int z, int lane,
-                                             int base, int zci, bool own, bool active, float gup[5], float& csb) {
+                                             int base, int zci, bool own, bool active, float& csb) {
   const CollideArgs& a = A.c;
   const bool mine = own && active;
   const Col col = make_col<F16>(a, z);
@@ -187,9 +189,14 @@ __device__ __forceinline__ void node_adjoint(const AdjointArgs& A, AdjLds& L, in
   typename Pop<F16>::Raw r[Q];
   issue_pulls<F16>(a, g, col, r);
   const uint32_t erow = rowpart(a, x, y) + col.c0;
+  // lambda_{n+1}(X): with FP32 states loaded here, in flight with the pulls;
+  // with FP16 states (more waves per SIMD) before its use, to hold fewer
+  // registers through the forward recompute
   float lam[Q];
+  if (!F16) {
 #pragma unroll
-  for (int i = 0; i < Q; ++i) lam[i] = A.lam_next[erow + (uint32_t)i * ZT];
+    for (int i = 0; i < Q; ++i) lam[i] = A.lam_next[erow + (uint32_t)i * ZT];
+  }
   float f[Q];
   convert_pulls<F16>(a, g, r, f);
 
@@ -214,7 +221,6 @@ __device__ __forceinline__ void node_adjoint(const AdjointArgs& A, AdjLds& L, in
   const float jx = (pr.d[3] + pr.d[7]) - (pr.d[1] + pr.d[5] + pr.d[8]);
   const float jy = pr.d[4] - (pr.d[0] + pr.d[5] + pr.d[6] + pr.d[7]);
   const float jz = -(pr.d[0] + pr.d[1] + pr.d[2] + pr.d[3] + pr.d[4]);
-  const float iw = 1.f / rho;  // pre-force velocities j / rho of the wall model
   float Fx = rho * a.g[0], Fy = rho * a.g[1], Fz = rho * a.g[2];
   const bool bot = base == 0, top = base == a.ny - YROWS;
   const bool wblock = a.wall_model && (bot || top);  // block-uniform
@@ -222,11 +228,16 @@ __device__ __forceinline__ void node_adjoint(const AdjointArgs& A, AdjLds& L, in
   const bool nrow = wblock && ((bot && y == 1) || (top && y == a.ny - 2));
   const int wslot = (bot && y <= 1) ? 0 : 1;
   bool wact = false, wbas = false;  // force applied; base vector defined
-  float wex = 0.f, wez = 0.f, witn = 0.f, wtw = 0.f, wut = 1.f, wdg = 1.f, wsg = 0.f, wline = 0.f;
+  // wall state kept for the reverse sweep: e_x, 1/|t|, the signed u_tau (the
+  // force is -rho wsu |wsu| e_x), d(u_tau u+)/du_tau and the pre-force u_w
+  float wex = 0.f, wez = 0.f, witn = 0.f, wsu = 0.f, wdg = 1.f, uwx = 0.f, uwz = 0.f;
   if (wblock) {
+    const float iw = 1.f / rho;  // pre-force velocities j / rho of the wall model
+    uwx = jx * iw;
+    uwz = jz * iw;
     if (nrow) {
-      L.u2[wslot][0][lane] = jx * iw;
-      L.u2[wslot][1][lane] = jz * iw;
+      L.u2[wslot][0][lane] = uwx;
+      L.u2[wslot][1][lane] = uwz;
     }
     __syncthreads();
     if (wrow) {
@@ -237,15 +248,13 @@ __device__ __forceinline__ void node_adjoint(const AdjointArgs& A, AdjLds& L, in
         witn = 1.f / sqrtf(tn2);
         wex = u2x * witn;
         wez = u2z * witn;
-        wline = a.wall_line[wslot * a.nx + x];
-        if (wline != 0.f) {
+        wsu = a.wall_line[wslot * a.nx + x];
+        if (wsu != 0.f) {
           wact = true;
-          wut = fabsf(wline);
-          wsg = wline > 0.f ? 1.f : -1.f;
-          wtw = -wsg * rho * wline * wline;
+          const float wtw = -rho * wsu * fabsf(wsu);
           Fx += wtw * wex;
           Fz += wtw * wez;
-          const float yp = a.y_wall * wut * a.inv_nu0;
+          const float yp = a.y_wall * fabsf(wsu) * a.inv_nu0;
           float up, dup;
           wall_law(a, yp, up, dup);
           wdg = up + yp * dup;  // d(u_tau u+)/du_tau at the line's root
@@ -255,15 +264,15 @@ __device__ __forceinline__ void node_adjoint(const AdjointArgs& A, AdjLds& L, in
         witn = 1.f / sqrtf(tn2);
         wex = u2x * witn;
         wez = u2z * witn;
-        const float uhat = jx * iw * wex + jz * iw * wez;
+        const float uhat = uwx * wex + uwz * wez;
         if (uhat != 0.f) {
           wact = true;
-          wut = newton_utau(a, fabsf(uhat));
-          wsg = uhat > 0.f ? 1.f : -1.f;
-          wtw = -wsg * rho * wut * wut;
+          const float ut = newton_utau(a, fabsf(uhat));
+          wsu = uhat > 0.f ? ut : -ut;
+          const float wtw = -rho * wsu * ut;
           Fx += wtw * wex;
           Fz += wtw * wez;
-          const float yp = a.y_wall * wut * a.inv_nu0;
+          const float yp = a.y_wall * ut * a.inv_nu0;
           float up, dup;
           wall_law(a, yp, up, dup);
           wdg = up + yp * dup;  // d(u_tau u+)/du_tau at the root
@@ -300,6 +309,14 @@ __device__ __forceinline__ void node_adjoint(const AdjointArgs& A, AdjLds& L, in
   const float F13 = ux * Fy + uy * Fx, F14 = uy * Fz + uz * Fy, F15 = ux * Fz + uz * Fx;
 
   // ---- reverse: collision ----
+  // The rows of M are orthogonal with M M^T = D, so lambda = M^T D^-1 (M lambda)
+  // and dL/df = lambda + M^T nu = M^T (D^-1 M lambda + nu): D^-1 M lambda is
+  // folded into nu once the cotangents nu_k have been read, and lambda itself
+  // is not kept.
+  if (F16) {
+#pragma unroll
+    for (int i = 0; i < Q; ++i) lam[i] = A.lam_next[erow + (uint32_t)i * ZT];
+  }
   moments(lam, ml);  // (M lambda)_k; delta_k / D_k enters f*, so mu_k = (M lambda)_k / D_k
   float nu[Q];       // dL/dm (moment-space cotangent of the pre-collision populations)
   nu[1] = -a.rs[1] * ml[1];
@@ -309,9 +326,11 @@ __device__ __forceinline__ void node_adjoint(const AdjointArgs& A, AdjLds& L, in
   nu[8] = -a.rs[8] * ml[8];
   nu[10] = -a.rs[10] * ml[10];
   nu[12] = -a.rs[12] * ml[12];
-  nu[16] = -a.rs[16] * ml[16];
-  nu[17] = -a.rs[17] * ml[17];
-  nu[18] = -a.rs[18] * ml[18];
+  // nu_16..18 are not read below: fold at once
+  nu[16] = 0.125f * ml[16] - a.rs[16] * ml[16];
+  nu[17] = 0.125f * ml[17] - a.rs[17] * ml[17];
+  nu[18] = 0.125f * ml[18] - a.rs[18] * ml[18];
+  const float lam0 = ml[0] * (1.f / 19.f), lam3 = 0.1f * ml[3], lam5 = 0.1f * ml[5], lam7 = 0.1f * ml[7];
   const float Fb1 = a.rf[1] * ml[1], Fb2 = a.rf[2] * ml[2], Fb4 = a.rf[4] * ml[4], Fb6 = a.rf[6] * ml[6];
   const float Fb8 = a.rf[8] * ml[8], Fb10 = a.rf[10] * ml[10], Fb12 = a.rf[12] * ml[12];
   const float mu9 = ml[9] * (1.f / 36.f), mu11 = ml[11] * (1.f / 12.f);
@@ -352,15 +371,28 @@ __device__ __forceinline__ void node_adjoint(const AdjointArgs& A, AdjLds& L, in
               uy * nu[14] - ux * nu[15];
   rhob += (19.f * uu + 11.f) * nu[1] - (3.f + 5.5f * uu) * nu[2] - (2.f * uxx - uyy - uzz) * q9b -
           (uyy - uzz) * q11b + ux * uy * nu[13] + uy * uz * nu[14] + ux * uz * nu[15];
+  // last read of nu_1..15: fold D^-1 M lambda
+  nu[1] += (1.f / 2394.f) * ml[1];
+  nu[2] += (1.f / 252.f) * ml[2];
+  nu[4] += (1.f / 40.f) * ml[4];
+  nu[6] += (1.f / 40.f) * ml[6];
+  nu[8] += (1.f / 40.f) * ml[8];
+  nu[10] += (1.f / 72.f) * ml[10];
+  nu[12] += (1.f / 24.f) * ml[12];
+  nu[9] += mu9;
+  nu[11] += mu11;
+  nu[13] += mu13;
+  nu[14] += mu14;
+  nu[15] += mu15;
   // Guo force moments F_k(u, F); the conserved moments 3, 5, 7 gain F itself
   const float uFb = 38.f * Fb1 - 11.f * Fb2;
   const float A9 = Fb9 - 0.5f * Fb10, A11 = Fb11 - 0.5f * Fb12;
   float uxb = uFb * Fx + 4.f * A9 * Fx + Fb13 * Fy + Fb15 * Fz;
   float uyb = uFb * Fy - 2.f * A9 * Fy + 2.f * A11 * Fy + Fb13 * Fx + Fb14 * Fz;
   float uzb = uFb * Fz - 2.f * A9 * Fz - 2.f * A11 * Fz + Fb14 * Fy + Fb15 * Fx;
-  float Fxb = uFb * ux - (2.f / 3.f) * Fb4 + 4.f * A9 * ux + Fb13 * uy + Fb15 * uz + 0.1f * ml[3];
-  float Fyb = uFb * uy - (2.f / 3.f) * Fb6 - 2.f * A9 * uy + 2.f * A11 * uy + Fb13 * ux + Fb14 * uz + 0.1f * ml[5];
-  float Fzb = uFb * uz - (2.f / 3.f) * Fb8 - 2.f * A9 * uz - 2.f * A11 * uz + Fb14 * uy + Fb15 * ux + 0.1f * ml[7];
+  float Fxb = uFb * ux - (2.f / 3.f) * Fb4 + 4.f * A9 * ux + Fb13 * uy + Fb15 * uz + lam3;
+  float Fyb = uFb * uy - (2.f / 3.f) * Fb6 - 2.f * A9 * uy + 2.f * A11 * uy + Fb13 * ux + Fb14 * uz + lam5;
+  float Fzb = uFb * uz - (2.f / 3.f) * Fb8 - 2.f * A9 * uz - 2.f * A11 * uz + Fb14 * uy + Fb15 * ux + lam7;
   // statistics source: d/du of sum_k coef_k (u, v, w, uu, vv, ww, uv, uw, vw)
   if (A.coef) {
     const int p = a.plane_of_x[x];
@@ -389,10 +421,11 @@ __device__ __forceinline__ void node_adjoint(const AdjointArgs& A, AdjLds& L, in
       float exb = 0.f, ezb = 0.f, uhb = 0.f, lb = 0.f;
       if (wact) {  // rho and e_x of the cell itself; u_tau of the line
         const float twb = Fxb * wex + Fzb * wez;
+        const float wtw = -rho * wsu * fabsf(wsu);
         exb = wtw * Fxb;
         ezb = wtw * Fzb;
-        rhob += twb * wtw * iw;
-        lb = twb * 2.f * wtw / wline;  // d tw / d line = 2 tw / line
+        rhob -= twb * wsu * fabsf(wsu);  // d tw / d rho = tw / rho
+        lb = -2.f * twb * rho * fabsf(wsu);  // d tw / d line = 2 tw / line
       }
       if constexpr (PROBE) {
         if (wrow) {  // wave-uniform: the whole wave reduces
@@ -409,7 +442,7 @@ __device__ __forceinline__ void node_adjoint(const AdjointArgs& A, AdjLds& L, in
         uhb = (float)s / (wdg * (float)a.nz);  // d line / d mean = 1 / wdg; d mean / d u_hat = 1 / nz
       }
       if (wbas) {  // u_hat = u_w . e_x of this cell entered the line's mean
-        const float uwx = jx * iw, uwz = jz * iw;
+        const float iw = 1.f / rho;
         exb += uhb * uwx;
         ezb += uhb * uwz;
         const float uwxb = uhb * wex, uwzb = uhb * wez;
@@ -422,11 +455,12 @@ __device__ __forceinline__ void node_adjoint(const AdjointArgs& A, AdjLds& L, in
       }
     } else if (wact) {
       const float twb = Fxb * wex + Fzb * wez;
+      const float ut = fabsf(wsu), wtw = -rho * wsu * ut;
+      const float iw = 1.f / rho;
       float exb = wtw * Fxb, ezb = wtw * Fzb;
-      rhob += twb * wtw * iw;
-      const float utb = twb * 2.f * wtw / wut;
-      const float uhb = wsg * utb / wdg;  // u_tau(|u_hat|): du_tau/d|u_hat| = 1 / wdg
-      const float uwx = jx * iw, uwz = jz * iw;
+      rhob -= twb * wsu * ut;  // d tw / d rho = tw / rho
+      // d tw / du_tau = 2 tw / u_tau; du_tau/d|u_hat| = 1 / wdg; d|u_hat|/du_hat = sign(u_hat)
+      const float uhb = -2.f * twb * rho * ut / wdg;
       exb += uhb * uwx;
       ezb += uhb * uwz;
       const float uwxb = uhb * wex, uwzb = uhb * wez;
@@ -444,18 +478,21 @@ __device__ __forceinline__ void node_adjoint(const AdjointArgs& A, AdjLds& L, in
     __syncthreads();
     if (nrow) {  // this row's pre-force velocity fed the wall row's base vector
       const float gx = L.g2[wslot][0][lane], gz = L.g2[wslot][1][lane];
+      const float iw = 1.f / rho;
       jxb += gx * iw;
       jzb += gz * iw;
-      rhob -= (gx * jx + gz * jz) * iw * iw;
+      rhob -= (gx * uwx + gz * uwz) * iw;
     }
   }
   if constexpr (PROBE) return;
 
-  // ---- dL/d(post-boundary populations) = lambda + M^T nu ----
-  nu[0] = rhob;
-  nu[3] = jxb;
-  nu[5] = jyb;
-  nu[7] = jzb;
+  // ---- dL/d(post-boundary populations) = M^T (D^-1 M lambda + nu) ----
+  nu[0] = lam0 + rhob;
+  nu[3] = lam3 + jxb;
+  nu[5] = lam5 + jyb;
+  nu[7] = lam7 + jzb;
+#pragma unroll
+  for (int i = 0; i < Q; ++i) lam[i] = 0.f;
   add_mt(lam, nu);
   float* gb = lam;
 
@@ -467,13 +504,13 @@ __device__ __forceinline__ void node_adjoint(const AdjointArgs& A, AdjLds& L, in
       const int hidx = (k * a.ny + y) * a.nz + z;
       const float t = gb[i] + A.eta_next[hidx];  // hist_{n+1} holds these populations
       if (mine) A.eta_prev[hidx] = a.out_wh * t;
-      gup[k] = a.out_wu * t;
+      L.gup[k][threadIdx.x] = a.out_wu * t;
       gb[i] = 0.f;
     }
   }
   if (inflow && x == a.nx - 2) {  // values the outlet node read through its upstream term
 #pragma unroll
-    for (int k = 0; k < 5; ++k) gb[OUT5[k]] += gup[k];
+    for (int k = 0; k < 5; ++k) gb[OUT5[k]] += L.gup[k][threadIdx.x];
   }
   const Col cl = make_col<false>(a, z);
   char* lp = reinterpret_cast<char*>(A.lam_prev);
@@ -531,8 +568,10 @@ __device__ __forceinline__ void node_adjoint(const AdjointArgs& A, AdjLds& L, in
 // x = nx-2 of an open channel first, so that their longer work overlaps the
 // rest; -1 pads).  Each block at nx-2 first does the outlet node of its
 // (y, z) (x = nx-1), whose dL/dhist feeds its own c_x < 0 values.
+// With FP16 states the kernel is held to 96 VGPRs (5 waves per SIMD).
 template <bool F16>
-__global__ __launch_bounds__(BLOCK) void adjoint_kernel(AdjointArgs A, const int* __restrict__ blist) {
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(F16 ? 5 : 1)))
+void adjoint_kernel(AdjointArgs A, const int* __restrict__ blist) {
   __shared__ AdjLds L;
   const CollideArgs& a = A.c;
   const int e = blist[blockIdx.x];
@@ -548,13 +587,12 @@ __global__ __launch_bounds__(BLOCK) void adjoint_kernel(AdjointArgs A, const int
   const bool active = zraw < a.nz;
   const int z = active ? zraw : a.nz - 1;  // inactive lanes compute a valid node and store nothing
   const bool own = row_owned(a, y, gy, base);
-  float gup[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
   float csb = 0.f;
   if (open && x0 == a.nx - 2) {  // block-uniform
-    node_adjoint<F16>(A, L, a.nx - 1, y, z, lane, base, zci, own, active, gup, csb);
+    node_adjoint<F16>(A, L, a.nx - 1, y, z, lane, base, zci, own, active, csb);
     __syncthreads();  // LDS reuse by the second node
   }
-  node_adjoint<F16>(A, L, x0, y, z, lane, base, zci, own, active, gup, csb);
+  node_adjoint<F16>(A, L, x0, y, z, lane, base, zci, own, active, csb);
   // dL/dC_s of the block (fixed-order FP64 reduction)
   double c = (double)csb;
 #pragma unroll
@@ -581,9 +619,8 @@ __global__ __launch_bounds__(BLOCK) void adjoint_line_probe_kernel(AdjointArgs A
   const int zraw = zci * ZT + lane;
   const bool active = zraw < a.nz;
   const int z = active ? zraw : a.nz - 1;
-  float gup[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
   float csb = 0.f;
-  node_adjoint<F16, true>(A, L, x, y, z, lane, base, zci, row_owned(a, y, gy, base), active, gup, csb);
+  node_adjoint<F16, true>(A, L, x, y, z, lane, base, zci, row_owned(a, y, gy, base), active, csb);
 }
 
 // grad[n_bins] += the accumulated per-block dL/dC_s (fixed-order tree), and
