@@ -189,14 +189,6 @@ __device__ __forceinline__ void node_adjoint(const AdjointArgs& A, AdjLds& L, in
   typename Pop<F16>::Raw r[Q];
   issue_pulls<F16>(a, g, col, r);
   const uint32_t erow = rowpart(a, x, y) + col.c0;
-  // lambda_{n+1}(X): with FP32 states loaded here, in flight with the pulls;
-  // with FP16 states (more waves per SIMD) before its use, to hold fewer
-  // registers through the forward recompute
-  float lam[Q];
-  if (!F16) {
-#pragma unroll
-    for (int i = 0; i < Q; ++i) lam[i] = A.lam_next[erow + (uint32_t)i * ZT];
-  }
   float f[Q];
   convert_pulls<F16>(a, g, r, f);
 
@@ -313,10 +305,11 @@ __device__ __forceinline__ void node_adjoint(const AdjointArgs& A, AdjLds& L, in
   // and dL/df = lambda + M^T nu = M^T (D^-1 M lambda + nu): D^-1 M lambda is
   // folded into nu once the cotangents nu_k have been read, and lambda itself
   // is not kept.
-  if (F16) {
+  // lambda_{n+1}(X), loaded here rather than with the pulls so that it does
+  // not hold registers through the forward recompute (more waves in flight)
+  float lam[Q];
 #pragma unroll
-    for (int i = 0; i < Q; ++i) lam[i] = A.lam_next[erow + (uint32_t)i * ZT];
-  }
+  for (int i = 0; i < Q; ++i) lam[i] = A.lam_next[erow + (uint32_t)i * ZT];
   moments(lam, ml);  // (M lambda)_k; delta_k / D_k enters f*, so mu_k = (M lambda)_k / D_k
   float nu[Q];       // dL/dm (moment-space cotangent of the pre-collision populations)
   nu[1] = -a.rs[1] * ml[1];
@@ -568,9 +561,10 @@ __device__ __forceinline__ void node_adjoint(const AdjointArgs& A, AdjLds& L, in
 // x = nx-2 of an open channel first, so that their longer work overlaps the
 // rest; -1 pads).  Each block at nx-2 first does the outlet node of its
 // (y, z) (x = nx-1), whose dL/dhist feeds its own c_x < 0 values.
-// With FP16 states the kernel is held to 96 VGPRs (5 waves per SIMD).
+// Held to 96 VGPRs: 5 waves per SIMD instead of 4, at the cost of one spilled
+// VGPR with FP16 states and 11 with FP32 states (measured faster for both).
 template <bool F16>
-__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(F16 ? 5 : 1)))
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(5)))
 void adjoint_kernel(AdjointArgs A, const int* __restrict__ blist) {
   __shared__ AdjLds L;
   const CollideArgs& a = A.c;
