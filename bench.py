@@ -170,6 +170,38 @@ def time_adjoint(device, name="c4", storage="f32", steps=400, segment=20, warmup
     return res
 
 
+def fp16_profile_error(device, name="c3", spin=1000, window=1000):
+    """Error of the FP16 storages in the mean statistics: U(y) and <u'v'>(y) at the four
+    statistics planes over steps spin+1 .. spin+window of the Re_tau = 5200 shape, FP16
+    against FP32 storage from the same initial state (the FP64 oracle cannot run this
+    lattice for thousands of steps; the FP32 path matches it to 1e-5 per step).  U error
+    relative to max U, stress error relative to max |R12| of the synthetic inputs."""
+    import numpy as np
+    import torch
+    from paper_2304_04214_amd import synthetic as S
+    res = {}
+    for storage in ("f32", "f16dev", "f16ref"):
+        ch, _ = make_channel(name, storage, device)
+        ch.step(spin)
+        ch.stats_reset()
+        ch.step(window)
+        res[storage] = ch.stats_read()[0]
+        ch.close()
+        del ch
+        torch.cuda.empty_cache()
+    w = S.WORKLOADS[name]
+    scale = np.abs(S.reynolds_stress(w["ny"], w["u_tau"])[1]).max()
+    b = res["f32"]
+    out = dict(workload="%dx%dx%d, statistics over steps %d-%d at x = delta, 2, 4, 8 delta" % (
+        w["nx"], w["ny"], w["nz"], spin + 1, spin + window), reference="FP32 storage")
+    for k in ("f16dev", "f16ref"):
+        a = res[k]
+        eU = np.abs(a[..., 0] - b[..., 0]).max() / np.abs(b[..., 0]).max()
+        euv = np.abs((a[..., 6] - a[..., 0] * a[..., 1]) - (b[..., 6] - b[..., 0] * b[..., 1])).max() / scale
+        out[k] = {"U_rel_err": float(eU), "uv_err_of_max_R12": float(euv)}
+    return out
+
+
 def copy_bandwidth(device, nbytes=2 << 30, reps=20):
     import torch
     from paper_2304_04214_amd.channel import copy_probe
@@ -254,6 +286,7 @@ def main():
     ap.add_argument("--steps", type=int, default=500)
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-accuracy", action="store_true", help="skip the FP16 mean-profile error leg")
     ap.add_argument("--only", default=None, help="time one (workload:storage), e.g. c2:f32 (profiling)")
     ap.add_argument("--copy-only", action="store_true", help="run the 2 GiB copy kernel only (counter calibration)")
     ap.add_argument("--adj-steps", type=int, default=400, help="steps of the adjoint workload (loss horizon)")
@@ -297,6 +330,10 @@ def main():
     radj = time_adjoint(device, steps=args.adj_steps)
     log("bench: adjoint 512x64x128 FP16")
     radj5 = time_adjoint(device, "c5a", "f16dev", steps=2000, segment=45)
+    acc = None
+    if not args.no_accuracy:
+        log("bench: FP16 storage error in the mean profiles (1536x128x384, 2000 steps each)")
+        acc = fp16_profile_error(device)
     log("bench: copy bandwidth")
     copy_gbs = copy_bandwidth(device)
     cpu = None
@@ -347,6 +384,7 @@ def main():
         "re5200_1536x256x384_f32": {"mlups": round(r5["mlups"], 1), "kernel_gbs": round(r5["kernel_gbs"], 1),
                                     "frac": round(r5["kernel_gbs"] / HBM_PEAK_GBS, 4),
                                     "ms_per_step": round(r5["ms_per_step"], 5), "status": r5["status"]},
+        "fp16_profile_error": acc,
         "adjoint": radj,
         "adjoint_512x64x128_fp16": radj5,
         "cpu_baseline": cpu,

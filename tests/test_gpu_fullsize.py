@@ -143,29 +143,10 @@ def test_fp16_mean_profiles_at_the_re5200_shape():
     whose spurious stress is about 1% of u_tau^2 downstream).  With deviations from the
     equilibrium at the mean inflow profile (lbm_set_reference) both are bounded by 1e-3."""
     import bench
-    res = {}
-    for storage in ("f32", "f16dev", "f16ref"):
-        _say("re5200 shape profiles", storage)
-        ch, (nx, ny, nz) = bench.make_channel("c3", storage, torch.device("cuda"))
-        ch.step(1000)
-        ch.stats_reset()
-        ch.step(1000)
-        means, n = ch.stats_read()
-        assert n == 1000
-        res[storage] = means
-        ch.close()
-        del ch
-        torch.cuda.empty_cache()
-    w = S.WORKLOADS["c3"]
-    scale = np.abs(S.reynolds_stress(w["ny"], w["u_tau"])[1]).max()
-    b = res["f32"]
-    err = {}
+    err = bench.fp16_profile_error(torch.device("cuda"))
     for k in ("f16dev", "f16ref"):
-        a = res[k]
-        eU = np.abs(a[..., 0] - b[..., 0]).max() / np.abs(b[..., 0]).max()
-        euv = np.abs((a[..., 6] - a[..., 0] * a[..., 1]) - (b[..., 6] - b[..., 0] * b[..., 1])).max() / scale
-        err[k] = (eU, euv)
-        _say("  %s vs FP32: U err %.3e, <u'v'> err %.3e (of max|R12|)" % (k, eU, euv))
-    assert err["f16dev"][0] <= 1e-3 and err["f16dev"][1] <= 2e-2
+        _say("  %s vs FP32: U err %.3e, <u'v'> err %.3e (of max|R12|)" % (
+            k, err[k]["U_rel_err"], err[k]["uv_err_of_max_R12"]))
+    assert err["f16dev"]["U_rel_err"] <= 1e-3 and err["f16dev"]["uv_err_of_max_R12"] <= 2e-2
     # deviations from the equilibrium at the mean inflow: both within the target
-    assert err["f16ref"][0] <= 1e-3 and err["f16ref"][1] <= 1e-3
+    assert err["f16ref"]["U_rel_err"] <= 1e-3 and err["f16ref"]["uv_err_of_max_R12"] <= 1e-3
