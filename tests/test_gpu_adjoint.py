@@ -132,6 +132,13 @@ CASES = {
                                                    "f16dev"),
     "f16_slip_inflow_musker_wall_law": (dict(nx=6, ny=8, nz=70, ywall="slip", xbc="inflow", wall_model=True,
                                              wall_law="musker"), "f16dev"),
+    # dispatch list: no bulk columns at all (nx = 3), and many columns of both classes over the
+    # 8 XCDs with padding (ragged nz, 3 y-groups of which 2 hold a wall row)
+    "slip_inflow_wallmodel_nx3": (dict(nx=3, ny=8, nz=20, ywall="slip", xbc="inflow", wall_model=True), "f32"),
+    "bounceback_inflow_wallmodel_23x12x130": (dict(nx=23, ny=12, nz=130, ywall="bounceback", xbc="inflow",
+                                                   wall_model=True), "f32"),
+    "f16_slip_inflow_wallmodel_23x12x130": (dict(nx=23, ny=12, nz=130, ywall="slip", xbc="inflow",
+                                                 wall_model=True), "f16dev"),
 }
 
 
