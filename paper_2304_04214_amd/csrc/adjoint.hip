@@ -301,12 +301,11 @@ __device__ __forceinline__ void node_adjoint(const AdjointArgs& A, AdjLds& L, in
   const float F13 = ux * Fy + uy * Fx, F14 = uy * Fz + uz * Fy, F15 = ux * Fz + uz * Fx;
 
   // ---- reverse: collision ----
-  // The rows of M are orthogonal with M M^T = D, so lambda = M^T D^-1 (M lambda)
-  // and dL/df = lambda + M^T nu = M^T (D^-1 M lambda + nu): D^-1 M lambda is
-  // folded into nu once the cotangents nu_k have been read, and lambda itself
-  // is not kept.
-  // lambda_{n+1}(X), loaded here rather than with the pulls so that it does
-  // not hold registers through the forward recompute (more waves in flight)
+  // lambda_{n+1}(X) is loaded here rather than with the pulls, so that it holds
+  // no registers through the forward recompute, and is not kept past its
+  // moments: the rows of M are orthogonal with M M^T = D, so lambda =
+  // M^T D^-1 (M lambda) and dL/df = lambda + M^T nu = M^T (D^-1 M lambda + nu),
+  // with D^-1 M lambda folded into nu once the cotangents nu_k have been read.
   float lam[Q];
 #pragma unroll
   for (int i = 0; i < Q; ++i) lam[i] = A.lam_next[erow + (uint32_t)i * ZT];
@@ -323,6 +322,7 @@ __device__ __forceinline__ void node_adjoint(const AdjointArgs& A, AdjLds& L, in
   nu[16] = 0.125f * ml[16] - a.rs[16] * ml[16];
   nu[17] = 0.125f * ml[17] - a.rs[17] * ml[17];
   nu[18] = 0.125f * ml[18] - a.rs[18] * ml[18];
+  // (D^-1 M lambda)_k of the conserved moments
   const float lam0 = ml[0] * (1.f / 19.f), lam3 = 0.1f * ml[3], lam5 = 0.1f * ml[5], lam7 = 0.1f * ml[7];
   const float Fb1 = a.rf[1] * ml[1], Fb2 = a.rf[2] * ml[2], Fb4 = a.rf[4] * ml[4], Fb6 = a.rf[6] * ml[6];
   const float Fb8 = a.rf[8] * ml[8], Fb10 = a.rf[10] * ml[10], Fb12 = a.rf[12] * ml[12];
