@@ -327,7 +327,9 @@ lbm_status lbm_set_cs_smag(lbm_handle h, double cs_smag);
  * stg->u_in (and stg->fluct) with the plane at t_next.  Errors: LBM_ERR_ARG (NULL or aliasing
  * buffers), LBM_ERR_SHAPE (alignment, ny > 4096), LBM_ERR_STATE
  * (LBM_X_INFLOW without bound STG inputs, coef without statistics planes).
- * Asynchronous on the handle's stream.
+ * Asynchronous on the handle's stream; the first call allocates the handle's
+ * adjoint scratch (accumulators and the block dispatch order) and copies the
+ * latter to the device synchronously.
  */
 lbm_status lbm_adjoint_step(lbm_handle h, const lbm_stg* stg, const void* s_n, const float* hist_n, double t_next,
                             const float* lam_next, const float* eta_next, float* lam_prev, float* eta_prev,
