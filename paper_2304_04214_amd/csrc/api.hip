@@ -556,11 +556,24 @@ lbm_status lbm_step_record(lbm_handle h, const lbm_stg* stg, const void* s_start
     if (st != LBM_OK) return st;
   }
   if (inflow && !h->stg_bound) return LBM_ERR_STATE;
+  // with every plane kept, the planes of up to STG_BATCH steps come from one launch
+  bool batch = inflow && uin_out && fluct_out;
+  for (int32_t k = 0; batch && k < nsteps; ++k) batch = fluct_out[k] != nullptr;
   for (int32_t k = 0; k < nsteps; ++k) {
     const void* src = k == 0 ? s_start : f_out[k - 1];
     float* uin = uin_out ? uin_out[k] : h->stg.u_in;
     float* fl = fluct_out ? fluct_out[k] : nullptr;
-    if (inflow) HIPCHK(lbm::launch_stg_fill(h, t_start + k + 1, h->stream, fl, uin));
+    if (batch && k % lbm::STG_BATCH == 0) {
+      const int nb = (int)std::min<int64_t>(lbm::STG_BATCH, nsteps - k);
+      lbm::PlaneDst dst{};
+      for (int j = 0; j < nb; ++j) {
+        dst.u[j] = uin_out[k + j];
+        dst.f[j] = fluct_out[k + j];
+      }
+      HIPCHK(lbm::launch_stg_fill_to(h, t_start + k + 1, nb, h->stream, dst));
+    } else if (inflow && !batch) {
+      HIPCHK(lbm::launch_stg_fill(h, t_start + k + 1, h->stream, fl, uin));
+    }
     const float* hsrc = inflow ? (k == 0 ? hist_start : hist_out[k - 1]) : nullptr;
     HIPCHK(lbm::launch_step_explicit(h, src, f_out[k], hsrc, inflow ? hist_out[k] : nullptr, inflow ? uin : nullptr,
                                      h->stream));

@@ -66,6 +66,13 @@ struct AdjointArgs {
   float dsmag;            // d(18 sqrt(2) C_s^2)/dC_s
 };
 
+// Per-step destinations of a batch of inlet planes (u_in and a v' of step j
+// of the batch), passed by value; u[0] == nullptr: not used.
+struct PlaneDst {
+  float* u[STG_BATCH];
+  float* f[STG_BATCH];
+};
+
 struct StgTables {
   int n_modes = 0;
   int cap_trigz = 0, cap_amp3 = 0, cap_ky = 0, cap_chol = 0, cap_sb = 0, cap_urans = 0, cap_rowamp = 0;
@@ -169,5 +176,6 @@ hipError_t launch_stg_fill(lbm_ctx* h, double t, hipStream_t stream, float* fluc
 hipError_t launch_set_time(double* p, double v, hipStream_t stream);
 hipError_t launch_stg_fill_batch(lbm_ctx* h, double time0, int nb, hipStream_t stream, float* ring, float* fring,
                                  int last_j, const double* time_base = nullptr);
+hipError_t launch_stg_fill_to(lbm_ctx* h, double time0, int nb, hipStream_t stream, const PlaneDst& dst);
 hipError_t launch_inflow_reichardt(lbm_ctx* h, double u_tau, double* u_rans);
 }  // namespace lbm

@@ -119,7 +119,7 @@ __global__ __launch_bounds__(256) void stg_spectrum_kernel(lbm_stg s, float* row
 // fring, and the plane of step last_j also to s.u_in / s.fluct.
 __global__ __launch_bounds__(256) void stg_fill_kernel(lbm_stg s, StgTables t, int ny, int nz, double time0,
                                                        int* err, float* ring, float* fring, int last_j,
-                                                       const double* time_base) {
+                                                       const double* time_base, PlaneDst dst) {
   __shared__ float2 rowph[LBM_MAX_MODES];
   __shared__ float amp[3][LBM_MAX_MODES];
   __shared__ float part[3][3][64];
@@ -180,14 +180,21 @@ __global__ __launch_bounds__(256) void stg_fill_kernel(lbm_stg s, StgTables t, i
   const float ux = t.urans[y] + sb * p0;
   const float uy = t.urans[ny + y] + sb * p1;
   const float uz = t.urans[2 * ny + y] + sb * p2;
-  const bool bound = ring == nullptr || j == last_j;
-  if (ring) {
-    float* u = ring + (size_t)j * 3 * pl;
+  float* u = nullptr;
+  float* f = nullptr;
+  if (dst.u[0]) {  // per-step destinations (block-uniform)
+    u = dst.u[j];
+    f = dst.f[j];
+  } else if (ring) {
+    u = ring + (size_t)j * 3 * pl;
+    f = fring ? fring + (size_t)j * 3 * pl : nullptr;
+  }
+  const bool bound = u == nullptr || j == last_j;
+  if (u) {
     u[o] = ux;
     u[pl + o] = uy;
     u[2 * pl + o] = uz;
-    if (fring) {
-      float* f = fring + (size_t)j * 3 * pl;
+    if (f) {
       f[o] = p0;
       f[pl + o] = p1;
       f[2 * pl + o] = p2;
@@ -266,7 +273,8 @@ hipError_t launch_stg_fill(lbm_ctx* h, double time, hipStream_t stream, float* f
   lbm_stg s = h->stg;
   if (fluct) s.fluct = fluct;
   if (u_in) s.u_in = u_in;
-  stg_fill_kernel<<<grid, 256, 0, stream>>>(s, h->tab, ny, nz, time, h->d_err, nullptr, nullptr, -1, nullptr);
+  stg_fill_kernel<<<grid, 256, 0, stream>>>(s, h->tab, ny, nz, time, h->d_err, nullptr, nullptr, -1, nullptr,
+                                            PlaneDst{});
   return hipGetLastError();
 }
 
@@ -277,7 +285,19 @@ hipError_t launch_stg_fill_batch(lbm_ctx* h, double time0, int nb, hipStream_t s
                                  int last_j, const double* time_base) {
   const int ny = h->cfg.ny, nz = h->cfg.nz;
   dim3 grid((nz + 63) / 64, ny, nb);
-  stg_fill_kernel<<<grid, 256, 0, stream>>>(h->stg, h->tab, ny, nz, time0, h->d_err, ring, fring, last_j, time_base);
+  stg_fill_kernel<<<grid, 256, 0, stream>>>(h->stg, h->tab, ny, nz, time0, h->d_err, ring, fring, last_j, time_base,
+                                            PlaneDst{});
+  return hipGetLastError();
+}
+
+// The inlet planes of nb <= STG_BATCH consecutive steps (times time0 ..
+// time0 + nb - 1) in one launch, plane j to dst.u[j] and a v' to dst.f[j]
+// (both non-null for j < nb); the bound outputs are not written.
+hipError_t launch_stg_fill_to(lbm_ctx* h, double time0, int nb, hipStream_t stream, const PlaneDst& dst) {
+  const int ny = h->cfg.ny, nz = h->cfg.nz;
+  dim3 grid((nz + 63) / 64, ny, nb);
+  stg_fill_kernel<<<grid, 256, 0, stream>>>(h->stg, h->tab, ny, nz, time0, h->d_err, nullptr, nullptr, -1, nullptr,
+                                            dst);
   return hipGetLastError();
 }
 
