@@ -361,9 +361,10 @@ lbm_status lbm_sync(lbm_handle h);
 const char* lbm_status_str(lbm_status s);
 
 /* When enabled, every launch of the dominant collide-stream kernel (with
-   LBM_STORE_F32 the single kernel over all nodes, with LBM_STORE_F16DEV the
+   LBM_STORE_F32 the single kernel over all nodes; with LBM_STORE_F16DEV the
    bulk kernel over the nodes away from the inlet, outlet and statistics
-   planes) is bracketed by HIP events on the handle's stream; *total_ms and
+   planes, or on lattices of up to 2^24 nodes the one kernel over all nodes)
+   is bracketed by HIP events on the handle's stream; *total_ms and
    *launches report the summed kernel time since the last reset, and
    *nodes_per_launch the nodes one launch updates (reading synchronises).
    enable = 2 resets. */

@@ -94,11 +94,12 @@ void free_tables(lbm_ctx* h) {
   t = lbm::StgTables();
 }
 
-// The timed collide launch (the bulk kernel with FP16 storage, the single
-// general kernel with FP32 storage), bracketed by events when enabled.
+// The timed collide launch (the bulk kernel with FP16 storage, or the fused
+// kernel on small lattices; the single general kernel with FP32 storage),
+// bracketed by events when enabled.
 hipError_t timed_launch(lbm_ctx* h, int src, int dst, const float* u_in, hipStream_t st) {
   auto launch = [&]() {
-    return h->split ? lbm::launch_bulk(h, src, dst, st)
+    return h->split ? lbm::launch_bulk(h, src, dst, st, u_in)
                     : lbm::launch_boundary(h, src, dst, st, u_in);
   };
   if (!h->timing) return launch();
@@ -185,6 +186,7 @@ lbm_status lbm_create(const lbm_config* cfg, void* f_a, void* f_b, float* hist_a
   h->zc = (cfg->nz + lbm::ZT - 1) / lbm::ZT;
   h->yg = (cfg->ny + lbm::YROWS - 1) / lbm::YROWS;
   h->split = cfg->storage == LBM_STORE_F16DEV;
+  h->fused = h->split && h->N <= lbm::FUSED_MAX_NODES;
   const int64_t nb = (int64_t)cfg->nx * h->yg * h->zc;
   if (nb >= (int64_t(1) << 31)) {
     delete h;
@@ -658,7 +660,7 @@ lbm_status lbm_kernel_timing(lbm_handle h, int32_t enable, double* total_ms, int
   HIPCHK(harvest_timing(h));
   if (total_ms) *total_ms = h->timed_ms;
   if (launches) *launches = h->timed_launches;
-  if (nodes_per_launch) *nodes_per_launch = h->split ? h->int_nodes : h->N;
+  if (nodes_per_launch) *nodes_per_launch = h->split && !h->fused ? h->int_nodes : h->N;
   if (enable == 2) {
     h->timed_ms = 0.0;
     h->timed_launches = 0;

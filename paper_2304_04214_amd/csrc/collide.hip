@@ -538,6 +538,50 @@ __global__ __launch_bounds__(BLOCK) void collide_general_kernel(CollideArgs a, c
   node_update<F16>(a, x, y, z, lane, base, zci, owned, active, col, f, lds_u2);
 }
 
+// FP16 storage on lattices up to FUSED_MAX_NODES: both block lists in one
+// launch, the general blocks (gl, n_gen entries) first so that their longer
+// work overlaps the bulk blocks (bl).  Held to 64 VGPRs (8 waves per SIMD, as
+// the bulk kernel; the general path spills a few).  A separate general launch
+// costs a fixed ~10 us (its blocks run alone as a latency-bound wave), more
+// than the fused kernel's slower bulk path on small lattices, less on large.
+template <bool F16, bool FORCE, bool REF>
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(8)))
+void collide_fused_kernel(CollideArgs a, const int* __restrict__ gl, int n_gen, const int* __restrict__ bl,
+                          const float* __restrict__ dref, const float* __restrict__ dpull) {
+  __shared__ float lds_u2[2][2][ZT];
+  const int b = (int)blockIdx.x;
+  if (b < n_gen) {  // a general block (block-uniform)
+    const int e = gl[b];
+    if (e < 0) return;  // padding of the XCD-ordered list (whole block)
+    int x, zci, gy;
+    block_coords(a, e, x, zci, gy);
+    const int lane = threadIdx.x & (ZT - 1);
+    const int base = min(YROWS * gy, a.ny - YROWS);
+    const int y = base + uni(threadIdx.x >> 6);
+    const bool owned = y >= YROWS * gy;
+    const int zraw = zci * ZT + lane;
+    const bool active = zraw < a.nz;
+    const int z = active ? zraw : a.nz - 1;
+    const Col col = make_col<F16>(a, z);
+    const Geo g = make_geo(a, x, y);
+    typename Pop<F16>::Raw r[Q];
+    issue_pulls<F16>(a, g, col, r);
+    float f[Q];
+    convert_pulls<F16>(a, g, r, f);
+    node_update<F16>(a, x, y, z, lane, base, zci, owned, active, col, f, lds_u2);
+    return;
+  }
+  const int e = bl[b - n_gen];
+  if (e < 0) return;
+  int x, zci, gy;
+  block_coords(a, e, x, zci, gy);
+  const int base = min(YROWS * gy, a.ny - YROWS);
+  if (a.ywall != LBM_Y_PERIODIC && (base == 0 || base == a.ny - YROWS))
+    wall_block<F16, REF>(a, x, zci, gy, lds_u2, dref);
+  else
+    plain_block<F16, FORCE, REF>(a, x, zci, gy, dref, dpull);
+}
+
 // Pre-force velocity (u_x, u_z) of node (x, y, z) after streaming and the
 // boundary rules, as node_update forms it.
 template <bool F16>
@@ -783,6 +827,24 @@ hipError_t launch_wall_line(lbm_ctx* h, CollideArgs& a, hipStream_t stream) {
 void launch_bulk_kernel(lbm_ctx* h, const CollideArgs& a, bool f16, hipStream_t stream) {
   const int n = h->n_int;
   const int* bl = h->d_blist_int;
+  if (h->fused) {
+    const int ng = h->n_bnd, nt = ng + n;
+    const int* gl = h->d_blist_bnd;
+    if (nt == 0) return;
+    if (a.dref) {
+      if (a.has_g)
+        collide_fused_kernel<true, true, true><<<nt, BLOCK, 0, stream>>>(a, gl, ng, bl, a.dref, a.dpull);
+      else
+        collide_fused_kernel<true, false, true><<<nt, BLOCK, 0, stream>>>(a, gl, ng, bl, a.dref, a.dpull);
+    } else {
+      if (a.has_g)
+        collide_fused_kernel<true, true, false><<<nt, BLOCK, 0, stream>>>(a, gl, ng, bl, a.dref, a.dpull);
+      else
+        collide_fused_kernel<true, false, false><<<nt, BLOCK, 0, stream>>>(a, gl, ng, bl, a.dref, a.dpull);
+    }
+    return;
+  }
+  if (n == 0) return;
   if (!f16) {
     if (a.has_g)
       collide_bulk_kernel<false, true, false><<<n, BLOCK, 0, stream>>>(a, bl, a.dref, a.dpull);
@@ -813,13 +875,14 @@ void launch_edge_kernels(lbm_ctx* h, const CollideArgs& a, hipStream_t stream) {
 }
 
 // The step's line u_tau (line-averaged wall model; also when no general block
-// exists, e.g. a periodic channel with FP16 storage) and the general blocks.
+// exists, e.g. a periodic channel with FP16 storage) and the general blocks
+// (unless the fused kernel takes them with the bulk blocks).
 hipError_t launch_boundary(lbm_ctx* h, int src, int dst, hipStream_t stream, const float* u_in) {
   CollideArgs a;
   fill_args(h, a, src, dst);
   if (u_in) a.u_in = u_in;
   hipError_t e = launch_wall_line(h, a, stream);
-  if (e != hipSuccess || h->n_bnd == 0) return e;
+  if (e != hipSuccess || h->n_bnd == 0 || h->fused) return e;
   launch_edge_kernels(h, a, stream);
   return hipGetLastError();
 }
@@ -840,17 +903,19 @@ hipError_t launch_step_explicit(lbm_ctx* h, const void* src, void* dst, const fl
   const bool f16 = h->cfg.storage == LBM_STORE_F16DEV;
   hipError_t e = launch_wall_line(h, a, stream);
   if (e != hipSuccess) return e;
-  launch_edge_kernels(h, a, stream);
-  if (h->n_int > 0) launch_bulk_kernel(h, a, f16, stream);
+  if (!h->fused) launch_edge_kernels(h, a, stream);
+  launch_bulk_kernel(h, a, f16, stream);
   return hipGetLastError();
 }
 
-// The bulk blocks of one step.  With the line-averaged wall model the step's
-// line u_tau must already be in h->d_wall_line on this stream (launch_boundary).
-hipError_t launch_bulk(lbm_ctx* h, int src, int dst, hipStream_t stream) {
-  if (h->n_int == 0) return hipSuccess;
+// The bulk blocks of one step (with the general blocks when fused; u_in, when
+// given, replaces the bound inlet plane).  With the line-averaged wall model
+// the step's line u_tau must already be in h->d_wall_line on this stream
+// (launch_boundary).
+hipError_t launch_bulk(lbm_ctx* h, int src, int dst, hipStream_t stream, const float* u_in) {
   CollideArgs a;
   fill_args(h, a, src, dst);
+  if (u_in) a.u_in = u_in;
   if (h->cfg.wall_avg == LBM_WALL_AVG_LINE && h->cfg.wall_model && h->cfg.ywall != LBM_Y_PERIODIC)
     a.wall_line = h->d_wall_line;
   launch_bulk_kernel(h, a, h->cfg.storage == LBM_STORE_F16DEV, stream);

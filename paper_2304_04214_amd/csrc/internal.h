@@ -20,6 +20,7 @@ constexpr int ZT = 64;     // z-lanes per wave (one wave = one (x, y) row segmen
 constexpr int YROWS = 4;   // rows (waves) per collide block
 constexpr int BLOCK = ZT * YROWS;
 constexpr int STG_BATCH = 32;  // steps whose inlet planes one STG launch computes
+constexpr int64_t FUSED_MAX_NODES = int64_t(1) << 24;  // FP16: one fused collide launch up to this size
 // Largest ny the adjoint supports (its bin reduction stages rows in LDS).
 #define LBM_ADJ_MAX_NY 4096
 
@@ -105,9 +106,11 @@ struct lbm_ctx {
   int n_int = 0, n_bnd = 0, cap_int = 0, cap_bnd = 0;
   int64_t int_nodes = 0;  // nodes updated by one bulk launch
   // FP16 storage: boundary blocks in the general kernel, then the bulk blocks
-  // in a lean kernel.  FP32 storage is HBM-bound with the general kernel
-  // alone: one launch over all blocks.
+  // in a lean kernel; on lattices up to FUSED_MAX_NODES both in one fused
+  // launch.  FP32 storage is HBM-bound with the general kernel alone: one
+  // launch over all blocks.
   bool split = false;
+  bool fused = false;
   double* d_stats = nullptr;
   double* d_wall_acc = nullptr;  // [2][nx][zc], with the wall model
   float* d_wall_line = nullptr;  // [2][nx] line-averaged u_tau of the current step
@@ -149,7 +152,7 @@ namespace lbm {
 // collide.hip
 // u_in, when given, replaces the bound inlet plane.
 hipError_t launch_boundary(lbm_ctx* h, int src, int dst, hipStream_t stream, const float* u_in = nullptr);
-hipError_t launch_bulk(lbm_ctx* h, int src, int dst, hipStream_t stream);
+hipError_t launch_bulk(lbm_ctx* h, int src, int dst, hipStream_t stream, const float* u_in = nullptr);
 hipError_t build_block_lists(lbm_ctx* h, const std::vector<int>& plane_of_x);
 hipError_t launch_stream_only(lbm_ctx* h, int src, int dst);
 hipError_t launch_init(lbm_ctx* h, const float* rho, const float* u, const float* pert, float eps);
