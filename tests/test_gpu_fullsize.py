@@ -10,6 +10,8 @@
   z tile edges, statistics planes) and random interior nodes.
   Tolerances as for the small cases: FP32 1e-5, FP16 deviations 2e-4
   relative L-inf over the sample.
+* The FP16 two-launch path (lattices above 2^24 nodes; smaller ones fuse the general
+  and bulk blocks into one launch) with the line-averaged wall model, 1040 x 128 x 128.
 * Adjoint: one adjoint step on the whole 256 x 64 x 64 lattice (FP32) and the
   whole 512 x 64 x 128 lattice (FP16-deviation state) against the oracle's
   adjoint (tolerances of tests/test_gpu_adjoint.py).
@@ -31,13 +33,15 @@ def _say(*a):
     print(*a, flush=True)
 
 
-def workload(name, storage, full_pert=True):
-    """Oracle and HIP sides of a benchmark workload from the same raw synthetic inputs.
+def workload(name, storage, full_pert=True, shape=None, wall_avg="local"):
+    """Oracle and HIP sides of a benchmark workload from the same raw synthetic inputs
+    (shape: another lattice with the workload's parameters).
     storage "f16ref": FP16 deviations from the equilibrium at the mean inflow profile."""
     w = S.WORKLOADS[name]
-    nx, ny, nz = w["nx"], w["ny"], w["nz"]
+    nx, ny, nz = shape or (w["nx"], w["ny"], w["nz"])
     k = int(name[1])
-    cfg = O.make_cfg(nx, ny, nz, ywall=2, xbc=1, wall_model=1, tau0=w["tau0"], cs_smag=S.CS_SMAG, u_conv=S.U_C)
+    cfg = O.make_cfg(nx, ny, nz, ywall=2, xbc=1, wall_model=1, tau0=w["tau0"], cs_smag=S.CS_SMAG, u_conv=S.U_C,
+                     wall_avg=1 if wall_avg == "line" else 0)
     U = O.reichardt_inflow(cfg, w["u_tau"])
     mt = S.mode_table(w["n_modes"], ny / 2, seed_offset=k)
     R = S.reynolds_stress(ny, w["u_tau"])
@@ -49,7 +53,7 @@ def workload(name, storage, full_pert=True):
     f, hist = O.init(cfg, U[:, None, :, None] + 1e-3 * du, pert=dp, eps=0.05)
     del du, dp
     ch = Channel(nx, ny, nz, tau0=w["tau0"], storage="f16dev" if storage == "f16ref" else storage, ywall="slip",
-                 xbc="inflow", wall_model=True, cs_smag=S.CS_SMAG, u_conv=S.U_C)
+                 xbc="inflow", wall_model=True, cs_smag=S.CS_SMAG, u_conv=S.U_C, wall_avg=wall_avg)
     U_g = ch.inflow_reichardt(w["u_tau"])
     dref = None
     if storage == "f16ref":
@@ -91,6 +95,26 @@ def test_full_size_one_step_sampled(name, storage, tol):
     err = rel_linf(gpu.astype(np.float64), ref)
     _say("  %d sampled nodes, rel Linf %.3e" % (len(nodes), err))
     assert err <= tol
+
+
+@pytest.mark.parametrize("storage", ["f16dev", "f16ref"])
+def test_fp16_two_launch_path_with_line_averaged_wall_model(storage):
+    """FP16 lattices above 2^24 nodes keep the general and bulk launches apart (smaller ones fuse
+    them, so the small parity cases run the fused kernel): one step of 1040 x 128 x 128 (17.0 M
+    nodes, the Re_tau = 5200 workload's parameters) with the line-averaged wall model, sampled
+    nodes against the FP64 oracle, FP16-deviation tolerance 2e-4."""
+    _say("two-launch FP16 path", storage)
+    cfg, stg, f, hist, ch, planes = workload("c3", storage, full_pert=False, shape=(1040, 128, 128),
+                                             wall_avg="line")
+    ch.step(1)
+    ch.sync()
+    nodes = sample_nodes(cfg.nx, cfg.ny, cfg.nz, planes, seed=9)
+    gpu = ch.populations().reshape(19, -1)[:, torch.as_tensor(nodes, device="cuda")].cpu().numpy()
+    st, ref, _ = O.step_nodes(cfg, f, hist, 1.0, nodes, stg=stg)
+    assert st == O.OK
+    err = rel_linf(gpu.astype(np.float64), ref)
+    _say("  %d sampled nodes, rel Linf %.3e" % (len(nodes), err))
+    assert err <= 2e-4
 
 
 @pytest.mark.parametrize("name,storage", [("c4", "f32"), ("c5a", "f16dev")])
