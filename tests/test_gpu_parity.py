@@ -232,6 +232,39 @@ def test_nonfinite_density_is_reported():
     assert e.value.status == A.LBM_ERR_NONFINITE
 
 
+@pytest.mark.parametrize("storage", ["f32", "f16dev"])
+def test_degenerate_calls(storage):
+    """Calls whose result is fixed without the oracle: zero steps change nothing; with every
+    amplitude scaling s_b = 0 the inlet plane is the mean inflow exactly (Eq. (22)); the adjoint
+    of lam = eta = 0 without a statistics source is zero everywhere, gradients included
+    (the step's transpose is linear)."""
+    c = Case(6, 8, 70, ywall="slip", xbc="inflow", wall_model=True, storage=storage)
+    ch = c.ch
+    f0, h0 = [t.clone() for t in ch.state()]
+    t0 = ch.time
+    ch.step(0)
+    f1, h1 = ch.state()
+    assert ch.time == t0 and torch.equal(f0, f1) and torch.equal(h0, h1)
+    ch.set_amp_bin(np.zeros(len(c.ab)))
+    ch.stg_fill(7.0)
+    ch.sync()
+    U = c.U_g.float()[:, :, None].expand(3, c.ny, c.nz)
+    assert torch.equal(ch.u_in, U)
+    ch.set_amp_bin(np.ones(len(c.ab)))
+    lam_n, lam_p = ch.new_field(), ch.new_field()
+    lam_n.zero_()
+    lam_p.fill_(1.0)
+    eta_n = torch.zeros((5, c.ny, c.nz), dtype=torch.float32, device="cuda")
+    eta_p = torch.ones_like(eta_n)
+    g_uin = torch.ones((3, c.ny, c.nz), dtype=torch.float32, device="cuda")
+    grad = torch.zeros(len(c.ab) + 1, dtype=torch.float64, device="cuda")
+    f_cur, h_cur = ch.state()
+    ch.adjoint_step(f_cur, h_cur, t0 + 1.0, lam_n, lam_p, eta_n, eta_p, g_uin=g_uin, grad=grad)
+    ch.sync()
+    assert not ch.field_export(lam_p).any()
+    assert not eta_p.any() and not g_uin.any() and not grad.any()
+
+
 @pytest.mark.parametrize("name", ["slip-inflow-wallmodel", "periodic-smag-force", "slip-inflow-wallmodel-sponge",
                                   "slip-inflow-musker-wall-law", "slip-inflow-line-averaged-utau",
                                   "bounceback-wallmodel", "bounceback-inflow-ny4", "slip-inflow-nz1",
