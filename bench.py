@@ -365,6 +365,9 @@ def main():
                      "frac_of_copy": round(achieved / copy_gbs, 4)},
         "fp16dev": {"mlups": round(r16["mlups"], 1), "ms_per_step": round(r16["ms_per_step"], 5),
                     "kernel_gbs": round(r16["kernel_gbs"], 1), "vs_fp32": round(r16["mlups"] / main_r["mlups"], 3),
+                    "kernel": "collide_fused_kernel<f16dev> (all blocks, one launch per step)",
+                    "bytes_per_node": BYTES_PER_NODE["f16dev"], "frac": round(r16["kernel_gbs"] / HBM_PEAK_GBS, 4),
+                    "traffic": measured_traffic("collide_traffic_re1000_768x64x192.json", "c2:f16dev"),
                     "status": r16["status"]},
         "fp16ref": {"storage": "half deviations from the equilibrium at the mean inflow profile",
                     "mlups": round(r16r["mlups"], 1), "ms_per_step": round(r16r["ms_per_step"], 5),
@@ -376,6 +379,9 @@ def main():
         "re5200_1536x128x384": {"f32_mlups": round(r3["mlups"], 1), "f32_kernel_gbs": round(r3["kernel_gbs"], 1),
                                 "f16dev_mlups": round(r3h["mlups"], 1),
                                 "f16dev_kernel_gbs": round(r3h["kernel_gbs"], 1),
+                                "f16dev_kernel": "collide_bulk_kernel<f16dev> (blocks away from the inlet, outlet "
+                                                 "and statistics planes; their general kernel runs first)",
+                                "f16dev_frac": round(r3h["kernel_gbs"] / HBM_PEAK_GBS, 4),
                                 "f16dev_vs_f32": round(r3h["mlups"] / r3["mlups"], 3),
                                 "f16ref_mlups": round(r3r["mlups"], 1),
                                 "f16ref_kernel_gbs": round(r3r["kernel_gbs"], 1),
