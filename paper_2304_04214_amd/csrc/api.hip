@@ -296,9 +296,10 @@ lbm_status stg_inlet_fill(lbm_handle h, const lbm_stg* stg, double t) {
 // (the handle's state is not advanced).  Everything on one stream: FP32
 // storage one kernel per step; FP16 storage the boundary blocks (with the
 // line-averaged wall model the line kernel first), then the bulk blocks, both
-// reading s_n and writing disjoint nodes of s_{n+1} (running the boundary
-// blocks concurrently on a second stream cost more in cross-stream waits than
-// it hid).  The inlet planes of up to STG_BATCH steps come from one launch
+// reading s_n and writing disjoint nodes of s_{n+1}, as two launches or, on
+// lattices up to FUSED_MAX_NODES, one (running the boundary blocks
+// concurrently on a second stream cost more in cross-stream waits than it
+// hid).  The inlet planes of up to STG_BATCH steps come from one launch
 // into a ring; the plane of the last step also goes to the bound u_in /
 // fluct.  time_base: when non-null the inlet times are *time_base + the
 // offsets (a graph captured once and replayed at any time).

@@ -345,9 +345,10 @@ __device__ __forceinline__ void node_update(const CollideArgs& a, int x, int y, 
 //    keeps few registers and many waves in flight to hide HBM latency;
 //  * boundary blocks (inlet and outlet planes, sampled statistics planes):
 //    the general kernel with every rule of Algorithm 1.
-// With FP32 storage the general kernel takes every block.  All read s_n and
-// write disjoint nodes of s_{n+1}.  Each walks a block list (x, z-chunk,
-// y-group) in memory order.
+// On lattices up to FUSED_MAX_NODES the two lists run as one launch
+// (collide_fused_kernel).  With FP32 storage the general kernel takes every
+// block.  All read s_n and write disjoint nodes of s_{n+1}.  Each walks a
+// block list (columns (x, y-group) dealt to the XCDs by xcd_order).
 
 // A block whose 3 x 3 source rows all lie inside the lattice (see the
 // block lists): plain shifted pulls, no boundary rule.
