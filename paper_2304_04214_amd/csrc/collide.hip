@@ -238,7 +238,8 @@ __device__ __forceinline__ void x_rules(const CollideArgs& a, int x, int y, int 
   if (inflow && x == 0) inlet_regularize(a, y, z, f);
 }
 
-template <bool F16>
+// NT: non-temporal population stores (see CollideArgs::nt_store).
+template <bool F16, bool NT = true>
 __device__ __forceinline__ void node_update(const CollideArgs& a, int x, int y, int z, int lane, int base, int zci,
                                             bool owned, bool active, const Col& col, float f[Q],
                                             float (*lds_u2)[2][ZT]) {
@@ -306,7 +307,8 @@ __device__ __forceinline__ void node_update(const CollideArgs& a, int x, int y, 
   if (active && owned) {
     char* p = const_cast<char*>(row_ptr<F16>(a.dst, rowpart(a, x, y)));
 #pragma unroll
-    for (int i = 0; i < Q; ++i) Pop<F16>::stp(p + i * ZT * Pop<F16>::ES, i, col.b0, f[i], ref_off(a, i, y));
+    for (int i = 0; i < Q; ++i)
+      Pop<F16>::template stp<NT>(p + i * ZT * Pop<F16>::ES, i, col.b0, f[i], ref_off(a, i, y));
   }
 
   if (a.stats_on) {
@@ -402,11 +404,11 @@ __device__ __forceinline__ void plain_block(const CollideArgs& a, int x, int zci
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
       if (F16 && REF)
-        Pop<true>::stp_dev(p + i * ZT * Pop<F16>::ES, col.b0, f[i], dref[y * Q + i]);
+        Pop<true>::stp_dev<true>(p + i * ZT * Pop<F16>::ES, col.b0, f[i], dref[y * Q + i]);
       else if (F16)
-        Pop<true>::stp_dev(p + i * ZT * Pop<F16>::ES, col.b0, f[i]);
+        Pop<true>::stp_dev<true>(p + i * ZT * Pop<F16>::ES, col.b0, f[i]);
       else
-        Pop<F16>::stp(p + i * ZT * Pop<F16>::ES, i, col.b0, f[i], 0.f);
+        Pop<F16>::template stp<true>(p + i * ZT * Pop<F16>::ES, i, col.b0, f[i], 0.f);
     }
   }
 }
@@ -489,11 +491,11 @@ __device__ __forceinline__ void wall_block(const CollideArgs& a, int x, int zci,
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
       if (F16 && REF)
-        Pop<true>::stp_dev(p + i * ZT * Pop<F16>::ES, col.b0, f[i], dref[y * Q + i]);
+        Pop<true>::stp_dev<true>(p + i * ZT * Pop<F16>::ES, col.b0, f[i], dref[y * Q + i]);
       else if (F16)
-        Pop<true>::stp_dev(p + i * ZT * Pop<F16>::ES, col.b0, f[i]);
+        Pop<true>::stp_dev<true>(p + i * ZT * Pop<F16>::ES, col.b0, f[i]);
       else
-        Pop<F16>::stp(p + i * ZT * Pop<F16>::ES, i, col.b0, f[i], 0.f);
+        Pop<F16>::template stp<true>(p + i * ZT * Pop<F16>::ES, i, col.b0, f[i], 0.f);
     }
   }
 }
@@ -516,7 +518,7 @@ __global__ __launch_bounds__(BLOCK) void collide_bulk_kernel(CollideArgs a, cons
     plain_block<F16, FORCE, REF>(a, x, zci, gy, dref, dpull);
 }
 
-template <bool F16>
+template <bool F16, bool NT = true>
 __global__ __launch_bounds__(BLOCK) void collide_general_kernel(CollideArgs a, const int* __restrict__ blist) {
   __shared__ float lds_u2[2][2][ZT];
   const int e = blist[blockIdx.x];
@@ -536,7 +538,7 @@ __global__ __launch_bounds__(BLOCK) void collide_general_kernel(CollideArgs a, c
   issue_pulls<F16>(a, g, col, r);
   float f[Q];
   convert_pulls<F16>(a, g, r, f);
-  node_update<F16>(a, x, y, z, lane, base, zci, owned, active, col, f, lds_u2);
+  node_update<F16, NT>(a, x, y, z, lane, base, zci, owned, active, col, f, lds_u2);
 }
 
 // FP16 storage on lattices up to FUSED_MAX_NODES: both block lists in one
@@ -776,6 +778,12 @@ void fill_args(lbm_ctx* h, CollideArgs& a, int src, int dst) {
   a.wall_law = c.wall_law;
   a.newton_iters = c.newton_iters;
   a.stats_on = h->stats_on && h->d_stats != nullptr;
+  // FP32 population stores bypass the caches (non-temporal) unless both state
+  // buffers fit in the Infinity Cache with room to spare: then the next step
+  // reads the state the last one wrote from there.  (FP16 storage measured
+  // no gain from cached stores: it always stores non-temporally.)
+  a.nt_store = h->cfg.storage == LBM_STORE_F16DEV ||
+               2 * 4 * (int64_t)Q * h->cfg.nx * h->cfg.ny * h->zc * ZT > NT_STORE_MIN_BYTES;
   a.has_g = (c.g[0] != 0.0 || c.g[1] != 0.0 || c.g[2] != 0.0) ? 1 : 0;
   a.tau0 = (float)c.tau0;
   a.tau0sq = (float)(c.tau0 * c.tau0);
@@ -870,8 +878,10 @@ void launch_edge_kernels(lbm_ctx* h, const CollideArgs& a, hipStream_t stream) {
   if (h->n_bnd > 0) {
     if (f16)
       collide_general_kernel<true><<<h->n_bnd, BLOCK, 0, stream>>>(a, h->d_blist_bnd);
+    else if (a.nt_store)
+      collide_general_kernel<false, true><<<h->n_bnd, BLOCK, 0, stream>>>(a, h->d_blist_bnd);
     else
-      collide_general_kernel<false><<<h->n_bnd, BLOCK, 0, stream>>>(a, h->d_blist_bnd);
+      collide_general_kernel<false, false><<<h->n_bnd, BLOCK, 0, stream>>>(a, h->d_blist_bnd);
   }
 }
 

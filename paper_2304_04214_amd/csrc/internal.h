@@ -21,6 +21,10 @@ constexpr int YROWS = 4;   // rows (waves) per collide block
 constexpr int BLOCK = ZT * YROWS;
 constexpr int STG_BATCH = 32;  // steps whose inlet planes one STG launch computes
 constexpr int64_t FUSED_MAX_NODES = int64_t(1) << 24;  // FP16: one fused collide launch up to this size
+// FP32 state buffers together larger than this: non-temporal population
+// stores (the 256 MB Infinity Cache cannot hold the state from one step to
+// the next).
+constexpr int64_t NT_STORE_MIN_BYTES = int64_t(192) << 20;
 // Largest ny the adjoint supports (its bin reduction stages rows in LDS).
 #define LBM_ADJ_MAX_NY 4096
 
@@ -39,6 +43,7 @@ struct CollideArgs {
   const int* plane_of_x;  // [nx], -1 when not sampled
   int* err;
   int nx, ny, nz, zc, yg, nblocks;
+  int nt_store;           // 1: non-temporal population stores (all but small FP32 lattices)
   int ywall, xbc, wall_model, newton_iters, stats_on, has_g, wall_law;
   float tau0, tau0sq, smag;  // smag = 18 sqrt(2) C_s^2
   float g[3];

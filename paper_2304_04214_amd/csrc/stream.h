@@ -10,14 +10,7 @@
 
 #include "internal.h"
 
-// Non-temporal population stores (each value is written once per step and
-// not re-read by the same kernel).
-#ifndef LBM_EXP_F16_NT
-#define LBM_EXP_F16_NT 1
-#endif
-#ifndef LBM_EXP_F32_NT
-#define LBM_EXP_F32_NT 1
-#endif
+#include <type_traits>
 
 namespace lbm {
 
@@ -44,12 +37,13 @@ struct Pop<false> {
   __device__ static __forceinline__ float ldp(const char* p, int, uint32_t off, float) {
     return *reinterpret_cast<const float*>(p + off);
   }
+  // NT: non-temporal store (see CollideArgs::nt_store)
+  template <bool NT>
   __device__ static __forceinline__ void stp(char* p, int, uint32_t off, float v, float) {
-#if LBM_EXP_F32_NT
-    __builtin_nontemporal_store(v, reinterpret_cast<float*>(p + off));  // streamed once, not re-read
-#else
-    *reinterpret_cast<float*>(p + off) = v;
-#endif
+    if constexpr (NT)
+      __builtin_nontemporal_store(v, reinterpret_cast<float*>(p + off));
+    else
+      *reinterpret_cast<float*>(p + off) = v;
   }
   __device__ static __forceinline__ void st_plain(void* base, int, uint32_t e, float v, float) {
     static_cast<float*>(base)[e] = v;
@@ -73,26 +67,25 @@ struct Pop<true> {
     return ((float)WD[i] + ref) + (float)*reinterpret_cast<const _Float16*>(p + off);
   }
   // h_i = f - w_i - r_i rounded to nearest even half
+  template <bool NT>
   __device__ static __forceinline__ void stp(char* p, int i, uint32_t off, float v, float ref) {
-    const uint32_t hb = __builtin_bit_cast(unsigned short, (_Float16)((v - (float)WD[i]) - ref));
-#if LBM_EXP_F16_NT
-    __builtin_nontemporal_store((unsigned short)hb, reinterpret_cast<unsigned short*>(p + off));
-#else
-    *reinterpret_cast<unsigned short*>(p + off) = (unsigned short)hb;
-#endif
+    stp_dev<NT>(p, off, (v - (float)WD[i]) - ref);
   }
   // The deviation from the weights f_i - w_i = h_i + r_i (kernels that compute
   // on deviations).
   __device__ static __forceinline__ float cvt_dev(Raw r) { return (float)__builtin_bit_cast(_Float16, (unsigned short)r); }
   __device__ static __forceinline__ float cvt_dev(Raw r, float ref) { return cvt_dev(r) + ref; }
-  __device__ static __forceinline__ void stp_dev(char* p, uint32_t off, float h, float ref) { stp_dev(p, off, h - ref); }
+  template <bool NT>
+  __device__ static __forceinline__ void stp_dev(char* p, uint32_t off, float h, float ref) {
+    stp_dev<NT>(p, off, h - ref);
+  }
+  template <bool NT>
   __device__ static __forceinline__ void stp_dev(char* p, uint32_t off, float h) {
-    const uint32_t hb = __builtin_bit_cast(unsigned short, (_Float16)h);
-#if LBM_EXP_F16_NT
-    __builtin_nontemporal_store((unsigned short)hb, reinterpret_cast<unsigned short*>(p + off));
-#else
-    *reinterpret_cast<unsigned short*>(p + off) = (unsigned short)hb;
-#endif
+    const unsigned short hb = __builtin_bit_cast(unsigned short, (_Float16)h);
+    if constexpr (NT)
+      __builtin_nontemporal_store(hb, reinterpret_cast<unsigned short*>(p + off));
+    else
+      *reinterpret_cast<unsigned short*>(p + off) = hb;
   }
   __device__ static __forceinline__ void st_plain(void* base, int i, uint32_t e, float v, float ref) {
     static_cast<_Float16*>(base)[e] = (_Float16)((v - (float)WD[i]) - ref);
