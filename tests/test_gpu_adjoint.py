@@ -202,6 +202,39 @@ def test_multistep_statistics_gradient_matches_oracle():
     assert e_amp < TOL_PARAM and e_cs < TOL_PARAM
 
 
+def test_autograd_function_gradient_matches_oracle():
+    """plane_statistics (the torch.autograd.Function over the adjoint sweep): a torch loss of its
+    output back-propagates to the amplitude scalings and C_s; the gradients equal the FP64
+    oracle's adjoint gradient of the same loss (6 steps, checkpoint segments of 4)."""
+    from paper_2304_04214_amd.adjoint import mean_profile_loss, plane_statistics
+    nx, ny, nz, T = 8, 8, 24, 6
+    case = Case(nx, ny, nz, ywall="slip", xbc="inflow", wall_model=True, n_modes=16, seed=4)
+    planes = [3, 6]
+    f0 = storage_round(case.f_or, "f32")
+    h0 = np.asarray(case.hist_or, dtype=np.float32).astype(np.float64)
+    case.ch.load_populations(torch.as_tensor(f0, dtype=torch.float32))
+    case.ch.state()[1].copy_(torch.as_tensor(h0, dtype=torch.float32))
+    U_t = case.U_or[0] * 1.02
+    R12_t = case.R[1]
+    run = StatsGradient(case.ch, planes, T, segment=4)
+    amp = torch.tensor(np.asarray(case.ab, dtype=np.float64), requires_grad=True)
+    cs = torch.tensor(0.1, dtype=torch.float64, requires_grad=True)
+    means = plane_statistics(run, amp, cs)
+    loss = sum(mean_profile_loss(means[p], U_t, R12_t) for p in range(len(planes)))
+    loss.backward()
+    # oracle: the same loss of its own statistics, and its adjoint gradient
+    acc = np.zeros((len(planes), ny, 9))
+    st, _, _ = O.run(case.ocfg, f0, h0, 0.0, T, stg=case.stg_or, planes=planes, acc=acc)
+    assert st == O.OK
+    assert rel_linf(means.detach().numpy(), acc / (nz * T)) < 1e-5
+    dmeans = loss_grad(acc / (nz * T), U_t, R12_t)
+    ref = O.gradient_run(case.ocfg, case.stg_or, f0, h0, 0.0, T, planes, dmeans / (nz * T))
+    e_amp = rel_linf(amp.grad.numpy(), ref["g_amp"])
+    e_cs = abs(float(cs.grad) - ref["g_cs"]) / abs(ref["g_cs"])
+    print("autograd g_amp err %.2e g_cs err %.2e" % (e_amp, e_cs), flush=True)
+    assert e_amp < TOL_PARAM and e_cs < TOL_PARAM
+
+
 def loss_grad(m, U_t, R12_t):
     """dL/dmeans of the mean-profile loss (summed over planes), plain numpy."""
     U, V, UV = m[..., 0], m[..., 1], m[..., 6]
