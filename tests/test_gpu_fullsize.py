@@ -97,6 +97,27 @@ def test_full_size_one_step_sampled(name, storage, tol):
     assert err <= tol
 
 
+def test_full_size_fp32_20_steps():
+    """20 steps of the Re_tau = 1000 workload 768 x 64 x 192 (FP32, the benchmark's setup with
+    its four statistics planes) against 20 steps of the FP64 oracle from the same state: every
+    node within 1e-5 relative L-inf (the FP32 target over 20-step horizons), and the
+    statistics sums."""
+    _say("full size 20 steps c2 f32")
+    cfg, stg, f, hist, ch, planes = workload("c2", "f32")
+    ch.stats_reset()
+    ch.step(20)
+    ch.sync()
+    acc = np.zeros((len(planes), cfg.ny, 9))
+    st, f_ref, _ = O.run(cfg, f, hist, 0.0, 20, stg=stg, planes=planes, acc=acc)
+    assert st == O.OK
+    err = rel_linf(ch.populations().cpu().numpy().astype(np.float64), f_ref)
+    means, n = ch.stats_read()
+    err_s = rel_linf(means, acc / (cfg.nz * 20))
+    _say("  all %d nodes: rel Linf %.3e; statistics %.3e" % (cfg.nx * cfg.ny * cfg.nz, err, err_s))
+    assert n == 20
+    assert err <= 1e-5 and err_s <= 1e-5
+
+
 @pytest.mark.parametrize("storage", ["f16dev", "f16ref"])
 def test_fp16_two_launch_path_with_line_averaged_wall_model(storage):
     """FP16 lattices above 2^24 nodes keep the general and bulk launches apart (smaller ones fuse
