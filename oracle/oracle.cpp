@@ -457,15 +457,20 @@ R uplus(const R& yp, double kappa, double B) {
   using std::log;
   using std::log1p;
   if (g_mutation == 5) return 2.5 * log(1.0 + 0.4 * yp) + 7.8 * (1.0 - exp(-yp / 11.0)) - yp * exp(-yp / 3.0);
+  /* planted misreadings of the buffer-layer term (tests only): 17 the e^(-y+/3)
+     decay read as e^(-y+/2), 18 its y+/11 prefactor read as y+/10 */
+  const double c3 = (g_mutation == 17) ? 2.0 : 3.0, c11 = (g_mutation == 18) ? 10.0 : 11.0;
   /* ln(1 + k y+) and 1 - e^(-y+/11) evaluated as log1p / -expm1: the same
      function, without the cancellation at small y+ */
-  return log1p(kappa * yp) / kappa + B * (-expm1(-yp / 11.0) - (yp / 11.0) * exp(-yp / 3.0));
+  return log1p(kappa * yp) / kappa + B * (-expm1(-yp / 11.0) - (yp / c11) * exp(-yp / c3));
 }
 template <class R>
 R duplus(const R& yp, double kappa, double B) {
   using std::exp;
+  /* the same planted misreadings as uplus, differentiated consistently */
+  const double c3 = (g_mutation == 17) ? 2.0 : 3.0, c11 = (g_mutation == 18) ? 10.0 : 11.0;
   return 1.0 / (1.0 + kappa * yp) +
-         B * (exp(-yp / 11.0) / 11.0 - exp(-yp / 3.0) / 11.0 + (yp / 33.0) * exp(-yp / 3.0));
+         B * (exp(-yp / 11.0) / 11.0 - exp(-yp / c3) / c11 + (yp / (c11 * c3)) * exp(-yp / c3));
 }
 
 /* ---- Sec. II.C with reading R21: Musker's explicit law of the wall ---- */

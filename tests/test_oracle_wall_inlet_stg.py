@@ -28,6 +28,29 @@ def test_reichardt_pin_catches_printed_form(mutation):
     assert O.uplus(1e-4) != pytest.approx(1e-4, rel=1e-2)
 
 
+def test_reichardt_values_match_closed_form():
+    """u+ at y+ = 1, 50, 260 against the closed form of Eq. (16) (reading R6) evaluated by
+    hand (tests/golden/reichardt_uplus.txt, six significant digits)."""
+    rows = np.loadtxt(os.path.join(GOLDEN, "reichardt_uplus.txt"))
+    for yp, up in rows:
+        assert O.uplus(yp) == pytest.approx(up, rel=1e-5), yp
+
+
+@pytest.mark.parametrize("k", [17, 18])
+def test_reichardt_value_pin_catches_buffer_layer_misreadings(mutation, k):
+    """Misreadings of the buffer-layer term, planted in u+ and du+ alike (17: e^(-y+/2) for
+    e^(-y+/3); 18: y+/10 for y+/11), fail the value pin.  Mutation 17 keeps the viscous
+    slope, the log-law limit and the derivative check, so only the value pin sees it."""
+    mutation(k)
+    rows = np.loadtxt(os.path.join(GOLDEN, "reichardt_uplus.txt"))
+    assert any(O.uplus(yp) != pytest.approx(up, rel=1e-5) for yp, up in rows)
+    if k == 17:
+        assert O.duplus(0.0) == pytest.approx(1.0, abs=1e-15)
+        for yp in (0.3, 11.0, 50.0):
+            h = 1e-5 * max(yp, 1.0)
+            assert O.duplus(yp) == pytest.approx((O.uplus(yp + h) - O.uplus(yp - h)) / (2 * h), rel=1e-8)
+
+
 def test_reichardt_log_law_limit():
     """u+ -> ln(y+)/kappa + ln(kappa)/kappa + B for y+ -> infinity."""
     C = np.log(KAPPA) / KAPPA + B
