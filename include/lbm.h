@@ -7,7 +7,8 @@
  *  - Every call returns lbm_status (0 = LBM_OK).  Nothing throws or aborts
  *    across the ABI.  Argument and shape errors are returned synchronously;
  *    errors detected on the device (non-finite or non-positive density, inlet
- *    Mach limit, invalid per-row spectrum inputs of a bound lbm_stg) are
+ *    Mach limit, invalid Reynolds stresses or per-row spectrum inputs of a
+ *    bound lbm_stg) are
  *    latched in a device word and returned by lbm_sync() or
  *    lbm_stats(LBM_STATS_READ).
  *  - Pointers named "device" are HIP device pointers.  Population and
@@ -141,7 +142,9 @@ typedef struct {
  *      phase at inlet node (y, z) and time t is
  *      kmag (d_y (y + 1/2) + d_z z) + omega t + phi.
  *  u_rans[3][ny]  mean inflow;  R[6][ny] Reynolds stresses (R11 R21 R22 R31 R32 R33,
- *      symmetric positive definite); amp_bin[n_bins] amplitude scalings s_b;
+ *      symmetric positive definite: a row that is not, or holds a non-finite
+ *      entry, is reported as LBM_ERR_ARG by the next lbm_sync and takes a zero
+ *      factor, u' = 0); amp_bin[n_bins] amplitude scalings s_b;
  *      bin_of_y[ny] bin of each row.  u' = s_b(y) a(y) v', a = chol(R).
  *  k_rans[ny], omega_rans[ny]   optional (both NULL or both set): RANS
  *      turbulent kinetic energy and specific dissipation rate of each inlet
@@ -227,17 +230,6 @@ lbm_status stg_inlet_fill(lbm_handle h, const lbm_stg* stg, double t);
  * Asynchronous on the handle's stream.
  */
 lbm_status lbm_step(lbm_handle h, const lbm_stg* stg, int32_t nsteps);
-
-/*
- * enable = 1: lbm_step runs whole batches of 32 steps as a replayed HIP graph
- * (captured once per state parity and reused until a call changes a kernel
- * argument: lbm_set_state, a new lbm_stg, lbm_stats ATTACH / DETACH,
- * lbm_set_cs_smag, lbm_set_reference), the rest of a call as plain
- * launches; the results are identical.  It removes the per-launch host cost,
- * which dominates on small lattices.  Not used while lbm_kernel_timing is
- * enabled.  enable = 0 (default): plain launches only.
- */
-lbm_status lbm_set_graphs(lbm_handle h, int32_t enable);
 
 /* Streaming with the wall rules only, current buffer -> other buffer, no
    collision; populations with no source (outside the x range) are set to -1.

@@ -18,7 +18,7 @@ MAX_MODES = 1024
 EXPORTED = [
     "lbm_create", "lbm_destroy", "lbm_set_state", "lbm_get_state", "lbm_init_equilibrium",
     "lbm_inflow_reichardt", "stg_inlet_fill", "lbm_step", "lbm_stream_only", "lbm_export_f32", "lbm_import_f32",
-    "lbm_set_reference", "lbm_set_graphs", "lbm_state_elems",
+    "lbm_set_reference", "lbm_state_elems",
     "lbm_stats", "lbm_sync", "lbm_status_str", "lbm_kernel_timing", "lbm_copy_probe", "lbm_lattice_tables",
     "lbm_set_cs_smag", "lbm_adjoint_step", "lbm_step_record", "lbm_field_export", "lbm_field_import",
 ]
@@ -72,7 +72,6 @@ def lib():
             "lbm_export_f32": [P, P],
             "lbm_import_f32": [P, P],
             "lbm_set_reference": [P, P],
-            "lbm_set_graphs": [P, I32],
             "lbm_state_elems": [P, P],
             "lbm_stats": [P, I32, P, I32, P, P],
             "lbm_sync": [P],

@@ -74,7 +74,7 @@ class StatsGradient:
         (HIP events around each segment's adjoint steps)."""
         ch = self.ch
         ring = self._buffers()
-        ch.stats_detach()
+        ch.stats_detach()  # the sampled planes keep their kernel: the recompute matches the forward run bit for bit
         open_ = ch.cfg.xbc == 1
         # each step adds one z-sum per (plane, y) to the accumulators; means divide by nz T
         coef = torch.as_tensor(np.asarray(dmeans, dtype=np.float64) / (ch.nz * self.T), dtype=torch.float32,

@@ -198,11 +198,6 @@ class Channel:
         A.check(A.lib().lbm_import_f32(self._h, _ptr(f)), "lbm_import_f32")
         self._keep_import = f
 
-    def set_graphs(self, enable=True):
-        """Run whole 32-step batches of step() as replayed HIP graphs (identical results,
-        less host cost per step)."""
-        A.check(A.lib().lbm_set_graphs(self._h, 1 if enable else 0), "lbm_set_graphs")
-
     def set_reference(self, u_ref):
         """FP16 storage: store deviations from the second-order equilibrium at the per-row
         reference velocity u_ref ([3, ny] or the streamwise [ny]; None: the weights).  The

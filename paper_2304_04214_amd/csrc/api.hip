@@ -64,7 +64,6 @@ lbm_status bind_stg(lbm_ctx* h, const lbm_stg* s) {
   h->stg = *s;
   HIPCHK(lbm::launch_stg_bind(h, s));
   h->stg_bound = true;
-  ++h->gen;
   return LBM_OK;
 }
 
@@ -237,10 +236,6 @@ lbm_status lbm_destroy(lbm_handle h) {
   if (h->d_uin_ring) (void)hipFree(h->d_uin_ring);
   if (h->d_fl_ring) (void)hipFree(h->d_fl_ring);
   if (h->d_ablist) (void)hipFree(h->d_ablist);
-  if (h->d_time0) (void)hipFree(h->d_time0);
-  for (int p = 0; p < 2; ++p)
-    if (h->gexec[p]) (void)hipGraphExecDestroy(h->gexec[p]);
-  if (h->cap) (void)hipStreamDestroy(h->cap);
   for (hipEvent_t e : h->ev) (void)hipEventDestroy(e);
   delete h;
   return LBM_OK;
@@ -257,7 +252,6 @@ lbm_status lbm_set_state(lbm_handle h, void* f_a, void* f_b, float* hist_a, floa
   h->hist[1] = hist_b;
   h->cur = 0;
   h->time = time;
-  ++h->gen;
   return LBM_OK;
 }
 
@@ -301,9 +295,8 @@ lbm_status stg_inlet_fill(lbm_handle h, const lbm_stg* stg, double t) {
 // concurrently on a second stream cost more in cross-stream waits than it
 // hid).  The inlet planes of up to STG_BATCH steps come from one launch
 // into a ring; the plane of the last step also goes to the bound u_in /
-// fluct.  time_base: when non-null the inlet times are *time_base + the
-// offsets (a graph captured once and replayed at any time).
-hipError_t enqueue_steps(lbm_ctx* h, int cur, int64_t time, int32_t nsteps, hipStream_t st, const double* time_base) {
+// fluct.
+hipError_t enqueue_steps(lbm_ctx* h, int cur, int64_t time, int32_t nsteps, hipStream_t st) {
   const bool inflow = h->cfg.xbc == LBM_X_INFLOW;
   const size_t plane = (size_t)3 * h->cfg.ny * h->cfg.nz;
   hipError_t e;
@@ -311,9 +304,9 @@ hipError_t enqueue_steps(lbm_ctx* h, int cur, int64_t time, int32_t nsteps, hipS
     const float* ring = inflow ? h->d_uin_ring + plane * (size_t)(n % lbm::STG_BATCH) : nullptr;
     if (inflow && n % lbm::STG_BATCH == 0) {
       const int nb = (int)std::min<int64_t>(lbm::STG_BATCH, nsteps - n);
-      const double t0 = (double)((time_base ? 0 : time) + n + 1);
+      const double t0 = (double)(time + n + 1);
       e = lbm::launch_stg_fill_batch(h, t0, nb, st, h->d_uin_ring, h->stg.fluct ? h->d_fl_ring : nullptr,
-                                     n + nb == nsteps ? nb - 1 : -1, time_base);
+                                     n + nb == nsteps ? nb - 1 : -1);
       if (e != hipSuccess) return e;
     }
     if (h->split && (e = lbm::launch_boundary(h, cur, 1 - cur, st, ring)) != hipSuccess) return e;
@@ -321,48 +314,6 @@ hipError_t enqueue_steps(lbm_ctx* h, int cur, int64_t time, int32_t nsteps, hipS
     cur = 1 - cur;
   }
   return hipSuccess;
-}
-
-// Buffers the captured launches use, allocated before any capture.
-hipError_t prepare_graphs(lbm_ctx* h) {
-  hipError_t e;
-  if (!h->cap && (e = hipStreamCreateWithFlags(&h->cap, hipStreamNonBlocking)) != hipSuccess) return e;
-  if (!h->d_time0 && (e = hipMalloc(&h->d_time0, sizeof(double))) != hipSuccess) return e;
-  const lbm_config& c = h->cfg;
-  if (c.wall_avg == LBM_WALL_AVG_LINE && c.wall_model && c.ywall != LBM_Y_PERIODIC && !h->d_wall_line) {
-    if ((e = hipMalloc(&h->d_wall_line, sizeof(float) * 2 * c.nx)) != hipSuccess) return e;
-    ++h->gen;
-  }
-  return hipSuccess;
-}
-
-// One batch of STG_BATCH steps from the current state as a graph replay: the
-// graph of this state parity is captured (once per argument generation) on
-// the capture stream and launched on the handle's stream after the batch's
-// start time is written to device memory.
-hipError_t replay_batch(lbm_ctx* h) {
-  const int p = h->cur;
-  hipError_t e;
-  if (!h->gexec[p] || h->ggen[p] != h->gen) {
-    if (h->gexec[p]) {
-      if ((e = hipGraphExecDestroy(h->gexec[p])) != hipSuccess) return e;
-      h->gexec[p] = nullptr;
-    }
-    if ((e = hipStreamBeginCapture(h->cap, hipStreamCaptureModeThreadLocal)) != hipSuccess) return e;
-    const hipError_t ee = enqueue_steps(h, p, 0, lbm::STG_BATCH, h->cap, h->d_time0);
-    hipGraph_t g = nullptr;
-    e = hipStreamEndCapture(h->cap, &g);
-    if (ee != hipSuccess) e = ee;
-    if (e == hipSuccess) e = hipGraphInstantiate(&h->gexec[p], g, nullptr, nullptr, 0);
-    if (g) (void)hipGraphDestroy(g);
-    if (e != hipSuccess) {
-      h->gexec[p] = nullptr;
-      return e;
-    }
-    h->ggen[p] = h->gen;
-  }
-  if ((e = lbm::launch_set_time(h->d_time0, (double)h->time, h->stream)) != hipSuccess) return e;
-  return hipGraphLaunch(h->gexec[p], h->stream);
 }
 
 lbm_status lbm_step(lbm_handle h, const lbm_stg* stg, int32_t nsteps) {
@@ -378,38 +329,12 @@ lbm_status lbm_step(lbm_handle h, const lbm_stg* stg, int32_t nsteps) {
   // a ring (the plane of the call's last step also into the bound u_in /
   // fluct); the steps' kernels then read their plane from the ring.
   const size_t plane = (size_t)3 * h->cfg.ny * h->cfg.nz;
-  if (inflow && !h->d_uin_ring) {
-    HIPCHK(hipMalloc(&h->d_uin_ring, sizeof(float) * plane * lbm::STG_BATCH));
-    ++h->gen;
-  }
-  if (inflow && h->stg.fluct && !h->d_fl_ring) {
-    HIPCHK(hipMalloc(&h->d_fl_ring, sizeof(float) * plane * lbm::STG_BATCH));
-    ++h->gen;
-  }
-  int32_t done = 0;
-  if (h->graphs && !h->timing && nsteps >= lbm::STG_BATCH) {
-    // whole batches of STG_BATCH steps as replayed graphs (an even count, so
-    // the state parity is unchanged); the rest as plain launches
-    HIPCHK(prepare_graphs(h));
-    for (; nsteps - done >= lbm::STG_BATCH; done += lbm::STG_BATCH) {
-      HIPCHK(replay_batch(h));
-      h->time += lbm::STG_BATCH;
-      if (h->stats_on) h->n_samples += lbm::STG_BATCH;
-    }
-  }
-  const int32_t rest = nsteps - done;
-  if (rest > 0) {
-    HIPCHK(enqueue_steps(h, h->cur, h->time, rest, h->stream, nullptr));
-    if (rest & 1) h->cur = 1 - h->cur;
-    h->time += rest;
-    if (h->stats_on) h->n_samples += rest;
-  }
-  return LBM_OK;
-}
-
-lbm_status lbm_set_graphs(lbm_handle h, int32_t enable) {
-  if (!h || (enable != 0 && enable != 1)) return LBM_ERR_ARG;
-  h->graphs = enable;
+  if (inflow && !h->d_uin_ring) HIPCHK(hipMalloc(&h->d_uin_ring, sizeof(float) * plane * lbm::STG_BATCH));
+  if (inflow && h->stg.fluct && !h->d_fl_ring) HIPCHK(hipMalloc(&h->d_fl_ring, sizeof(float) * plane * lbm::STG_BATCH));
+  HIPCHK(enqueue_steps(h, h->cur, h->time, nsteps, h->stream));
+  if (nsteps & 1) h->cur = 1 - h->cur;
+  h->time += nsteps;
+  if (h->stats_on) h->n_samples += nsteps;
   return LBM_OK;
 }
 
@@ -436,7 +361,6 @@ lbm_status lbm_import_f32(lbm_handle h, const float* in) {
 lbm_status lbm_set_reference(lbm_handle h, const double* u_ref) {
   if (!h || h->cfg.storage != LBM_STORE_F16DEV) return LBM_ERR_ARG;
   HIPCHK(lbm::launch_set_reference(h, u_ref));
-  ++h->gen;
   return LBM_OK;
 }
 
@@ -470,16 +394,12 @@ lbm_status lbm_stats(lbm_handle h, int32_t op, const int32_t* x_planes, int32_t 
       h->stats_on = 1;
       h->plane_of_x = map;
       HIPCHK(lbm::build_block_lists(h, h->plane_of_x));
-      ++h->gen;
       return LBM_OK;
     }
     case LBM_STATS_DETACH:
-      if (h->stats_on) {
-        h->stats_on = 0;
-        HIPCHK(hipStreamSynchronize(h->stream));
-        HIPCHK(lbm::build_block_lists(h, h->plane_of_x));
-        ++h->gen;
-      }
+      // the planes keep their block routing (general kernel with FP16 storage), so a step's
+      // result does not depend on whether its statistics are accumulated
+      h->stats_on = 0;
       return LBM_OK;
     case LBM_STATS_RESET: {
       if (!h->d_stats) return LBM_ERR_STATE;
@@ -533,7 +453,6 @@ lbm_status lbm_stats(lbm_handle h, int32_t op, const int32_t* x_planes, int32_t 
 lbm_status lbm_set_cs_smag(lbm_handle h, double cs_smag) {
   if (!h || !(cs_smag >= 0.0)) return LBM_ERR_ARG;
   h->cfg.cs_smag = cs_smag;
-  ++h->gen;
   return LBM_OK;
 }
 

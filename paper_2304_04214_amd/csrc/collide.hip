@@ -961,6 +961,10 @@ std::vector<int> xcd_order(const std::vector<int>& entries, int zc, const std::v
 
 // Split the blocks (x, z-chunk, y-group) into bulk and boundary lists,
 // each ordered by xcd_order (see collide_bulk_kernel / collide_general_kernel).
+// The planes of plane_of_x (the attached statistics planes) are boundary
+// blocks whether or not statistics are being accumulated: the two kernels
+// round FP16 deviations differently (the bulk kernel computes on deviations),
+// and a recompute with statistics off must reproduce the forward run.
 hipError_t build_block_lists(lbm_ctx* h, const std::vector<int>& plane_of_x) {
   const lbm_config& c = h->cfg;
   std::vector<int> in, bd;
@@ -970,7 +974,8 @@ hipError_t build_block_lists(lbm_ctx* h, const std::vector<int>& plane_of_x) {
   const bool split = h->split;
   // columns (x, y-group) in memory order, each with its zc z-chunks
   for (int x = 0; x < c.nx; ++x) {
-    const bool xb = (c.xbc == LBM_X_INFLOW && (x == 0 || x == c.nx - 1)) || (h->stats_on && plane_of_x[x] >= 0);
+    // statistics planes (attached, accumulating or not) take the general kernel
+    const bool xb = (c.xbc == LBM_X_INFLOW && (x == 0 || x == c.nx - 1)) || plane_of_x[x] >= 0;
     for (int gy = 0; gy < h->yg; ++gy) {
       const int base = std::min(YROWS * gy, c.ny - YROWS);
       const bool bulk_block = split && !xb;  // wall groups take the bulk kernel's wall branch

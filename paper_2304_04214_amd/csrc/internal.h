@@ -14,7 +14,7 @@ namespace lbm {
 // Bits of the device error word.
 constexpr int ERRBIT_MACH = 1;
 constexpr int ERRBIT_NONFINITE = 2;
-constexpr int ERRBIT_STG_TABLE = 4;  // invalid per-row spectrum inputs (kmag order, k, omega)
+constexpr int ERRBIT_STG_TABLE = 4;  // invalid STG inputs: R not positive definite, per-row spectrum (kmag order, k, omega)
 
 constexpr int ZT = 64;     // z-lanes per wave (one wave = one (x, y) row segment)
 constexpr int YROWS = 4;   // rows (waves) per collide block
@@ -121,14 +121,6 @@ struct lbm_ctx {
   float* d_wall_line = nullptr;  // [2][nx] line-averaged u_tau of the current step
   double* d_line_part = nullptr; // [2][nx][zc] adjoint partial sums of the line model
   float* d_dref = nullptr;       // [ny][19] FP16 storage reference offsets (null: none)
-  // Replayed step graphs (lbm_set_graphs): one per state parity, valid while
-  // gen (bumped by every call that changes a kernel argument) is unchanged.
-  int graphs = 0;
-  uint64_t gen = 1;
-  hipGraphExec_t gexec[2] = {nullptr, nullptr};
-  uint64_t ggen[2] = {0, 0};
-  hipStream_t cap = nullptr;  // capture stream (default priority); graphs run on `stream`
-  double* d_time0 = nullptr;  // start time of a replayed graph
   float* d_dpull = nullptr;      // [ny][19] the same, of the plain pulls' source rows
   int n_planes = 0;
   std::vector<int> plane_of_x;  // host copy of d_plane_of_x
@@ -181,9 +173,8 @@ hipError_t launch_adjoint_reduce(lbm_ctx* h, double* grad);
 // stg.hip
 hipError_t launch_stg_bind(lbm_ctx* h, const lbm_stg* s);
 hipError_t launch_stg_fill(lbm_ctx* h, double t, hipStream_t stream, float* fluct = nullptr, float* u_in = nullptr);
-hipError_t launch_set_time(double* p, double v, hipStream_t stream);
 hipError_t launch_stg_fill_batch(lbm_ctx* h, double time0, int nb, hipStream_t stream, float* ring, float* fring,
-                                 int last_j, const double* time_base = nullptr);
+                                 int last_j);
 hipError_t launch_stg_fill_to(lbm_ctx* h, double time0, int nb, hipStream_t stream, const PlaneDst& dst);
 hipError_t launch_inflow_reichardt(lbm_ctx* h, double u_tau, double* u_rans);
 }  // namespace lbm

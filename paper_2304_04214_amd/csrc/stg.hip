@@ -20,7 +20,7 @@ namespace {
 constexpr double TWO_PI = 6.283185307179586476925286766559;
 constexpr float MACH_LIMIT = 0.17320508075688773f;  // 0.3 c_s, c_s = 1/sqrt(3)
 
-__global__ void stg_bind_kernel(lbm_stg s, StgTables t, int ny, int nz) {
+__global__ void stg_bind_kernel(lbm_stg s, StgTables t, int ny, int nz, int* err) {
   const bool rows = s.k_rans != nullptr;  // per-row spectrum: sqrt(6 q^n(y)) lives in rowamp
   const int N = s.n_modes;
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -44,15 +44,33 @@ __global__ void stg_bind_kernel(lbm_stg s, StgTables t, int ny, int nz) {
   const int64_t k3 = k2 - N;
   if (k3 < ny) {
     const int y = (int)k3;
-    // Eq. (24): lower Cholesky factor of R (FP64), a11 a21 a22 a31 a32 a33
+    // Eq. (24): lower Cholesky factor of R (FP64), a11 a21 a22 a31 a32 a33.
+    // A row whose R is not symmetric positive definite (a pivot R11,
+    // R22 - a21^2 or R33 - a31^2 - a32^2 not positive, or a non-finite entry)
+    // is reported (LBM_ERR_ARG at the next lbm_sync) and gets a zero factor.
     const double R11 = s.R[y], R21 = s.R[ny + y], R22 = s.R[2 * ny + y];
     const double R31 = s.R[3 * ny + y], R32 = s.R[4 * ny + y], R33 = s.R[5 * ny + y];
-    const double a11 = sqrt(R11);
-    const double a21 = R21 / a11;
-    const double a22 = sqrt(R22 - a21 * a21);
-    const double a31 = R31 / a11;
-    const double a32 = (R32 - a21 * a31) / a22;
-    const double a33 = sqrt(R33 - a31 * a31 - a32 * a32);
+    double a11 = 0.0, a21 = 0.0, a22 = 0.0, a31 = 0.0, a32 = 0.0, a33 = 0.0;
+    bool ok = R11 > 0.0 && isfinite(R11) && isfinite(R21) && isfinite(R22) && isfinite(R31) && isfinite(R32) &&
+              isfinite(R33);
+    if (ok) {
+      a11 = sqrt(R11);
+      a21 = R21 / a11;
+      a31 = R31 / a11;
+      const double p22 = R22 - a21 * a21;
+      ok = p22 > 0.0;
+      if (ok) {
+        a22 = sqrt(p22);
+        a32 = (R32 - a21 * a31) / a22;
+        const double p33 = R33 - a31 * a31 - a32 * a32;
+        ok = p33 > 0.0;
+        if (ok) a33 = sqrt(p33);
+      }
+    }
+    if (!ok) {
+      a11 = a21 = a22 = a31 = a32 = a33 = 0.0;
+      atomicOr(err, ERRBIT_STG_TABLE);
+    }
     t.chol[y] = (float)a11;
     t.chol[ny + y] = (float)a21;
     t.chol[2 * ny + y] = (float)a22;
@@ -113,13 +131,12 @@ __global__ __launch_bounds__(256) void stg_spectrum_kernel(lbm_stg s, float* row
 
 // One block per (inlet row y, 64 spanwise nodes, step); its four waves each
 // sum a quarter of the modes, and the partial sums are added in a fixed order.
-// Step j = blockIdx.z has time time0 + j (plus *time_base when given: a
-// replayed graph reads its start time from device memory).  With ring ==
+// Step j = blockIdx.z has time time0 + j.  With ring ==
 // nullptr the plane goes to s.u_in / s.fluct; otherwise to plane j of ring /
 // fring, and the plane of step last_j also to s.u_in / s.fluct.
 __global__ __launch_bounds__(256) void stg_fill_kernel(lbm_stg s, StgTables t, int ny, int nz, double time0,
                                                        int* err, float* ring, float* fring, int last_j,
-                                                       const double* time_base, PlaneDst dst) {
+                                                       PlaneDst dst) {
   __shared__ float2 rowph[LBM_MAX_MODES];
   __shared__ float amp[3][LBM_MAX_MODES];
   __shared__ float part[3][3][64];
@@ -130,7 +147,7 @@ __global__ __launch_bounds__(256) void stg_fill_kernel(lbm_stg s, StgTables t, i
   const int z = zr < nz ? zr : nz - 1;
   const int N = s.n_modes;
   const int j = blockIdx.z;
-  const double time = (time_base ? *time_base : 0.0) + time0 + j;
+  const double time = time0 + j;
   // (y, t)-dependent phase of every mode, FP64 then reduced to [0, 2 pi)
   for (int n = threadIdx.x; n < N; n += 256) {
     const double ph = fmod(t.ky[n] * (y + 0.5) + s.omega[n] * time + s.phi[n], TWO_PI);
@@ -254,7 +271,7 @@ hipError_t launch_stg_bind(lbm_ctx* h, const lbm_stg* s) {
   const int64_t total = (int64_t)N * nz + N + ny;
   const int nb = (int)((total + 255) / 256);
   t.rowamp = nullptr;
-  stg_bind_kernel<<<nb, 256, 0, h->stream>>>(*s, t, ny, nz);
+  stg_bind_kernel<<<nb, 256, 0, h->stream>>>(*s, t, ny, nz, h->d_err);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   if (s->k_rans) {
     if ((e = grow(&t.rowamp_buf, &t.cap_rowamp, ny * N)) != hipSuccess) return e;
@@ -273,8 +290,7 @@ hipError_t launch_stg_fill(lbm_ctx* h, double time, hipStream_t stream, float* f
   lbm_stg s = h->stg;
   if (fluct) s.fluct = fluct;
   if (u_in) s.u_in = u_in;
-  stg_fill_kernel<<<grid, 256, 0, stream>>>(s, h->tab, ny, nz, time, h->d_err, nullptr, nullptr, -1, nullptr,
-                                            PlaneDst{});
+  stg_fill_kernel<<<grid, 256, 0, stream>>>(s, h->tab, ny, nz, time, h->d_err, nullptr, nullptr, -1, PlaneDst{});
   return hipGetLastError();
 }
 
@@ -282,10 +298,10 @@ hipError_t launch_stg_fill(lbm_ctx* h, double time, hipStream_t stream, float* f
 // one launch, into plane j of ring (and fring); the plane of step last_j
 // (-1: none) also goes to the bound u_in / fluct.
 hipError_t launch_stg_fill_batch(lbm_ctx* h, double time0, int nb, hipStream_t stream, float* ring, float* fring,
-                                 int last_j, const double* time_base) {
+                                 int last_j) {
   const int ny = h->cfg.ny, nz = h->cfg.nz;
   dim3 grid((nz + 63) / 64, ny, nb);
-  stg_fill_kernel<<<grid, 256, 0, stream>>>(h->stg, h->tab, ny, nz, time0, h->d_err, ring, fring, last_j, time_base,
+  stg_fill_kernel<<<grid, 256, 0, stream>>>(h->stg, h->tab, ny, nz, time0, h->d_err, ring, fring, last_j,
                                             PlaneDst{});
   return hipGetLastError();
 }
@@ -296,18 +312,7 @@ hipError_t launch_stg_fill_batch(lbm_ctx* h, double time0, int nb, hipStream_t s
 hipError_t launch_stg_fill_to(lbm_ctx* h, double time0, int nb, hipStream_t stream, const PlaneDst& dst) {
   const int ny = h->cfg.ny, nz = h->cfg.nz;
   dim3 grid((nz + 63) / 64, ny, nb);
-  stg_fill_kernel<<<grid, 256, 0, stream>>>(h->stg, h->tab, ny, nz, time0, h->d_err, nullptr, nullptr, -1, nullptr,
-                                            dst);
-  return hipGetLastError();
-}
-
-__global__ void set_time_kernel(double* p, double v) {
-  if (threadIdx.x == 0) *p = v;
-}
-
-// *p = v on the stream (the start time of a replayed step graph).
-hipError_t launch_set_time(double* p, double v, hipStream_t stream) {
-  set_time_kernel<<<1, 64, 0, stream>>>(p, v);
+  stg_fill_kernel<<<grid, 256, 0, stream>>>(h->stg, h->tab, ny, nz, time0, h->d_err, nullptr, nullptr, -1, dst);
   return hipGetLastError();
 }
 

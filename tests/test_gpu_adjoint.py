@@ -248,17 +248,25 @@ def loss_grad(m, U_t, R12_t):
     return d
 
 
-@pytest.mark.parametrize("storage,avg,ref,n,keep", [("f32", "local", False, 3, True), ("f16dev", "local", False, 3, True),
-                                                    ("f32", "line", False, 3, True), ("f16dev", "line", False, 3, True),
-                                                    ("f16dev", "local", True, 3, True),
-                                                    ("f32", "local", False, 35, True), ("f16dev", "local", False, 5, False)])
-def test_step_record_matches_step(storage, avg, ref, n, keep):
+@pytest.mark.parametrize("storage,avg,ref,n,keep,stats", [
+    ("f32", "local", False, 3, True, False), ("f16dev", "local", False, 3, True, False),
+    ("f32", "line", False, 3, True, False), ("f16dev", "line", False, 3, True, False),
+    ("f16dev", "local", True, 3, True, False),
+    ("f32", "local", False, 35, True, False), ("f16dev", "local", False, 5, False, False),
+    ("f16dev", "local", False, 4, True, True), ("f16dev", "local", True, 4, True, True)])
+def test_step_record_matches_step(storage, avg, ref, n, keep, stats):
     """The recompute entry point reproduces lbm_step bit for bit (same kernels,
     caller buffers) and keeps the inlet plane of every step (planes of up to 32
-    steps from one launch: n = 35 spans two; keep=False: planes not kept)."""
+    steps from one launch: n = 35 spans two; keep=False: planes not kept).
+    stats: the forward steps accumulate statistics at two planes while the recompute
+    runs with them detached, as in a gradient sweep (with FP16 storage the sampled
+    planes keep their kernel, whose rounding differs from the bulk kernel's)."""
     case = Case(8, 8, 70, ywall="slip", xbc="inflow", wall_model=True, storage=storage, g=(2e-6, 0.0, 0.0),
                 wall_avg=avg, reference=ref)
     ch = case.ch
+    if stats:
+        ch.stats_attach([2, 5])
+        ch.stats_detach()
     f0, h0 = [t.clone() for t in ch.state()]
     t0 = ch.time
     ring_f = [torch.empty_like(f0) for _ in range(n)]
@@ -266,6 +274,8 @@ def test_step_record_matches_step(storage, avg, ref, n, keep):
     ring_u = [torch.empty((3, 8, 70), dtype=torch.float32, device="cuda") for _ in range(n)] if keep else None
     ring_fl = [torch.empty((3, 8, 70), dtype=torch.float32, device="cuda") for _ in range(n)] if keep else None
     ch.step_record(f0, h0, t0, ring_f, ring_h, ring_u, ring_fl)
+    if stats:
+        ch.stats_attach([2, 5])
     valid = torch.ones_like(f0, dtype=torch.bool)  # bricks (x, zc, y, i, z%64): padding nodes z >= nz are unwritten
     valid[:, -1, :, :, 70 - 64:] = False
     for k in range(n):

@@ -16,12 +16,23 @@ import oracle as O
 from paper_2304_04214_amd import _abi as A
 from paper_2304_04214_amd.channel import Channel
 from parity_cases import Case, rel_linf
+from test_gpu_adjoint import storage_round
 
 pytestmark = [pytest.mark.gpu,
               pytest.mark.skipif(not torch.cuda.is_available(), reason="needs a GPU")]
 
 TOL32 = 1e-5
 TOL16 = 2e-4
+# FP32 error relative to the largest deviation from the weights max |f - w| and to the
+# largest velocity max |u| (density and momentum of the populations): the absolute
+# rounding error of the O(1/3) populations, ~1e-7 after 20 steps, against flows with
+# max |u| down to ~1e-2 (measured 0.8-2.1e-5 of max |f - w|)
+TOL_DEV = 1e-4
+
+
+def macro(cfg, f):
+    """Density and velocity j / rho of populations [19, nx, ny, nz] (oracle's moments, FP64)."""
+    return O.macro(cfg, f)
 
 
 def _say(*a):
@@ -95,8 +106,15 @@ def test_fp32_fields_match_oracle_over_20_steps(name):
     f_g, hist_g = c.gpu_state()
     err = rel_linf(f_g, f_or)
     dev = np.abs(f_g - f_or).max() / np.abs(f_or - O.tables()["w"][:, None, None, None]).max()
-    _say("  rel Linf %.3e   (vs max |f - w|: %.3e)" % (err, dev))
+    rho_g, u_g = macro(c.ocfg, f_g)
+    rho_or, u_or = macro(c.ocfg, f_or)
+    e_rho = rel_linf(rho_g, rho_or)
+    e_u = np.abs(u_g - u_or).max() / np.abs(u_or).max()
+    _say("  rel Linf %.3e   (vs max |f - w|: %.3e; rho %.3e, u vs max |u| %.3e)" % (err, dev, e_rho, e_u))
     assert err <= TOL32
+    # the deviations from the weights carry the flow: FP32 rounding of O(1/3) populations
+    # (absolute ~1e-7 after 20 steps) against max |f - w| and max |u| of the case
+    assert dev <= TOL_DEV and e_rho <= TOL32 and e_u <= TOL_DEV
     if c.xbc == "inflow":
         assert rel_linf(hist_g, hist_or) <= TOL32
 
@@ -206,6 +224,71 @@ def test_invalid_row_spectrum_is_reported():
     with pytest.raises(A.LbmError) as e:
         p.stg_fill(1.0)
     assert e.value.status == A.LBM_ERR_ARG
+
+
+def test_non_spd_reynolds_stress_is_reported():
+    """A Reynolds-stress row that is not positive definite (R22 < R21^2 / R11, so the
+    Cholesky factor of Eq. (24) does not exist): LBM_ERR_ARG at the next sync, and that row
+    takes a zero factor (its inlet velocity is the mean inflow), the other rows are
+    unchanged."""
+    c = Case(4, 6, 8, ywall="slip", xbc="inflow", wall_model=False, n_modes=16)
+    c.ch.stg_fill(3.0)
+    c.ch.sync()
+    good = c.ch.u_in.clone()
+    R = c.R.copy()
+    R[2, 2] = 0.5 * R[1, 2] ** 2 / R[0, 2]  # row 2: R22 - a21^2 < 0
+    c.ch.set_stg(c.mt, c.U_g, R, c.ab, c.boy)
+    c.ch.stg_fill(3.0)
+    with pytest.raises(A.LbmError) as e:
+        c.ch.sync()
+    assert e.value.status == A.LBM_ERR_ARG
+    c.ch.sync()  # cleared once reported
+    U = c.U_g.float()
+    assert torch.equal(c.ch.u_in[:, 2, :], U[:, 2, None].expand(3, c.nz))
+    rows = [y for y in range(c.ny) if y != 2]
+    assert torch.equal(c.ch.u_in[:, rows, :], good[:, rows, :])
+
+
+@pytest.mark.parametrize("storage", ["f32", "f16dev"])
+def test_wall_model_degenerate_branches(storage):
+    """The wall model's degenerate branches (Sec. II.C, Eq. (18)-(21)): a lattice uniform in x
+    and z whose populations are dyadic numbers (every moment exact in FP32 and FP64), at rest
+    except for an x momentum in row 1 (bottom: u_2 tangential, u_w = 0, so u_hat = 0) and in
+    row ny-1 (top: u_w tangential, u_2 = 0, so the base vector e_x of Eq. (18) is undefined).
+    Both give F_w = 0: one step equals the step without the wall model bit for bit, the wall
+    statistics report u_tau = 0 exactly (FP32; with FP16 storage no plane is sampled, so
+    every block takes the bulk kernel, which sums the exactly representable deviations),
+    and the oracle agrees."""
+    nx, ny, nz = 4, 8, 70
+    f = np.full((19, nx, ny, nz), 1.0 / 32.0)
+    f[9] = 1.0 - 18.0 / 32.0  # rho = 1
+    for y in (1, ny - 1):  # c = (-1,0,0) is i = 8, (1,0,0) is i = 10
+        f[10, :, y, :] += 1.0 / 64.0
+        f[8, :, y, :] -= 1.0 / 64.0
+    out = {}
+    for wm in (True, False):
+        ch = Channel(nx, ny, nz, tau0=0.52, storage=storage, ywall="slip", xbc="periodic", wall_model=wm,
+                     cs_smag=0.1)
+        ch.load_populations(torch.as_tensor(f, dtype=torch.float32))
+        stats = wm and storage == "f32"
+        if stats:
+            ch.stats_attach([1])
+        ch.step(1)
+        ch.sync()
+        out[wm] = ch.populations()
+        if stats:
+            wall, n = ch.stats_read_wall()
+            assert n == 1 and not wall.any(), wall
+        ch.close()
+    assert torch.equal(out[True], out[False])
+    cfg = O.make_cfg(nx, ny, nz, ywall=2, xbc=0, wall_model=1, tau0=0.52, cs_smag=0.1)
+    f0 = storage_round(f, storage)
+    wall_acc = np.zeros((2, nx))
+    st, f1, _ = O.step(cfg, f0, None, 1.0, wall_acc=wall_acc)
+    assert st == O.OK and not wall_acc.any()
+    err = rel_linf(out[True].cpu().numpy(), f1)
+    _say("degenerate wall model (%s): rel Linf vs oracle %.3e" % (storage, err))
+    assert err <= (TOL32 if storage == "f32" else TOL16)
 
 
 def test_mach_guard_is_reported():
