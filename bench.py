@@ -315,7 +315,7 @@ def measured_traffic(record, key):
         return None
 
 
-def cpu_baseline(target_s=15.0, slab=8):
+def cpu_baseline(target_s=15.0, slab=64):
     """The FP64 oracle on the host cores, on an x-slab of the Re_tau = 5200 workload."""
     import oracle as O
     from paper_2304_04214_amd import synthetic as S

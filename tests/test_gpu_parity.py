@@ -26,8 +26,9 @@ TOL16 = 2e-4
 # FP32 error relative to the largest deviation from the weights max |f - w| and to the
 # largest velocity max |u| (density and momentum of the populations): the absolute
 # rounding error of the O(1/3) populations, ~1e-7 after 20 steps, against flows with
-# max |u| down to ~1e-2 (measured 0.8-2.1e-5 of max |f - w|)
+# max |u| down to ~1e-2 (measured 0.9-2.8e-5 of max |f - w| and 1.6-4.2e-6 of max |u|)
 TOL_DEV = 1e-4
+TOL_U = 2e-5
 
 
 def macro(cfg, f):
@@ -114,7 +115,7 @@ def test_fp32_fields_match_oracle_over_20_steps(name):
     assert err <= TOL32
     # the deviations from the weights carry the flow: FP32 rounding of O(1/3) populations
     # (absolute ~1e-7 after 20 steps) against max |f - w| and max |u| of the case
-    assert dev <= TOL_DEV and e_rho <= TOL32 and e_u <= TOL_DEV
+    assert dev <= TOL_DEV and e_rho <= TOL32 and e_u <= TOL_U
     if c.xbc == "inflow":
         assert rel_linf(hist_g, hist_or) <= TOL32
 
