@@ -219,6 +219,27 @@ lbm_status lbm_inflow_reichardt(lbm_handle h, double u_tau, double* u_rans);
 lbm_status stg_inlet_fill(lbm_handle h, const lbm_stg* stg, double t);
 
 /*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid it): stg_inlet_fill
+ * without any device allocation or free.  The inputs stg (required) are bound
+ * for this call only, into the library's static device scratch of
+ * LBM_NOALLOC_STG_BYTES per device (held from the first lbm_create on that
+ * device until the process ends), and the plane at time t is written to
+ * stg->u_in (and stg->fluct); the handle's own bound inputs and tables are
+ * neither read nor changed.  The tables need
+ * 8 N nz + 20 N + 40 ny bytes (+ 4 ny N with k_rans / omega_rans), each of the
+ * seven rounded up to 256: LBM_ERR_SHAPE when that exceeds the scratch (e.g.
+ * N = 1024 modes with nz = 512).  Every table is written by the call before it
+ * is read, so nothing must start at zero.  All calls on one device share its
+ * scratch: calls whose work can overlap in time (other streams, other threads)
+ * race and must not be issued; calls ordered on one stream are safe.  Errors as
+ * stg_inlet_fill (LBM_ERR_ARG for invalid inputs; device-detected ones at the
+ * next lbm_sync).  Asynchronous on the handle's stream.
+ */
+#define LBM_NOALLOC_STG_BYTES (4u << 20)
+lbm_status stg_inlet_fill_noalloc(lbm_handle h, const lbm_stg* stg, double t);
+
+/*
  * Advance nsteps time steps (Algorithm 1): for each step n -> n+1 the inlet
  * plane is filled for t = n+1 (when xbc = LBM_X_INFLOW), then one fused
  * pull-stream / boundary / wall-model / MRT-Smagorinsky collision runs over

@@ -17,7 +17,7 @@ MAX_MODES = 1024
 
 EXPORTED = [
     "lbm_create", "lbm_destroy", "lbm_set_state", "lbm_get_state", "lbm_init_equilibrium",
-    "lbm_inflow_reichardt", "stg_inlet_fill", "lbm_step", "lbm_stream_only", "lbm_export_f32", "lbm_import_f32",
+    "lbm_inflow_reichardt", "stg_inlet_fill", "stg_inlet_fill_noalloc", "lbm_step", "lbm_stream_only", "lbm_export_f32", "lbm_import_f32",
     "lbm_set_reference", "lbm_state_elems",
     "lbm_stats", "lbm_sync", "lbm_status_str", "lbm_kernel_timing", "lbm_copy_probe", "lbm_lattice_tables",
     "lbm_set_cs_smag", "lbm_adjoint_step", "lbm_step_record", "lbm_field_export", "lbm_field_import",
@@ -67,6 +67,7 @@ def lib():
             "lbm_init_equilibrium": [P, P, P, P, C.c_float],
             "lbm_inflow_reichardt": [P, D, P],
             "stg_inlet_fill": [P, P, D],
+            "stg_inlet_fill_noalloc": [P, P, D],
             "lbm_step": [P, P, I32],
             "lbm_stream_only": [P],
             "lbm_export_f32": [P, P],

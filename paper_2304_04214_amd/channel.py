@@ -159,6 +159,13 @@ class Channel:
         A.check(A.lib().stg_inlet_fill(self._h, self._stg_arg(), float(t)), "stg_inlet_fill")
         return self.u_in
 
+    def stg_fill_noalloc(self, t):
+        """The inlet plane at time t from the current STG inputs, with their tables in the
+        library's static device scratch (stg_inlet_fill_noalloc: no device allocation; the
+        handle's bound inputs are not changed)."""
+        A.check(A.lib().stg_inlet_fill_noalloc(self._h, C.byref(self._stg), float(t)), "stg_inlet_fill_noalloc")
+        return self.u_in
+
     def step(self, n=1):
         A.check(A.lib().lbm_step(self._h, self._stg_arg(), int(n)), "lbm_step")
 

@@ -173,7 +173,8 @@ lbm_status lbm_create(const lbm_config* cfg, void* f_a, void* f_b, float* hist_a
   h->cfg = *cfg;
   if (h->cfg.newton_iters == 0 && h->cfg.wall_model) h->cfg.newton_iters = 4;
   h->stream = static_cast<hipStream_t>(hip_stream);
-  if (hipGetDevice(&h->device) != hipSuccess) {
+  // the device's address of the static scratch of stg_inlet_fill_noalloc (once per device)
+  if (hipGetDevice(&h->device) != hipSuccess || lbm::noalloc_scratch_setup(h->device) != hipSuccess) {
     delete h;
     return LBM_ERR_HIP;
   }
@@ -283,6 +284,15 @@ lbm_status stg_inlet_fill(lbm_handle h, const lbm_stg* stg, double t) {
   }
   if (!h->stg_bound) return LBM_ERR_STATE;
   HIPCHK(lbm::launch_stg_fill(h, t, h->stream));
+  return LBM_OK;
+}
+
+lbm_status stg_inlet_fill_noalloc(lbm_handle h, const lbm_stg* stg, double t) {
+  if (!h) return LBM_ERR_ARG;
+  lbm_status st = check_stg(h, stg);
+  if (st != LBM_OK) return st;
+  if (lbm::noalloc_stg_bytes(h, stg) > lbm::NOALLOC_STG_BYTES) return LBM_ERR_SHAPE;
+  HIPCHK(lbm::launch_stg_fill_noalloc(h, stg, t));
   return LBM_OK;
 }
 

@@ -25,6 +25,9 @@ constexpr int64_t FUSED_MAX_NODES = int64_t(1) << 24;  // FP16: one fused collid
 // stores (the 256 MB Infinity Cache cannot hold the state from one step to
 // the next).
 constexpr int64_t NT_STORE_MIN_BYTES = int64_t(192) << 20;
+// Static device scratch of stg_inlet_fill_noalloc (per device, for the process
+// lifetime): the STG tables of one call must fit.
+constexpr size_t NOALLOC_STG_BYTES = size_t(4) << 20;
 // Largest ny the adjoint supports (its bin reduction stages rows in LDS).
 #define LBM_ADJ_MAX_NY 4096
 
@@ -177,4 +180,9 @@ hipError_t launch_stg_fill_batch(lbm_ctx* h, double time0, int nb, hipStream_t s
                                  int last_j);
 hipError_t launch_stg_fill_to(lbm_ctx* h, double time0, int nb, hipStream_t stream, const PlaneDst& dst);
 hipError_t launch_inflow_reichardt(lbm_ctx* h, double u_tau, double* u_rans);
+// The static scratch of stg_inlet_fill_noalloc: per-device address lookup (once per
+// device, that device current), the bytes a binding needs, the fill itself.
+hipError_t noalloc_scratch_setup(int device);
+size_t noalloc_stg_bytes(const lbm_ctx* h, const lbm_stg* s);
+hipError_t launch_stg_fill_noalloc(lbm_ctx* h, const lbm_stg* s, double time);
 }  // namespace lbm

@@ -11,8 +11,16 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <mutex>
 
 #include "internal.h"
+
+// Scratch of the allocation-free inlet fill (stg_inlet_fill_noalloc): the STG
+// tables of one call (the inputs' binding, as the handle's tables hold it for
+// stg_inlet_fill).  One copy per device, held until the process ends; every
+// call on a device uses that device's copy.  Host code never uses this name
+// as an address: lbm::noalloc_scratch_setup looks up each device's address.
+static __device__ __align__(256) unsigned char scratch[lbm::NOALLOC_STG_BYTES];
 
 namespace lbm {
 namespace {
@@ -313,6 +321,100 @@ hipError_t launch_stg_fill_to(lbm_ctx* h, double time0, int nb, hipStream_t stre
   const int ny = h->cfg.ny, nz = h->cfg.nz;
   dim3 grid((nz + 63) / 64, ny, nb);
   stg_fill_kernel<<<grid, 256, 0, stream>>>(h->stg, h->tab, ny, nz, time0, h->d_err, nullptr, nullptr, -1, dst);
+  return hipGetLastError();
+}
+
+namespace {
+
+// Device address of `scratch` per device, looked up once (lbm_create, with the
+// device current).
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void* g_scratch[MAX_DEVICES] = {};
+
+size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
+
+// Byte offsets of the tables in the scratch (each 256-byte aligned) and their
+// total: trigz [N][nz] float2, amp3 [3][N] float, ky [N] double, chol [6][ny],
+// sb [ny], urans [3][ny] float, rowamp [ny][N] float with the per-row spectrum.
+struct NoallocLayout {
+  size_t trigz, amp3, ky, chol, sb, urans, rowamp, total;
+};
+NoallocLayout noalloc_layout(int n_modes, int ny, int nz, bool rows) {
+  NoallocLayout L;
+  size_t o = 0;
+  L.trigz = o;
+  o += align256(sizeof(float2) * (size_t)n_modes * nz);
+  L.amp3 = o;
+  o += align256(sizeof(float) * 3 * (size_t)n_modes);
+  L.ky = o;
+  o += align256(sizeof(double) * (size_t)n_modes);
+  L.chol = o;
+  o += align256(sizeof(float) * 6 * (size_t)ny);
+  L.sb = o;
+  o += align256(sizeof(float) * (size_t)ny);
+  L.urans = o;
+  o += align256(sizeof(float) * 3 * (size_t)ny);
+  L.rowamp = o;
+  if (rows) o += align256(sizeof(float) * (size_t)ny * n_modes);
+  L.total = o;
+  return L;
+}
+
+}  // namespace
+
+hipError_t noalloc_scratch_setup(int device) {
+  if (device < 0 || device >= MAX_DEVICES) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch[device]) return hipSuccess;
+  void* p = nullptr;
+  hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  if (e != hipSuccess) return e;
+  if (!p) return hipErrorInvalidSymbol;
+  g_scratch[device] = p;
+  return hipSuccess;
+}
+
+size_t noalloc_stg_bytes(const lbm_ctx* h, const lbm_stg* s) {
+  return noalloc_layout(s->n_modes, h->cfg.ny, h->cfg.nz, s->k_rans != nullptr).total;
+}
+
+// stg_inlet_fill with the inputs bound into the device's scratch instead of the
+// handle's tables: the same bind, spectrum and fill kernels, no allocation.
+// The caller has checked noalloc_stg_bytes <= NOALLOC_STG_BYTES.
+hipError_t launch_stg_fill_noalloc(lbm_ctx* h, const lbm_stg* s, double time) {
+  if (h->device < 0 || h->device >= MAX_DEVICES) return hipErrorInvalidDevice;
+  char* base;
+  {
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    base = static_cast<char*>(g_scratch[h->device]);
+  }
+  if (!base) return hipErrorInvalidSymbol;
+  const int N = s->n_modes, ny = h->cfg.ny, nz = h->cfg.nz;
+  const bool rows = s->k_rans != nullptr;
+  const NoallocLayout L = noalloc_layout(N, ny, nz, rows);
+  if (L.total > NOALLOC_STG_BYTES) return hipErrorInvalidValue;
+  StgTables t;
+  t.n_modes = N;
+  t.trigz = reinterpret_cast<float2*>(base + L.trigz);
+  t.amp3 = reinterpret_cast<float*>(base + L.amp3);
+  t.ky = reinterpret_cast<double*>(base + L.ky);
+  t.chol = reinterpret_cast<float*>(base + L.chol);
+  t.sb = reinterpret_cast<float*>(base + L.sb);
+  t.urans = reinterpret_cast<float*>(base + L.urans);
+  t.rowamp = nullptr;
+  const int64_t total = (int64_t)N * nz + N + ny;
+  stg_bind_kernel<<<(int)((total + 255) / 256), 256, 0, h->stream>>>(*s, t, ny, nz, h->d_err);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  if (rows) {
+    float* rowamp = reinterpret_cast<float*>(base + L.rowamp);
+    stg_spectrum_kernel<<<ny, 256, 0, h->stream>>>(*s, rowamp, ny, (h->cfg.tau0 - 0.5) / 3.0, h->d_err);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    t.rowamp = rowamp;
+  }
+  dim3 grid((nz + 63) / 64, ny);
+  stg_fill_kernel<<<grid, 256, 0, h->stream>>>(*s, t, ny, nz, time, h->d_err, nullptr, nullptr, -1, PlaneDst{});
   return hipGetLastError();
 }
 
