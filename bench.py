@@ -13,7 +13,7 @@ and deviations from the weights), the Re_tau = 1000 shape 768 x 64 x 192 in
 every storage and with the outlet sponge, the 1536 x 256 x 384 lattice in FP32
 over its 5000 steps, and the discrete adjoint on 256 x 64 x 64 (gradient of a
 mean-profile loss over 400 steps, checkpoints every 20) and 512 x 64 x 128
-(FP16 states, 2000 steps).  Every leg is timed REPEATS times (windows of
+(FP16 states in both storages, 2000 steps).  Every leg is timed REPEATS times (windows of
 --steps steps); the line reports the median with the min and max.
 
 Prints ONE JSON line.
@@ -214,6 +214,39 @@ def time_adjoint(device, name="c4", storage="f32", steps=400, segment=20, warmup
     return res
 
 
+def fp16_gradient_error(device, name="c5a", steps=2000, segment=45):
+    """Error of the FP16-state gradients of the large adjoint workload (512 x 64 x 128,
+    mean-profile loss at x = 128 over 2000 steps, checkpoints every 45): each FP16 storage
+    against the FP32-state gradient from the same seeded initial state."""
+    import torch
+    from paper_2304_04214_amd.adjoint import StatsGradient, mean_profile_loss
+    from paper_2304_04214_amd import synthetic as S
+    res = {}
+    for storage in ("f32", "f16ref", "f16dev"):
+        ch, (nx, ny, nz) = make_channel(name, storage, device, planes=[2 * S.WORKLOADS[name]["ny"]], seed=5)
+        x_obs = 2 * ny
+        run = StatsGradient(ch, [x_obs], steps, segment=segment)
+        means = run.forward()
+        U_t = torch.as_tensor(ch._stg_tensors["u_rans"][0].cpu())
+        R12_t = torch.as_tensor(S.reynolds_stress(ny, S.WORKLOADS[name]["u_tau"])[1])
+        m = torch.tensor(means, dtype=torch.float64, requires_grad=True)
+        loss = mean_profile_loss(m[0], U_t, R12_t)
+        loss.backward()
+        res[storage] = (float(loss.detach()), run.backward(m.grad.numpy()))
+        ch.close()
+        del ch, run
+        torch.cuda.empty_cache()
+    L32, g32 = res["f32"]
+    out = dict(workload="512x64x128, loss at x=128 over %d steps, checkpoint every %d" % (steps, segment),
+               reference="FP32-state gradient from the same initial state")
+    for k in ("f16ref", "f16dev"):
+        L, g = res[k]
+        out[k] = dict(grad_rel_linf=float(np.abs(g - g32).max() / np.abs(g32).max()),
+                      amp_rel_linf=float(np.abs(g[:-1] - g32[:-1]).max() / np.abs(g32[:-1]).max()),
+                      cs_rel=float(abs(g[-1] - g32[-1]) / abs(g32[-1])), loss_rel=abs(L - L32) / abs(L32))
+    return out
+
+
 def fp16_oracle_profile_error(device):
     """Mean-profile error of every storage against the FP64 oracle at the workloads' tau0:
     the 256 x 64 x 64 channel (Re_tau = 1000 parameters, tau0 = 0.500427), means over z
@@ -384,8 +417,9 @@ def main():
     if args.only == "adjoint":
         print(json.dumps(time_adjoint(device, steps=args.adj_steps, repeats=rep)), flush=True)
         return
-    if args.only == "adjoint-large":
-        print(json.dumps(time_adjoint(device, "c5a", "f16dev", steps=2000, segment=45, repeats=rep)), flush=True)
+    if args.only in ("adjoint-large", "adjoint-large-dev"):
+        storage = "f16dev" if args.only.endswith("-dev") else "f16ref"
+        print(json.dumps(time_adjoint(device, "c5a", storage, steps=2000, segment=45, repeats=rep)), flush=True)
         return
     if args.only == "accuracy":
         print(json.dumps(fp16_oracle_profile_error(device)), flush=True)
@@ -409,10 +443,13 @@ def main():
     r5 = time_channel("c5", "f32", C5_STEPS // rep, max(3, args.warmup // 4), device, repeats=rep)
     log("bench: adjoint 256x64x64")
     radj = time_adjoint(device, steps=args.adj_steps, repeats=rep)
-    log("bench: adjoint 512x64x128 FP16")
-    radj5 = time_adjoint(device, "c5a", "f16dev", steps=2000, segment=45, repeats=rep)
-    acc_or = acc3 = None
+    log("bench: adjoint 512x64x128 FP16 (both FP16 storages)")
+    radj5 = time_adjoint(device, "c5a", "f16ref", steps=2000, segment=45, repeats=rep)
+    radj5d = time_adjoint(device, "c5a", "f16dev", steps=2000, segment=45, repeats=rep)
+    acc_or = acc3 = gerr = None
     if not args.no_accuracy:
+        log("bench: FP16-state gradients against the FP32-state gradient (512x64x128, 2000 steps)")
+        gerr = fp16_gradient_error(device)
         log("bench: mean-profile error against the FP64 oracle (256x64x64, 2000 steps per storage)")
         acc_or = fp16_oracle_profile_error(device)
         log("bench: FP16 mean-profile error against FP32 (1536x128x384, 2000 steps per storage)")
@@ -476,7 +513,10 @@ def main():
         "re5200_1536x256x384_f32": {"steps": C5_STEPS, **brief(r5),
                                     "traffic": measured_traffic("collide_traffic_re5200_1536x256x384.json", "c5:f32")},
         "adjoint": radj,
-        "adjoint_512x64x128_fp16": radj5,
+        "adjoint_512x64x128_fp16": {**radj5, "storage": "half deviations from the mean-inflow equilibrium",
+                                    "gradient_error_vs_fp32_state": None if gerr is None else gerr.get("f16ref")},
+        "adjoint_512x64x128_fp16dev": {**radj5d, "storage": "half deviations from the weights",
+                                       "gradient_error_vs_fp32_state": None if gerr is None else gerr.get("f16dev")},
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

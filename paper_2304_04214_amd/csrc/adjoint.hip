@@ -179,9 +179,14 @@ struct AdjLds {
 //
 // PROBE (line-averaged model only): stop after the wall force and store the
 // wave's sum of dL/d(line u_tau) of the wall rows in A.line_part.
-template <bool F16, bool PROBE = false>
+// REF (FP16 storage relative to a reference profile): dref / dpull are the
+// reference offsets of the stored rows and of the plain pulls' source rows,
+// passed as restrict kernel arguments so that their scalar loads are not
+// ordered after stores (the values of a.dref / a.dpull).
+template <bool F16, bool REF, bool PROBE = false>
 __device__ __forceinline__ void node_adjoint(const AdjointArgs& A, AdjLds& L, int x, int y, int z, int lane,
-                                             int base, int zci, bool own, bool active, float& csb) {
+                                             int base, int zci, bool own, bool active, float& csb,
+                                             const float* __restrict__ dref, const float* __restrict__ dpull) {
   const CollideArgs& a = A.c;
   const bool mine = own && active;
   const Col col = make_col<F16>(a, z);
@@ -190,7 +195,19 @@ __device__ __forceinline__ void node_adjoint(const AdjointArgs& A, AdjLds& L, in
   issue_pulls<F16>(a, g, col, r);
   const uint32_t erow = rowpart(a, x, y) + col.c0;
   float f[Q];
-  convert_pulls<F16>(a, g, r, f);
+  if (!F16 || !REF) {
+    convert_pulls<F16>(a, g, r, f);
+  } else if (interior(g)) {  // wave-uniform: plain pulls, offsets of the source rows y - c_y
+#pragma unroll
+    for (int i = 0; i < Q; ++i) f[i] = Pop<F16>::cvt(i, r[i], dpull[y * Q + i]);
+  } else {
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+      int plane, ysrc;
+      pull_plane_row(a, g, i, plane, ysrc);
+      f[i] = pull_ok(a, g, i) ? Pop<F16>::cvt(i, r[i], dref[ysrc * Q + plane]) : 0.f;
+    }
+  }
 
   // ---- forward recompute: boundary rules ----
   const bool inflow = a.xbc == LBM_X_INFLOW;
@@ -563,9 +580,10 @@ __device__ __forceinline__ void node_adjoint(const AdjointArgs& A, AdjLds& L, in
 // (y, z) (x = nx-1), whose dL/dhist feeds its own c_x < 0 values.
 // Held to 96 VGPRs: 5 waves per SIMD instead of 4, at the cost of one spilled
 // VGPR with FP16 states and 11 with FP32 states (measured faster for both).
-template <bool F16>
+template <bool F16, bool REF>
 __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(5)))
-void adjoint_kernel(AdjointArgs A, const int* __restrict__ blist) {
+void adjoint_kernel(AdjointArgs A, const int* __restrict__ blist, const float* __restrict__ dref,
+                    const float* __restrict__ dpull) {
   __shared__ AdjLds L;
   const CollideArgs& a = A.c;
   const int e = blist[blockIdx.x];
@@ -583,10 +601,10 @@ void adjoint_kernel(AdjointArgs A, const int* __restrict__ blist) {
   const bool own = row_owned(a, y, gy, base);
   float csb = 0.f;
   if (open && x0 == a.nx - 2) {  // block-uniform
-    node_adjoint<F16>(A, L, a.nx - 1, y, z, lane, base, zci, own, active, csb);
+    node_adjoint<F16, REF>(A, L, a.nx - 1, y, z, lane, base, zci, own, active, csb, dref, dpull);
     __syncthreads();  // LDS reuse by the second node
   }
-  node_adjoint<F16>(A, L, x0, y, z, lane, base, zci, own, active, csb);
+  node_adjoint<F16, REF>(A, L, x0, y, z, lane, base, zci, own, active, csb, dref, dpull);
   // dL/dC_s of the block (fixed-order FP64 reduction)
   double c = (double)csb;
 #pragma unroll
@@ -599,8 +617,9 @@ void adjoint_kernel(AdjointArgs A, const int* __restrict__ blist) {
 // Line-averaged wall model: the wall blocks (y-groups 0 and yg-1 of every
 // (x, z-chunk)) store dL/d(line u_tau) per wall-line chunk; every chunk of
 // every line is written, so the main launch reads no stale sums.
-template <bool F16>
-__global__ __launch_bounds__(BLOCK) void adjoint_line_probe_kernel(AdjointArgs A) {
+template <bool F16, bool REF>
+__global__ __launch_bounds__(BLOCK) void adjoint_line_probe_kernel(AdjointArgs A, const float* __restrict__ dref,
+                                                                  const float* __restrict__ dpull) {
   __shared__ AdjLds L;
   const CollideArgs& a = A.c;
   const int ng = a.yg > 1 ? 2 : 1;
@@ -614,7 +633,8 @@ __global__ __launch_bounds__(BLOCK) void adjoint_line_probe_kernel(AdjointArgs A
   const bool active = zraw < a.nz;
   const int z = active ? zraw : a.nz - 1;
   float csb = 0.f;
-  node_adjoint<F16, true>(A, L, x, y, z, lane, base, zci, row_owned(a, y, gy, base), active, csb);
+  node_adjoint<F16, REF, true>(A, L, x, y, z, lane, base, zci, row_owned(a, y, gy, base), active, csb, dref,
+                               dpull);
 }
 
 // grad[n_bins] += the accumulated per-block dL/dC_s (fixed-order tree), and
@@ -715,17 +735,21 @@ hipError_t launch_adjoint(lbm_ctx* h, const AdjointArgs& args, int storage_f16, 
       return e;
     A.line_part = h->d_line_part;
     const int nprobe = c.nx * h->zc * (h->yg > 1 ? 2 : 1);
-    if (storage_f16)
-      adjoint_line_probe_kernel<true><<<nprobe, BLOCK, 0, h->stream>>>(A);
+    if (storage_f16 && A.c.dref)
+      adjoint_line_probe_kernel<true, true><<<nprobe, BLOCK, 0, h->stream>>>(A, A.c.dref, A.c.dpull);
+    else if (storage_f16)
+      adjoint_line_probe_kernel<true, false><<<nprobe, BLOCK, 0, h->stream>>>(A, nullptr, nullptr);
     else
-      adjoint_line_probe_kernel<false><<<nprobe, BLOCK, 0, h->stream>>>(A);
+      adjoint_line_probe_kernel<false, false><<<nprobe, BLOCK, 0, h->stream>>>(A, nullptr, nullptr);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
   if ((e = adjoint_list(h)) != hipSuccess) return e;
-  if (storage_f16)
-    adjoint_kernel<true><<<h->n_ablist, BLOCK, 0, h->stream>>>(A, h->d_ablist);
+  if (storage_f16 && A.c.dref)
+    adjoint_kernel<true, true><<<h->n_ablist, BLOCK, 0, h->stream>>>(A, h->d_ablist, A.c.dref, A.c.dpull);
+  else if (storage_f16)
+    adjoint_kernel<true, false><<<h->n_ablist, BLOCK, 0, h->stream>>>(A, h->d_ablist, nullptr, nullptr);
   else
-    adjoint_kernel<false><<<h->n_ablist, BLOCK, 0, h->stream>>>(A, h->d_ablist);
+    adjoint_kernel<false, false><<<h->n_ablist, BLOCK, 0, h->stream>>>(A, h->d_ablist, nullptr, nullptr);
   return hipGetLastError();
 }
 
