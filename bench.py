@@ -192,8 +192,10 @@ def time_adjoint(device, name="c4", storage="f32", steps=400, segment=20, warmup
     fwd_ms = statistics.median(fwd)
     bpn = ADJ_BYTES_PER_NODE if storage == "f32" else ADJ_BYTES_PER_NODE - 38  # s_n in half deviations
     achieved = bpn * N / (adj_ms * 1e-3) / 1e9
+    label = {"f32": "FP32", "f16dev": "FP16 storage, deviations from the weights",
+             "f16ref": "FP16 storage, deviations from the mean-inflow equilibrium"}[storage]
     res = dict(workload="%dx%dx%d channel (%s), loss at x=%d over %d steps, checkpoint every %d" % (
-        nx, ny, nz, "FP32" if storage == "f32" else "FP16-deviation storage", x_obs, steps, segment),
+        nx, ny, nz, label, x_obs, steps, segment),
         nodes=N, repeats=repeats, forward_ms_per_step=round(fwd_ms, 5),
         forward_kernel_ms=round(statistics.median(fwd_k), 5), adjoint_step_ms=round(adj_ms, 5),
         adjoint_step_ms_min=round(min(adj), 5), adjoint_step_ms_max=round(max(adj), 5),
