@@ -127,6 +127,8 @@ CASES = {
                                           reference=True), "f16dev"),
     "f16ref_bounceback_periodic_force": (dict(nx=5, ny=9, nz=66, ywall="bounceback", xbc="periodic",
                                               wall_model=True, g=(4e-6, 0.0, 0.0), reference=True), "f16dev"),
+    "f16ref_slip_inflow_line_averaged_utau": (dict(nx=6, ny=8, nz=70, ywall="slip", xbc="inflow", wall_model=True,
+                                                   wall_avg="line", reference=True), "f16dev"),
     "f16_bounceback_periodic_line_averaged_utau": (dict(nx=5, ny=9, nz=66, ywall="bounceback", xbc="periodic",
                                                         wall_model=True, g=(4e-6, 0.0, 0.0), wall_avg="line"),
                                                    "f16dev"),

@@ -139,7 +139,7 @@ def test_fp16_two_launch_path_with_line_averaged_wall_model(storage):
     assert err <= 2e-4
 
 
-@pytest.mark.parametrize("name,storage", [("c4", "f32"), ("c5a", "f16dev")])
+@pytest.mark.parametrize("name,storage", [("c4", "f32"), ("c5a", "f16dev"), ("c5a", "f16ref")])
 def test_full_size_adjoint_step(name, storage):
     _say("full size adjoint", name, storage)
     cfg, stg, f, hist, ch, _ = workload(name, storage)
