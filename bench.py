@@ -14,7 +14,8 @@ every storage and with the outlet sponge, the 1536 x 256 x 384 lattice in FP32
 over its 5000 steps, and the discrete adjoint on 256 x 64 x 64 (gradient of a
 mean-profile loss over 400 steps, checkpoints every 20) and 512 x 64 x 128
 (FP16 states in both storages, 2000 steps).  Every leg is timed REPEATS times (windows of
---steps steps); the line reports the median with the min and max.
+--steps steps; at least 200 on the 768 x 64 x 192 lattice, whose steps take 0.14-0.25 ms); the
+line reports the median with the min and max.
 
 Prints ONE JSON line.
 """
@@ -35,6 +36,7 @@ HBM_PEAK_GBS = 8000.0
 BYTES_PER_NODE = {"f32": 152, "f16dev": 76, "f16ref": 76}  # 19 populations read + 19 written
 REPEATS = 5
 C5_STEPS = 5000  # the 151 M-node workload's horizon (REPEATS windows of C5_STEPS / REPEATS steps)
+C2_MIN_STEPS = 200  # shortest timed window on the 768 x 64 x 192 lattice
 SPONGE_NU = 0.1  # viscosity at the outlet plane of the 1-delta sponge (the paper gives no value)
 PROFILES_FILE = os.path.join(ROOT, "tests", "golden", "c4_profiles.txt")
 
@@ -437,10 +439,13 @@ def main():
     r3r = time_channel("c3", "f16ref", args.steps, args.warmup, device, repeats=rep)
     r3h = time_channel("c3", "f16dev", args.steps, args.warmup, device, repeats=rep)
     log("bench: c2 f32 / f16ref / f16dev / f32 with the outlet sponge")
-    r2 = time_channel("c2", "f32", args.steps, args.warmup, device, repeats=rep)
-    r2r = time_channel("c2", "f16ref", args.steps, args.warmup, device, repeats=rep)
-    r2h = time_channel("c2", "f16dev", args.steps, args.warmup, device, repeats=rep)
-    rsp = time_channel("c2", "f32", args.steps, args.warmup, device, sponge=True, repeats=rep)
+    # the 9.4 M-node lattice's steps take 0.14-0.25 ms: windows of at least C2_MIN_STEPS steps, so
+    # that each window is tens of milliseconds of back-to-back launches
+    c2_steps, c2_warm = max(args.steps, C2_MIN_STEPS), max(args.warmup, 50)
+    r2 = time_channel("c2", "f32", c2_steps, c2_warm, device, repeats=rep)
+    r2r = time_channel("c2", "f16ref", c2_steps, c2_warm, device, repeats=rep)
+    r2h = time_channel("c2", "f16dev", c2_steps, c2_warm, device, repeats=rep)
+    rsp = time_channel("c2", "f32", c2_steps, c2_warm, device, sponge=True, repeats=rep)
     log("bench: c5 f32 1536x256x384, %d steps (the workload's horizon, FP64 statistics on)" % C5_STEPS)
     r5 = time_channel("c5", "f32", C5_STEPS // rep, max(3, args.warmup // 4), device, repeats=rep)
     log("bench: adjoint 256x64x64")
@@ -503,7 +508,8 @@ def main():
                     "error_vs_fp32_1536x128x384": None if acc3 is None else acc3.get("f16dev")},
         "fp32_error_vs_oracle": None if acc_or is None else acc_or.get("f32"),
         "profile_error_setup": None if acc_or is None else {k: acc_or[k] for k in ("workload", "reference")},
-        "re1000_768x64x192": {"f32": {**brief(r2), "bytes_per_node": 152},
+        "re1000_768x64x192": {"steps_per_window": c2_steps,
+                              "f32": {**brief(r2), "bytes_per_node": 152},
                               "f16ref": {**brief(r2r), "vs_fp32": round(r2r["mlups"] / r2["mlups"], 3),
                                          "kernel": "collide_fused_kernel<f16, reference> (all blocks, one launch)"},
                               "f16dev": {**brief(r2h), "vs_fp32": round(r2h["mlups"] / r2["mlups"], 3),
