@@ -92,6 +92,7 @@ def time_channel(name, storage, steps, warmup, device, sponge=False, repeats=REP
     import torch
     ch, (nx, ny, nz) = make_channel(name, storage, device, sponge=sponge)
     N = nx * ny * nz
+    n_disp, disp_planes = ch.collide_dispatches()
     ch.step(warmup)
     ch.sync()
     ch.stats_reset()
@@ -120,7 +121,8 @@ def time_channel(name, storage, steps, warmup, device, sponge=False, repeats=REP
                mlups_max=N / (w["min"] * 1e-3) / 1e6,
                step_frac=bpn * N / (w["median"] * 1e-3) / 1e9 / HBM_PEAK_GBS,
                kernel_ms=k["median"], kernel_ms_min=k["min"], kernel_ms_max=k["max"], kernel_nodes=k_nodes,
-               kernel_gbs=bpn * k_nodes / (k["median"] * 1e-3) / 1e9, status=status)
+               kernel_gbs=bpn * k_nodes / (k["median"] * 1e-3) / 1e9, status=status,
+               dispatches_per_step=n_disp if storage == "f32" else 1, planes_per_dispatch=disp_planes)
     res["kernel_frac"] = res["kernel_gbs"] / HBM_PEAK_GBS
     ch.close()
     del ch
@@ -129,7 +131,7 @@ def time_channel(name, storage, steps, warmup, device, sponge=False, repeats=REP
 
 
 def brief(r, keys=("mlups", "mlups_min", "mlups_max", "ms_per_step", "kernel_ms", "kernel_gbs", "kernel_frac",
-                   "step_frac", "status")):
+                   "step_frac", "dispatches_per_step", "status")):
     return {k: (round(r[k], 5) if isinstance(r[k], float) else r[k]) for k in keys}
 
 
@@ -490,7 +492,9 @@ def main():
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": measured_traffic("collide_traffic_re5200_1536x128x384.json", "c3:f32"),
-                     "kernel": "collide_general_kernel<f32> (all blocks)", "kernel_ms": round(r3["kernel_ms"], 5),
+                     "kernel": "collide_general_kernel<f32> (all blocks; a launch is one step's %d dispatches "
+                               "over x-ranges of %d planes)" % (r3["dispatches_per_step"], r3["planes_per_dispatch"]),
+                     "dispatches_per_launch": r3["dispatches_per_step"], "kernel_ms": round(r3["kernel_ms"], 5),
                      "kernel_ms_min": round(r3["kernel_ms_min"], 5), "kernel_ms_max": round(r3["kernel_ms_max"], 5),
                      "kernel_nodes": r3["kernel_nodes"], "bytes_per_node": BYTES_PER_NODE["f32"],
                      "step_frac": round(r3["step_frac"], 4), "copy_kernel_gbs": round(copy_gbs, 1),

@@ -374,15 +374,25 @@ lbm_status lbm_sync(lbm_handle h);
 const char* lbm_status_str(lbm_status s);
 
 /* When enabled, every launch of the dominant collide-stream kernel (with
-   LBM_STORE_F32 the single kernel over all nodes; with LBM_STORE_F16DEV the
-   bulk kernel over the nodes away from the inlet, outlet and statistics
-   planes, or on lattices of up to 2^24 nodes the one kernel over all nodes)
-   is bracketed by HIP events on the handle's stream; *total_ms and
-   *launches report the summed kernel time since the last reset, and
-   *nodes_per_launch the nodes one launch updates (reading synchronises).
-   enable = 2 resets. */
+   LBM_STORE_F32 the general kernel over all nodes, one launch being the
+   step's dispatches over its x-chunks (lbm_collide_dispatches); with
+   LBM_STORE_F16DEV the bulk kernel over the nodes away from the inlet, outlet
+   and statistics planes, or on lattices of up to 2^24 nodes the one kernel
+   over all nodes) is bracketed by HIP events on the handle's stream;
+   *total_ms and *launches report the summed kernel time since the last
+   reset, and *nodes_per_launch the nodes one launch updates (reading
+   synchronises).  enable = 2 resets. */
 lbm_status lbm_kernel_timing(lbm_handle h, int32_t enable, double* total_ms, int64_t* launches,
                              int64_t* nodes_per_launch);
+
+/* Shape of one step's general-kernel dispatches (host only, no device work).
+   With LBM_STORE_F32 the step goes out as one dispatch per range of
+   *planes x-planes (the last range may be shorter), the ranges holding about
+   30000 blocks of 256 nodes each, so *dispatches = ceil(nx / *planes); with
+   LBM_STORE_F16DEV the general blocks, if any, are one dispatch
+   (*dispatches = 1, or 0 without such blocks; *planes = nx).  Either pointer
+   may be NULL. */
+lbm_status lbm_collide_dispatches(lbm_handle h, int32_t* dispatches, int32_t* planes);
 
 /* Plain device copy kernel (bandwidth calibration): dst[0:bytes) = src[0:bytes),
    bytes a multiple of 16, both 16-byte aligned. */

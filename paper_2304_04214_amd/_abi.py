@@ -19,7 +19,7 @@ EXPORTED = [
     "lbm_create", "lbm_destroy", "lbm_set_state", "lbm_get_state", "lbm_init_equilibrium",
     "lbm_inflow_reichardt", "stg_inlet_fill", "stg_inlet_fill_noalloc", "lbm_step", "lbm_stream_only", "lbm_export_f32", "lbm_import_f32",
     "lbm_set_reference", "lbm_state_elems",
-    "lbm_stats", "lbm_sync", "lbm_status_str", "lbm_kernel_timing", "lbm_copy_probe", "lbm_lattice_tables",
+    "lbm_stats", "lbm_sync", "lbm_status_str", "lbm_kernel_timing", "lbm_collide_dispatches", "lbm_copy_probe", "lbm_lattice_tables",
     "lbm_set_cs_smag", "lbm_adjoint_step", "lbm_step_record", "lbm_field_export", "lbm_field_import",
 ]
 
@@ -77,6 +77,7 @@ def lib():
             "lbm_stats": [P, I32, P, I32, P, P],
             "lbm_sync": [P],
             "lbm_kernel_timing": [P, I32, P, P, P],
+            "lbm_collide_dispatches": [P, P, P],
             "lbm_copy_probe": [P, P, I64, P],
             "lbm_set_cs_smag": [P, D],
             "lbm_adjoint_step": [P, P, P, P, D, P, P, P, P, P, P, P, P, P],

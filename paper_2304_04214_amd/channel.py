@@ -313,6 +313,13 @@ class Channel:
                 "lbm_kernel_timing")
         return ms.value, n.value, nodes.value
 
+    def collide_dispatches(self):
+        """(dispatches per step, x-planes per dispatch) of the general collide kernel."""
+        d = C.c_int32()
+        p = C.c_int32()
+        A.check(A.lib().lbm_collide_dispatches(self._h, C.byref(d), C.byref(p)), "lbm_collide_dispatches")
+        return d.value, p.value
+
 
 def copy_probe(src, dst):
     """Plain device copy kernel of the library (bandwidth calibration)."""

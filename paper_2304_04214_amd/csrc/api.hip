@@ -94,8 +94,8 @@ void free_tables(lbm_ctx* h) {
 }
 
 // The timed collide launch (the bulk kernel with FP16 storage, or the fused
-// kernel on small lattices; the single general kernel with FP32 storage),
-// bracketed by events when enabled.
+// kernel on small lattices; with FP32 storage the general kernel's dispatches
+// over the step's x-chunks), bracketed by events when enabled.
 hipError_t timed_launch(lbm_ctx* h, int src, int dst, const float* u_in, hipStream_t st) {
   auto launch = [&]() {
     return h->split ? lbm::launch_bulk(h, src, dst, st, u_in)
@@ -298,12 +298,12 @@ lbm_status stg_inlet_fill_noalloc(lbm_handle h, const lbm_stg* stg, double t) {
 
 // nsteps steps from state parity cur at time index `time`, enqueued on st
 // (the handle's state is not advanced).  Everything on one stream: FP32
-// storage one kernel per step; FP16 storage the boundary blocks (with the
-// line-averaged wall model the line kernel first), then the bulk blocks, both
-// reading s_n and writing disjoint nodes of s_{n+1}, as two launches or, on
-// lattices up to FUSED_MAX_NODES, one (running the boundary blocks
-// concurrently on a second stream cost more in cross-stream waits than it
-// hid).  The inlet planes of up to STG_BATCH steps come from one launch
+// storage the general kernel, one dispatch per x-chunk; FP16 storage the
+// boundary blocks (with the line-averaged wall model the line kernel first),
+// then the bulk blocks, both reading s_n and writing disjoint nodes of
+// s_{n+1}, as two launches or, on lattices up to FUSED_MAX_NODES, one
+// (running the boundary blocks concurrently on a second stream cost more in
+// cross-stream waits than it hid).  The inlet planes of up to STG_BATCH steps come from one launch
 // into a ring; the plane of the last step also goes to the bound u_in /
 // fluct.
 hipError_t enqueue_steps(lbm_ctx* h, int cur, int64_t time, int32_t nsteps, hipStream_t st) {
@@ -598,6 +598,13 @@ lbm_status lbm_kernel_timing(lbm_handle h, int32_t enable, double* total_ms, int
   } else {
     h->timing = enable ? 1 : 0;
   }
+  return LBM_OK;
+}
+
+lbm_status lbm_collide_dispatches(lbm_handle h, int32_t* dispatches, int32_t* planes) {
+  if (!h) return LBM_ERR_ARG;
+  if (dispatches) *dispatches = (int32_t)h->bnd_off.size() - 1;
+  if (planes) *planes = h->chunk_planes;
   return LBM_OK;
 }
 

@@ -872,16 +872,20 @@ void launch_bulk_kernel(lbm_ctx* h, const CollideArgs& a, bool f16, hipStream_t 
   }
 }
 
-// The general blocks of one step.
+// The general blocks of one step: one dispatch per x-chunk of the list (the
+// chunks update disjoint nodes from s_n, so their order is free).
 void launch_edge_kernels(lbm_ctx* h, const CollideArgs& a, hipStream_t stream) {
   const bool f16 = h->cfg.storage == LBM_STORE_F16DEV;
-  if (h->n_bnd > 0) {
+  for (size_t k = 0; k + 1 < h->bnd_off.size(); ++k) {
+    const int n = h->bnd_off[k + 1] - h->bnd_off[k];
+    const int* bl = h->d_blist_bnd + h->bnd_off[k];
+    if (n <= 0) continue;
     if (f16)
-      collide_general_kernel<true><<<h->n_bnd, BLOCK, 0, stream>>>(a, h->d_blist_bnd);
+      collide_general_kernel<true><<<n, BLOCK, 0, stream>>>(a, bl);
     else if (a.nt_store)
-      collide_general_kernel<false, true><<<h->n_bnd, BLOCK, 0, stream>>>(a, h->d_blist_bnd);
+      collide_general_kernel<false, true><<<n, BLOCK, 0, stream>>>(a, bl);
     else
-      collide_general_kernel<false, false><<<h->n_bnd, BLOCK, 0, stream>>>(a, h->d_blist_bnd);
+      collide_general_kernel<false, false><<<n, BLOCK, 0, stream>>>(a, bl);
   }
 }
 
@@ -965,6 +969,9 @@ std::vector<int> xcd_order(const std::vector<int>& entries, int zc, const std::v
 // blocks whether or not statistics are being accumulated: the two kernels
 // round FP16 deviations differently (the bulk kernel computes on deviations),
 // and a recompute with statistics off must reproduce the forward run.
+// With FP32 storage the boundary list (all blocks) is cut into x-chunks of
+// about CHUNK_BLOCKS blocks, each ordered by xcd_order on its own, since
+// every chunk is a dispatch of its own.
 hipError_t build_block_lists(lbm_ctx* h, const std::vector<int>& plane_of_x) {
   const lbm_config& c = h->cfg;
   std::vector<int> in, bd;
@@ -992,7 +999,26 @@ hipError_t build_block_lists(lbm_ctx* h, const std::vector<int>& plane_of_x) {
     }
   }
   in = xcd_order(in, h->zc, &in_heavy);
-  bd = xcd_order(bd, h->zc);
+  // bd is in memory order (x-major), so an x-range is a contiguous run of it
+  int nchunk = 1;
+  if (!split) nchunk = (int)std::max<int64_t>(1, std::llround((double)h->nblocks / CHUNK_BLOCKS));
+  const int planes = (c.nx + std::min(nchunk, c.nx) - 1) / std::min(nchunk, c.nx);
+  const int per_plane = h->zc * h->yg;
+  {
+    std::vector<int> out;
+    h->bnd_off.assign(1, 0);
+    size_t i = 0;
+    for (int x0 = 0; x0 < c.nx; x0 += planes) {
+      std::vector<int> part;
+      while (i < bd.size() && bd[i] / per_plane < x0 + planes) part.push_back(bd[i++]);
+      if (part.empty()) continue;
+      part = xcd_order(part, h->zc);
+      out.insert(out.end(), part.begin(), part.end());
+      h->bnd_off.push_back((int)out.size());
+    }
+    bd.swap(out);
+  }
+  h->chunk_planes = planes;
   hipError_t err;
   for (int k = 0; k < 2; ++k) {
     std::vector<int>& v = k == 0 ? in : bd;

@@ -21,6 +21,13 @@ constexpr int YROWS = 4;   // rows (waves) per collide block
 constexpr int BLOCK = ZT * YROWS;
 constexpr int STG_BATCH = 32;  // steps whose inlet planes one STG launch computes
 constexpr int64_t FUSED_MAX_NODES = int64_t(1) << 24;  // FP16: one fused collide launch up to this size
+// FP32 storage: each step's general-kernel blocks go out as one dispatch per
+// range of x-planes holding about this many blocks (whole planes; a lattice of
+// up to 1.5x this many blocks is one dispatch).  On lattices of tens of
+// millions of nodes this holds the pull at about 0.75 of HBM peak where one
+// dispatch over all blocks reaches 0.69-0.70; the FP16 bulk kernel gains
+// nothing from it and keeps one dispatch.
+constexpr int CHUNK_BLOCKS = 30000;
 // FP32 state buffers together larger than this: non-temporal population
 // stores (the 256 MB Infinity Cache cannot hold the state from one step to
 // the next).
@@ -112,6 +119,10 @@ struct lbm_ctx {
   int* d_blist_int = nullptr;  // bulk / boundary collide block lists
   int* d_blist_bnd = nullptr;
   int n_int = 0, n_bnd = 0, cap_int = 0, cap_bnd = 0;
+  // Offsets of the x-chunks of d_blist_bnd (chunks + 1 entries; one chunk
+  // except with FP32 storage on large lattices), and the x-planes per chunk.
+  std::vector<int> bnd_off;
+  int chunk_planes = 0;
   int64_t int_nodes = 0;  // nodes updated by one bulk launch
   // FP16 storage: boundary blocks in the general kernel, then the bulk blocks
   // in a lean kernel; on lattices up to FUSED_MAX_NODES both in one fused

@@ -7,7 +7,8 @@
   from the oracle's seeded initial state (imported, rounded to the storage
   type), compared with the FP64 oracle on sampled nodes: every boundary class
   (inlet, outlet and their neighbours, wall rows and the first off-wall rows,
-  z tile edges, statistics planes) and random interior nodes.
+  z tile edges, statistics planes, the planes on both sides of each boundary
+  between the FP32 step's x-chunk dispatches) and random interior nodes.
   Tolerances as for the small cases: FP32 1e-5, FP16 deviations 2e-4
   relative L-inf over the sample.
 * 20 steps of the 768 x 64 x 192 FP32 workload against 20 oracle steps on every node.
@@ -71,8 +72,9 @@ def workload(name, storage, full_pert=True, shape=None, wall_avg="local"):
     return cfg, stg, f, hist, ch, planes
 
 
-def sample_nodes(nx, ny, nz, planes, seed, n_random=3000):
-    xs = sorted({0, 1, 2, nx // 2, nx - 3, nx - 2, nx - 1, *planes, *[p - 1 for p in planes], *[p + 1 for p in planes]})
+def sample_nodes(nx, ny, nz, planes, seed, n_random=3000, extra_x=()):
+    xs = sorted({0, 1, 2, nx // 2, nx - 3, nx - 2, nx - 1, *planes, *[p - 1 for p in planes], *[p + 1 for p in planes],
+                 *extra_x})
     ys = sorted({0, 1, 2, 3, 4, ny // 2, ny - 5, ny - 4, ny - 3, ny - 2, ny - 1})
     zs = sorted({0, 1, 62, 63, 64, 65, nz - 2, nz - 1} & set(range(nz)))
     g = np.random.default_rng(seed)
@@ -81,15 +83,25 @@ def sample_nodes(nx, ny, nz, planes, seed, n_random=3000):
     return np.unique(np.asarray(nodes, dtype=np.int64))
 
 
+# FP32 steps go out as one general-kernel dispatch per x-range of about 30000
+# blocks of 256 nodes (whole planes); FP16 keeps one dispatch.
+DISPATCHES = {("c2", "f32"): (1, 768), ("c3", "f32"): (10, 154), ("c5", "f32"): (20, 77)}
+
+
 @pytest.mark.parametrize("name,storage,tol", [("c2", "f32", 1e-5), ("c2", "f16dev", 2e-4), ("c2", "f16ref", 2e-4),
                                               ("c3", "f32", 1e-5), ("c3", "f16dev", 2e-4), ("c3", "f16ref", 2e-4),
                                               ("c5", "f32", 1e-5)])
 def test_full_size_one_step_sampled(name, storage, tol):
+    """One step against the oracle on sampled nodes, the planes on both sides of every
+    boundary between the FP32 step's x-chunk dispatches among them."""
     _say("full size", name, storage)
     cfg, stg, f, hist, ch, planes = workload(name, storage, full_pert=(name == "c2"))
+    n_disp, per = ch.collide_dispatches()
+    assert (n_disp, per) == DISPATCHES.get((name, storage), (1, cfg.nx))
+    edges = [e for k in range(1, n_disp) for e in (k * per - 1, k * per)]
     ch.step(1)
     ch.sync()
-    nodes = sample_nodes(cfg.nx, cfg.ny, cfg.nz, planes, seed=int(name[1]))
+    nodes = sample_nodes(cfg.nx, cfg.ny, cfg.nz, planes, seed=int(name[1]), extra_x=edges)
     gpu = ch.populations().reshape(19, -1)[:, torch.as_tensor(nodes, device="cuda")].cpu().numpy()
     st, ref, _ = O.step_nodes(cfg, f, hist, 1.0, nodes, stg=stg)
     assert st == O.OK
