@@ -36,7 +36,7 @@ HBM_PEAK_GBS = 8000.0
 BYTES_PER_NODE = {"f32": 152, "f16dev": 76, "f16ref": 76}  # 19 populations read + 19 written
 REPEATS = 5
 C5_STEPS = 5000  # the 151 M-node workload's horizon (REPEATS windows of C5_STEPS / REPEATS steps)
-C2_MIN_STEPS = 200  # shortest timed window on the 768 x 64 x 192 lattice
+C2_MIN_STEPS = 200  # shortest timed window on the 9-19 M-node lattices (768 x 64 x 192, the 8-GPU slab)
 SPONGE_NU = 0.1  # viscosity at the outlet plane of the 1-delta sponge (the paper gives no value)
 PROFILES_FILE = os.path.join(ROOT, "tests", "golden", "c4_profiles.txt")
 
@@ -45,25 +45,31 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def make_channel(name, storage, device, sponge=False, planes=None, seed=None):
+def make_channel(name, storage, device, sponge=False, planes=None, seed=None, shard=0):
     """storage: "f32", "f16dev" (half deviations from the weights) or "f16ref" (half
-    deviations from the equilibrium at the mean inflow profile)."""
+    deviations from the equilibrium at the mean inflow profile).  shard = n > 0: the x-slab
+    one of n GPUs would own in the middle of the channel (nx / n planes, x-periodic in place of
+    the halo exchange with its neighbours; no inlet, outlet or statistics planes)."""
     import torch
     from paper_2304_04214_amd import synthetic as S
     from paper_2304_04214_amd.channel import Channel
     w = S.WORKLOADS[name]
     nx, ny, nz = w["nx"], w["ny"], w["nz"]
+    if shard:
+        nx //= shard
+        planes = []
     delta = ny / 2
     ch = Channel(nx, ny, nz, tau0=w["tau0"], storage="f16dev" if storage == "f16ref" else storage, ywall="slip",
-                 xbc="inflow", wall_model=True, cs_smag=S.CS_SMAG, u_conv=S.U_C, device=device,
-                 sponge_cells=int(delta) if sponge else 0, sponge_nu=SPONGE_NU if sponge else 0.0)
+                 xbc="periodic" if shard else "inflow", wall_model=True, cs_smag=S.CS_SMAG, u_conv=S.U_C,
+                 device=device, sponge_cells=int(delta) if sponge else 0, sponge_nu=SPONGE_NU if sponge else 0.0)
     U = ch.inflow_reichardt(w["u_tau"])
     if storage == "f16ref":
         ch.set_reference(U)
     k = int(name[1])
-    mt = S.mode_table(w["n_modes"], delta, seed_offset=k)
-    ab, boy = S.amp_bins(ny)
-    ch.set_stg(mt, U, S.reynolds_stress(ny, w["u_tau"]), ab, boy)
+    if not shard:
+        mt = S.mode_table(w["n_modes"], delta, seed_offset=k)
+        ab, boy = S.amp_bins(ny)
+        ch.set_stg(mt, U, S.reynolds_stress(ny, w["u_tau"]), ab, boy)
     if seed is None:
         g = torch.Generator(device=device)
         g.manual_seed(S.SEED_BASE + k)
@@ -77,7 +83,8 @@ def make_channel(name, storage, device, sponge=False, planes=None, seed=None):
     del u
     if planes is None:
         planes = [p for p in (int(delta), int(2 * delta), int(4 * delta), int(8 * delta)) if p < nx]
-    ch.stats_attach(planes)
+    if planes:
+        ch.stats_attach(planes)
     return ch, (nx, ny, nz)
 
 
@@ -85,17 +92,18 @@ def _spread(vals):
     return dict(median=statistics.median(vals), min=min(vals), max=max(vals))
 
 
-def time_channel(name, storage, steps, warmup, device, sponge=False, repeats=REPEATS):
+def time_channel(name, storage, steps, warmup, device, sponge=False, repeats=REPEATS, shard=0):
     """REPEATS timed windows of `steps` steps after `warmup` untimed steps; per window the
     wall time between two device synchronisations and the HIP-event time of the dominant
     collide launches."""
     import torch
-    ch, (nx, ny, nz) = make_channel(name, storage, device, sponge=sponge)
+    ch, (nx, ny, nz) = make_channel(name, storage, device, sponge=sponge, shard=shard)
     N = nx * ny * nz
     n_disp, disp_planes = ch.collide_dispatches()
     ch.step(warmup)
     ch.sync()
-    ch.stats_reset()
+    if not shard:
+        ch.stats_reset()
     wall, kern = [], []
     k_nodes = 0
     for _ in range(repeats):
@@ -404,7 +412,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-accuracy", action="store_true", help="skip the FP16 mean-profile error legs")
     ap.add_argument("--only", default=None,
-                    help="time one leg: workload:storage[:sponge] (e.g. c3:f32), adjoint, adjoint-large, accuracy")
+                    help="time one leg: workload:storage[:sponge|:shardN] (e.g. c3:f32, c5:f32:shard8), adjoint, "
+                         "adjoint-large, accuracy")
     ap.add_argument("--repeats", type=int, default=REPEATS)
     ap.add_argument("--copy-only", action="store_true", help="run the 2 GiB copy kernel only (counter calibration)")
     ap.add_argument("--adj-steps", type=int, default=400, help="steps of the adjoint workload (loss horizon)")
@@ -432,8 +441,9 @@ def main():
         return
     if args.only:
         name, storage = args.only.split(":")[:2]
+        shard = int(args.only.split(":shard")[1]) if ":shard" in args.only else 0
         r = time_channel(name, storage, args.steps, args.warmup, device, sponge=args.only.endswith(":sponge"),
-                         repeats=rep)
+                         repeats=rep, shard=shard)
         print(json.dumps(r), flush=True)
         return
     log("bench: c3 f32 (headline), f16ref, f16dev")
@@ -450,6 +460,10 @@ def main():
     rsp = time_channel("c2", "f32", c2_steps, c2_warm, device, sponge=True, repeats=rep)
     log("bench: c5 f32 1536x256x384, %d steps (the workload's horizon, FP64 statistics on)" % C5_STEPS)
     r5 = time_channel("c5", "f32", C5_STEPS // rep, max(3, args.warmup // 4), device, repeats=rep)
+    log("bench: the per-GPU x-slab of 1536x256x384 on 8 GPUs (192x256x384, x-periodic), f32 / f16ref")
+    rsh = time_channel("c5", "f32", max(args.steps, C2_MIN_STEPS), max(args.warmup, 20), device, repeats=rep, shard=8)
+    rshr = time_channel("c5", "f16ref", max(args.steps, C2_MIN_STEPS), max(args.warmup, 20), device, repeats=rep,
+                        shard=8)
     log("bench: adjoint 256x64x64")
     radj = time_adjoint(device, steps=args.adj_steps, repeats=rep)
     log("bench: adjoint 512x64x128 FP16 (both FP16 storages)")
@@ -524,6 +538,10 @@ def main():
                               "f32_traffic": measured_traffic("collide_traffic_re1000_768x64x192.json", "c2:f32")},
         "re5200_1536x256x384_f32": {"steps": C5_STEPS, **brief(r5),
                                     "traffic": measured_traffic("collide_traffic_re5200_1536x256x384.json", "c5:f32")},
+        "shard_192x256x384": {"what": "the x-slab one of 8 GPUs would own of 1536x256x384, x-periodic in place of "
+                                      "the halo exchange (not part of it); no inlet, outlet or statistics planes",
+                              "f32": brief(rsh), "f16ref": {**brief(rshr), "vs_fp32": round(rshr["mlups"] / rsh["mlups"], 3)},
+                              "steps_per_window": max(args.steps, C2_MIN_STEPS)},
         "adjoint": radj,
         "adjoint_512x64x128_fp16": {**radj5, "storage": "half deviations from the mean-inflow equilibrium",
                                     "gradient_error_vs_fp32_state": None if gerr is None else gerr.get("f16ref")},
