@@ -228,6 +228,44 @@ def time_adjoint(device, name="c4", storage="f32", steps=400, segment=20, warmup
     return res
 
 
+def fd_gradient_error(device):
+    """The 256 x 64 x 64 adjoint workload's gradient against the FP64 oracle's central
+    differences stored in tests/golden/c4_fd_gradient.txt (mean-profile loss at x = 128 over
+    400 steps, h = 1e-4, the amplitude scalings of seven rows and C_s), the HIP side started
+    from the same seeded state (initialised by the library) with checkpoints every 20 steps.
+    Error = max |g_adjoint - g_FD| / max |g_FD| over the eight parameters."""
+    import torch
+    from paper_2304_04214_amd.adjoint import StatsGradient, mean_profile_loss
+    from paper_2304_04214_amd import synthetic as S
+    names, fd, L0 = [], [], None
+    for line in open(os.path.join(ROOT, "tests", "golden", "c4_fd_gradient.txt")):
+        if line.startswith("# L0"):
+            L0 = float(line.split()[2])
+        if line.startswith("#") or not line.strip():
+            continue
+        t = line.split()
+        names.append(t[0])
+        fd.append(float(t[3]))
+    fd = np.array(fd)
+    ch, (nx, ny, nz) = make_channel("c4", "f32", device, planes=[], seed=4)
+    x_obs = int(4 * ny / 2)
+    run = StatsGradient(ch, [x_obs], 400, segment=20)
+    U_t = torch.as_tensor(ch._stg_tensors["u_rans"][0].cpu())
+    R12_t = torch.as_tensor(S.reynolds_stress(ny, S.WORKLOADS["c4"]["u_tau"])[1])
+    means = run.forward()
+    m = torch.tensor(means, dtype=torch.float64, requires_grad=True)
+    loss = mean_profile_loss(m[0], U_t, R12_t)
+    loss.backward()
+    g = run.backward(m.grad.numpy())
+    ad = np.array([g[int(n[1:])] if n != "cs" else g[-1] for n in names])
+    ch.close()
+    del ch, run
+    torch.cuda.empty_cache()
+    return {"grad_rel_err": float(np.abs(ad - fd).max() / np.abs(fd).max()),
+            "loss_rel_err": abs(float(loss.detach()) - L0) / abs(L0), "parameters": names,
+            "reference": "FP64 oracle central differences, tests/golden/c4_fd_gradient.txt"}
+
+
 def fp16_gradient_error(device, name="c5a", steps=2000, segment=45):
     """Error of the FP16-state gradients of the large adjoint workload (512 x 64 x 128,
     mean-profile loss at x = 128 over 2000 steps, checkpoints every 45): each FP16 storage
@@ -412,7 +450,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-accuracy", action="store_true", help="skip the FP16 mean-profile error legs")
     ap.add_argument("--only", default=None,
-                    help="time one leg: workload:storage[:sponge|:shardN] (e.g. c3:f32, c5:f32:shard8), adjoint, "
+                    help="time one leg: workload:storage[:sponge|:shardN] (e.g. c3:f32, c5:f32:shard8), adjoint, fd, "
                          "adjoint-large, accuracy")
     ap.add_argument("--repeats", type=int, default=REPEATS)
     ap.add_argument("--copy-only", action="store_true", help="run the 2 GiB copy kernel only (counter calibration)")
@@ -438,6 +476,9 @@ def main():
         return
     if args.only == "accuracy":
         print(json.dumps(fp16_oracle_profile_error(device)), flush=True)
+        return
+    if args.only == "fd":
+        print(json.dumps(fd_gradient_error(device)), flush=True)
         return
     if args.only:
         name, storage = args.only.split(":")[:2]
@@ -469,8 +510,10 @@ def main():
     log("bench: adjoint 512x64x128 FP16 (both FP16 storages)")
     radj5 = time_adjoint(device, "c5a", "f16ref", steps=2000, segment=45, repeats=rep)
     radj5d = time_adjoint(device, "c5a", "f16dev", steps=2000, segment=45, repeats=rep)
-    acc_or = acc3 = gerr = None
+    acc_or = acc3 = gerr = gfd = None
     if not args.no_accuracy:
+        log("bench: the 256x64x64 gradient against the oracle's finite differences (400 steps)")
+        gfd = fd_gradient_error(device)
         log("bench: FP16-state gradients against the FP32-state gradient (512x64x128, 2000 steps)")
         gerr = fp16_gradient_error(device)
         log("bench: mean-profile error against the FP64 oracle (256x64x64, 2000 steps per storage)")
@@ -542,7 +585,7 @@ def main():
                                       "the halo exchange (not part of it); no inlet, outlet or statistics planes",
                               "f32": brief(rsh), "f16ref": {**brief(rshr), "vs_fp32": round(rshr["mlups"] / rsh["mlups"], 3)},
                               "steps_per_window": max(args.steps, C2_MIN_STEPS)},
-        "adjoint": radj,
+        "adjoint": {**radj, "gradient_error_vs_oracle_fd": gfd},
         "adjoint_512x64x128_fp16": {**radj5, "storage": "half deviations from the mean-inflow equilibrium",
                                     "gradient_error_vs_fp32_state": None if gerr is None else gerr.get("f16ref")},
         "adjoint_512x64x128_fp16dev": {**radj5d, "storage": "half deviations from the weights",
