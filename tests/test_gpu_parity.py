@@ -142,6 +142,27 @@ def test_c1_oracle_config_50_steps():
     assert e50 <= 5 * TOL32
 
 
+def test_fp32_x_range_dispatches_full_field():
+    """A lattice of 96,000 blocks (12000 x 32 x 8: every z-chunk holds 8 of its 64 lanes), whose
+    FP32 step goes out as three dispatches of 4000 x-planes: every node and the statistics of
+    the planes on both sides of the two dispatch boundaries after 5 steps, against the oracle."""
+    _say("x-range dispatches 12000x32x8")
+    c = Case(12000, 32, 8, ywall="slip", xbc="inflow", wall_model=True, n_modes=24, seed=7)
+    assert c.ch.collide_dispatches() == (3, 4000)
+    planes = [3999, 4000, 7999, 8000]
+    c.ch.stats_attach(planes)
+    c.ch.step(5)
+    means, n = c.ch.stats_read()
+    assert n == 5
+    st, f_or, hist_or, acc = c.run_oracle(5, planes=planes)
+    assert st == O.OK
+    f_g, hist_g = c.gpu_state()
+    err = rel_linf(f_g, f_or)
+    e_s = np.abs(means - acc / (5 * c.nz)).max() / np.abs(acc / (5 * c.nz)).max()
+    _say("  rel Linf %.3e, outlet history %.3e, statistics %.3e" % (err, rel_linf(hist_g, hist_or), e_s))
+    assert err <= TOL32 and rel_linf(hist_g, hist_or) <= TOL32 and e_s <= TOL32
+
+
 def test_statistics_match_oracle():
     c = Case(8, 10, 70, ywall="slip", xbc="inflow", wall_model=True, n_modes=30)
     planes = [1, 4, 7]
