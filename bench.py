@@ -228,15 +228,8 @@ def time_adjoint(device, name="c4", storage="f32", steps=400, segment=20, warmup
     return res
 
 
-def fd_gradient_error(device):
-    """The 256 x 64 x 64 adjoint workload's gradient against the FP64 oracle's central
-    differences stored in tests/golden/c4_fd_gradient.txt (mean-profile loss at x = 128 over
-    400 steps, h = 1e-4, the amplitude scalings of seven rows and C_s), the HIP side started
-    from the same seeded state (initialised by the library) with checkpoints every 20 steps.
-    Error = max |g_adjoint - g_FD| / max |g_FD| over the eight parameters."""
-    import torch
-    from paper_2304_04214_amd.adjoint import StatsGradient, mean_profile_loss
-    from paper_2304_04214_amd import synthetic as S
+def read_fd_fixture():
+    """(parameter names, central differences, L0) of tests/golden/c4_fd_gradient.txt."""
     names, fd, L0 = [], [], None
     for line in open(os.path.join(ROOT, "tests", "golden", "c4_fd_gradient.txt")):
         if line.startswith("# L0"):
@@ -246,7 +239,19 @@ def fd_gradient_error(device):
         t = line.split()
         names.append(t[0])
         fd.append(float(t[3]))
-    fd = np.array(fd)
+    return names, np.array(fd), L0
+
+
+def fd_gradient_error(device):
+    """The 256 x 64 x 64 adjoint workload's gradient against the FP64 oracle's central
+    differences stored in tests/golden/c4_fd_gradient.txt (mean-profile loss at x = 128 over
+    400 steps, h = 1e-4, the amplitude scalings of seven rows and C_s), the HIP side started
+    from the same seeded state (initialised by the library) with checkpoints every 20 steps.
+    Error = max |g_adjoint - g_FD| / max |g_FD| over the eight parameters."""
+    import torch
+    from paper_2304_04214_amd.adjoint import StatsGradient, mean_profile_loss
+    from paper_2304_04214_amd import synthetic as S
+    names, fd, L0 = read_fd_fixture()
     ch, (nx, ny, nz) = make_channel("c4", "f32", device, planes=[], seed=4)
     x_obs = int(4 * ny / 2)
     run = StatsGradient(ch, [x_obs], 400, segment=20)
