@@ -142,12 +142,15 @@ def test_c1_oracle_config_50_steps():
     assert e50 <= 5 * TOL32
 
 
-def test_fp32_x_range_dispatches_full_field():
+@pytest.mark.parametrize("wall_avg", ["local", "line"])
+def test_fp32_x_range_dispatches_full_field(wall_avg):
     """A lattice of 96,000 blocks (12000 x 32 x 8: every z-chunk holds 8 of its 64 lanes), whose
     FP32 step goes out as three dispatches of 4000 x-planes: every node and the statistics of
-    the planes on both sides of the two dispatch boundaries after 5 steps, against the oracle."""
-    _say("x-range dispatches 12000x32x8")
-    c = Case(12000, 32, 8, ywall="slip", xbc="inflow", wall_model=True, n_modes=24, seed=7)
+    the planes on both sides of the two dispatch boundaries after 5 steps, against the oracle;
+    the local and the line-averaged wall model (the line kernel runs once per step, before the
+    dispatches)."""
+    _say("x-range dispatches 12000x32x8", wall_avg)
+    c = Case(12000, 32, 8, ywall="slip", xbc="inflow", wall_model=True, n_modes=24, seed=7, wall_avg=wall_avg)
     assert c.ch.collide_dispatches() == (3, 4000)
     planes = [3999, 4000, 7999, 8000]
     c.ch.stats_attach(planes)
