@@ -45,7 +45,7 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def make_channel(name, storage, device, sponge=False, planes=None, seed=None, shard=0):
+def make_channel(name, storage, device, sponge=False, planes=None, seed=None, shard=0, f64_init=False):
     """storage: "f32", "f16dev" (half deviations from the weights) or "f16ref" (half
     deviations from the equilibrium at the mean inflow profile).  shard = n > 0: the x-slab
     one of n GPUs would own in the middle of the channel (nx / n planes, x-periodic in place of
@@ -75,6 +75,10 @@ def make_channel(name, storage, device, sponge=False, planes=None, seed=None, sh
         g.manual_seed(S.SEED_BASE + k)
         u = U.float()[:, None, :, None].expand(3, nx, ny, nz).contiguous()
         u += 1e-3 * (2 * torch.rand((3, nx, ny, nz), generator=g, device=device) - 1)
+    elif f64_init:  # the reference computations' initial state: FP64 fields, f_eq formed in FP64
+        du, _ = S.perturbations(nx, ny, nz, seed_offset=seed)
+        u = U[:, None, :, None] + 1e-3 * torch.as_tensor(du, device=device)
+        del du
     else:  # the seeded host perturbation of the reference computations
         du, _ = S.perturbations(nx, ny, nz, seed_offset=seed, dtype=np.float32)
         u = U.float()[:, None, :, None] + 1e-3 * torch.as_tensor(du, device=device)
@@ -246,13 +250,14 @@ def fd_gradient_error(device):
     """The 256 x 64 x 64 adjoint workload's gradient against the FP64 oracle's central
     differences stored in tests/golden/c4_fd_gradient.txt (mean-profile loss at x = 128 over
     400 steps, h = 1e-4, the amplitude scalings of seven rows and C_s), the HIP side started
-    from the same seeded state (initialised by the library) with checkpoints every 20 steps.
+    from the same seeded state (the library's FP64 initial equilibrium of the same FP64 fields,
+    rounded to FP32 as the fixture's state is) with checkpoints every 20 steps.
     Error = max |g_adjoint - g_FD| / max |g_FD| over the eight parameters."""
     import torch
     from paper_2304_04214_amd.adjoint import StatsGradient, mean_profile_loss
     from paper_2304_04214_amd import synthetic as S
     names, fd, L0 = read_fd_fixture()
-    ch, (nx, ny, nz) = make_channel("c4", "f32", device, planes=[], seed=4)
+    ch, (nx, ny, nz) = make_channel("c4", "f32", device, planes=[], seed=4, f64_init=True)
     x_obs = int(4 * ny / 2)
     run = StatsGradient(ch, [x_obs], 400, segment=20)
     U_t = torch.as_tensor(ch._stg_tensors["u_rans"][0].cpu())
@@ -267,6 +272,7 @@ def fd_gradient_error(device):
     del ch, run
     torch.cuda.empty_cache()
     return {"grad_rel_err": float(np.abs(ad - fd).max() / np.abs(fd).max()),
+            "per_parameter": {n: float(abs(x - y) / np.abs(fd).max()) for n, x, y in zip(names, ad, fd)},
             "loss_rel_err": abs(float(loss.detach()) - L0) / abs(L0), "parameters": names,
             "reference": "FP64 oracle central differences, tests/golden/c4_fd_gradient.txt"}
 

@@ -206,6 +206,12 @@ lbm_status lbm_get_state(lbm_handle h, void** f_cur, float** hist_cur, int64_t* 
  * 1), u [3][N], pert [19][N] (NULL: none): device float arrays.
  */
 lbm_status lbm_init_equilibrium(lbm_handle h, const float* rho, const float* u, const float* pert, float eps);
+/* The same from device double arrays, the equilibrium formed in FP64 and
+   rounded once to the storage (with FP16 storage, the deviation f - w - r
+   formed in FP64): a state that matches an FP64 computation of Eq. (27) from
+   the same fields up to that rounding. */
+lbm_status lbm_init_equilibrium_f64(lbm_handle h, const double* rho, const double* u, const double* pert,
+                                    double eps);
 
 /* Mean inflow U(y) = u_tau u+(d u_tau / nu0), d = min(y + 1/2, ny - y - 1/2),
    with the Reichardt law of Sec. II.C; writes device double u_rans[3][ny]. */

@@ -17,6 +17,7 @@ MAX_MODES = 1024
 
 EXPORTED = [
     "lbm_create", "lbm_destroy", "lbm_set_state", "lbm_get_state", "lbm_init_equilibrium",
+    "lbm_init_equilibrium_f64",
     "lbm_inflow_reichardt", "stg_inlet_fill", "stg_inlet_fill_noalloc", "lbm_step", "lbm_stream_only", "lbm_export_f32", "lbm_import_f32",
     "lbm_set_reference", "lbm_state_elems",
     "lbm_stats", "lbm_sync", "lbm_status_str", "lbm_kernel_timing", "lbm_collide_dispatches", "lbm_copy_probe", "lbm_lattice_tables",
@@ -65,6 +66,7 @@ def lib():
             "lbm_set_state": [P, P, P, P, P, I64],
             "lbm_get_state": [P, P, P, P],
             "lbm_init_equilibrium": [P, P, P, P, C.c_float],
+            "lbm_init_equilibrium_f64": [P, P, P, P, D],
             "lbm_inflow_reichardt": [P, D, P],
             "stg_inlet_fill": [P, P, D],
             "stg_inlet_fill_noalloc": [P, P, D],

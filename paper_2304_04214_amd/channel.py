@@ -143,15 +143,22 @@ class Channel:
         return self._stg_tensors["fluct"]
 
     def init(self, u, rho=None, pert=None, eps=0.0):
-        """f = f_eq(rho, u) + eps w pert in the current buffer; time index set to 0."""
+        """f = f_eq(rho, u) + eps w pert in the current buffer; time index set to 0.  A float64 u
+        (torch or numpy) takes the FP64 path (lbm_init_equilibrium_f64), rho and pert with it."""
         dev = self.device
-        u = _dev(u, torch.float32, dev).reshape(3, self.N)
-        rho = None if rho is None else _dev(rho, torch.float32, dev).reshape(self.N)
-        pert = None if pert is None else _dev(pert, torch.float32, dev).reshape(19, self.N)
+        f64 = (u.dtype == torch.float64) if torch.is_tensor(u) else (np.asarray(u).dtype == np.float64)
+        dt = torch.float64 if f64 else torch.float32
+        u = _dev(u, dt, dev).reshape(3, self.N)
+        rho = None if rho is None else _dev(rho, dt, dev).reshape(self.N)
+        pert = None if pert is None else _dev(pert, dt, dev).reshape(19, self.N)
         A.check(A.lib().lbm_set_state(self._h, _ptr(self.f[0]), _ptr(self.f[1]), _ptr(self.hist[0]),
                                       _ptr(self.hist[1]), 0), "lbm_set_state")
-        A.check(A.lib().lbm_init_equilibrium(self._h, _ptr(rho), _ptr(u), _ptr(pert), float(eps)),
-                "lbm_init_equilibrium")
+        if f64:
+            A.check(A.lib().lbm_init_equilibrium_f64(self._h, _ptr(rho), _ptr(u), _ptr(pert), float(eps)),
+                    "lbm_init_equilibrium_f64")
+        else:
+            A.check(A.lib().lbm_init_equilibrium(self._h, _ptr(rho), _ptr(u), _ptr(pert), float(eps)),
+                    "lbm_init_equilibrium")
         self._keep_init = (u, rho, pert)  # alive until the enqueued kernel has read them
 
     # ---- time stepping ----

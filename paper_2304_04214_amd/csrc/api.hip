@@ -270,6 +270,13 @@ lbm_status lbm_init_equilibrium(lbm_handle h, const float* rho, const float* u, 
   return LBM_OK;
 }
 
+lbm_status lbm_init_equilibrium_f64(lbm_handle h, const double* rho, const double* u, const double* pert,
+                                     double eps) {
+  if (!h || !u) return LBM_ERR_ARG;
+  HIPCHK(lbm::launch_init(h, rho, u, pert, eps));
+  return LBM_OK;
+}
+
 lbm_status lbm_inflow_reichardt(lbm_handle h, double u_tau, double* u_rans) {
   if (!h || !u_rans || !(u_tau >= 0.0)) return LBM_ERR_ARG;
   HIPCHK(lbm::launch_inflow_reichardt(h, u_tau, u_rans));

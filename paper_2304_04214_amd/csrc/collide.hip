@@ -656,28 +656,35 @@ __global__ __launch_bounds__(BLOCK) void stream_only_kernel(CollideArgs a) {
   for (int i = 0; i < Q; ++i) Pop<false>::st_plain(a.dst, i, row + (uint32_t)i * ZT + col.c0, pull_dir<false>(a, g, i, col, -1.f), 0.f);
 }
 
-// f_i = f_eq_i(rho, u) + eps w_i pert_i from SoA node fields [.][N], N = (x ny + y) nz + z.
-template <bool F16>
-__global__ __launch_bounds__(BLOCK) void init_kernel(CollideArgs a, float* hist, const float* rho, const float* u,
-                                                     const float* pert, float eps) {
+// f_i = f_eq_i(rho, u) + eps w_i pert_i from SoA node fields [.][N], N = (x ny + y) nz + z,
+// in the precision T of the inputs (float or double), rounded once to the
+// storage: FP32 populations, or with FP16 storage the deviation f - w - r
+// formed in T.
+template <bool F16, typename T>
+__global__ __launch_bounds__(BLOCK) void init_kernel(CollideArgs a, float* hist, const T* rho, const T* u,
+                                                     const T* pert, T eps) {
   const Node nd = decode(a);
   if (!nd.active || !nd.owned) return;
   const int N = a.nx * a.ny * a.nz;
   const int n = (nd.x * a.ny + nd.y) * a.nz + nd.z;
-  const float r = rho ? rho[n] : 1.f;
-  const float ux = u[n], uy = u[N + n], uz = u[2 * N + n];
-  const float uu15 = 1.5f * (ux * ux + uy * uy + uz * uz);
+  const T r = rho ? rho[n] : T(1);
+  const T ux = u[n], uy = u[N + n], uz = u[2 * N + n];
+  const T uu15 = T(1.5) * (ux * ux + uy * uy + uz * uz);
   const uint32_t e0 = rowpart(a, nd.x, nd.y) + colpart(a, nd.z);
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
-    const float cu = CX[i] * ux + CY[i] * uy + CZ[i] * uz;
-    float v = (float)WD[i] * r * (1.f + 3.f * cu + 4.5f * cu * cu - uu15);
-    if (pert) v += eps * (float)WD[i] * pert[(size_t)i * N + n];
-    Pop<F16>::st_plain(a.dst, i, e0 + (uint32_t)i * ZT, v, ref_off(a, i, nd.y));
+    const T cu = CX[i] * ux + CY[i] * uy + CZ[i] * uz;
+    T v = (T)WD[i] * r * (T(1) + T(3) * cu + T(4.5) * cu * cu - uu15);
+    if (pert) v += eps * (T)WD[i] * pert[(size_t)i * N + n];
+    const float ref = ref_off(a, i, nd.y);
+    if (F16 && sizeof(T) == 8)
+      static_cast<_Float16*>(a.dst)[e0 + (uint32_t)i * ZT] = (_Float16)(float)((v - WD[i]) - (T)ref);
+    else
+      Pop<F16>::st_plain(a.dst, i, e0 + (uint32_t)i * ZT, (float)v, ref);
     if (hist && nd.x == a.nx - 1) {
 #pragma unroll
       for (int k = 0; k < 5; ++k)
-        if (OUT5[k] == i) hist[(k * a.ny + nd.y) * a.nz + nd.z] = v;
+        if (OUT5[k] == i) hist[(k * a.ny + nd.y) * a.nz + nd.z] = (float)v;
     }
   }
 }
@@ -1046,15 +1053,24 @@ hipError_t launch_stream_only(lbm_ctx* h, int src, int dst) {
   return hipGetLastError();
 }
 
-hipError_t launch_init(lbm_ctx* h, const float* rho, const float* u, const float* pert, float eps) {
+template <typename T>
+hipError_t launch_init_t(lbm_ctx* h, const T* rho, const T* u, const T* pert, T eps) {
   CollideArgs a;
   fill_args(h, a, h->cur, h->cur);
   float* hist = h->cfg.xbc == LBM_X_INFLOW ? h->hist[h->cur] : nullptr;
   if (h->cfg.storage == LBM_STORE_F16DEV)
-    init_kernel<true><<<h->nblocks, BLOCK, 0, h->stream>>>(a, hist, rho, u, pert, eps);
+    init_kernel<true, T><<<h->nblocks, BLOCK, 0, h->stream>>>(a, hist, rho, u, pert, eps);
   else
-    init_kernel<false><<<h->nblocks, BLOCK, 0, h->stream>>>(a, hist, rho, u, pert, eps);
+    init_kernel<false, T><<<h->nblocks, BLOCK, 0, h->stream>>>(a, hist, rho, u, pert, eps);
   return hipGetLastError();
+}
+
+hipError_t launch_init(lbm_ctx* h, const float* rho, const float* u, const float* pert, float eps) {
+  return launch_init_t(h, rho, u, pert, eps);
+}
+
+hipError_t launch_init(lbm_ctx* h, const double* rho, const double* u, const double* pert, double eps) {
+  return launch_init_t(h, rho, u, pert, eps);
 }
 
 hipError_t launch_export(lbm_ctx* h, float* out) {

@@ -167,6 +167,7 @@ hipError_t launch_bulk(lbm_ctx* h, int src, int dst, hipStream_t stream, const f
 hipError_t build_block_lists(lbm_ctx* h, const std::vector<int>& plane_of_x);
 hipError_t launch_stream_only(lbm_ctx* h, int src, int dst);
 hipError_t launch_init(lbm_ctx* h, const float* rho, const float* u, const float* pert, float eps);
+hipError_t launch_init(lbm_ctx* h, const double* rho, const double* u, const double* pert, double eps);
 hipError_t launch_export(lbm_ctx* h, float* out);
 hipError_t launch_import(lbm_ctx* h, const float* in);
 hipError_t launch_set_reference(lbm_ctx* h, const double* u_ref);

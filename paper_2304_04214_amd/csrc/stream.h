@@ -315,12 +315,34 @@ __device__ __forceinline__ Tau0 tau0_of_x(const CollideArgs& a, int x) {
   return Tau0{t, t * t};
 }
 
-// Reichardt law u+ and du+/dy+ (Sec. II.C, Eq. (16), with log1p / expm1 so
-// that small y+ loses no digits).
+// e^x through the hardware base-2 exponential (about 1 ulp; results below
+// the normal range flush to 0, where the Reichardt terms are negligible).
+__device__ __forceinline__ float exp_hw(float x) { return __builtin_amdgcn_exp2f(x * 1.44269504088896341f); }
+
+// log(1 + x), x > -1, from the hardware base-2 logarithm with the correction
+// for the rounding of 1 + x (Goldberg): log(u) x / (u - 1), u = fl(1 + x), and
+// x itself where u rounds to 1.  About 2 ulp, also for small x.
+__device__ __forceinline__ float log1p_hw(float x) {
+  const float u = 1.f + x, d = u - 1.f;
+  const float l = __builtin_amdgcn_logf(u) * 0.693147180559945309f;
+  return d == 0.f ? x : l * (x * rcp_fast(d));
+}
+
+// Reichardt law u+ and du+/dy+ (Sec. II.C, Eq. (16)) in FP32 from hardware
+// transcendentals: e^(-y+/11) - 1 by its Taylor series up to t^6 where
+// |t| = y+/11 < 0.3 (truncation below 2e-7 relative) so that small y+ loses no
+// digits, log1p as above.  u+ within about 4e-7 relative of the exact law and
+// u_tau of the Newton solve within about 2e-7 for y+ from 1e-4 to 1e4 (the
+// library's expf / log1pf / expm1f cost five times the instructions, and the
+// solve runs in every wall cell of every step).
 __device__ __forceinline__ void reichardt(const CollideArgs& a, float yp, float& up, float& dup) {
-  const float e1 = expf(yp * (-1.f / 11.f)), e3 = expf(yp * (-1.f / 3.f));
-  up = log1pf(a.kappa * yp) * a.inv_kappa - a.b_reich * (expm1f(yp * (-1.f / 11.f)) + yp * (1.f / 11.f) * e3);
-  dup = 1.f / (1.f + a.kappa * yp) + a.b_reich * ((e1 - e3) * (1.f / 11.f) + yp * (1.f / 33.f) * e3);
+  const float t = yp * (-1.f / 11.f);
+  const float e1 = exp_hw(t), e3 = exp_hw(yp * (-1.f / 3.f));
+  const float em1s =
+      t * (1.f + t * (0.5f + t * ((1.f / 6.f) + t * ((1.f / 24.f) + t * ((1.f / 120.f) + t * (1.f / 720.f))))));
+  const float em1 = t > -0.3f ? em1s : e1 - 1.f;
+  up = log1p_hw(a.kappa * yp) * a.inv_kappa - a.b_reich * (em1 + yp * (1.f / 11.f) * e3);
+  dup = rcp_fast(1.f + a.kappa * yp) + a.b_reich * ((e1 - e3) * (1.f / 11.f) + yp * (1.f / 33.f) * e3);
 }
 
 // Musker's explicit law of the wall (the alternative Sec. II.C names):
@@ -350,12 +372,12 @@ __device__ __forceinline__ void wall_law(const CollideArgs& a, float yp, float& 
 // u_tau from a fixed number of Newton steps on u_tau u+(y u_tau / nu0) = ua
 // (Sec. II.C, Eq. (20)), started from the viscous-sublayer estimate.
 __device__ __forceinline__ float newton_utau(const CollideArgs& a, float ua) {
-  float ut = sqrtf(a.nu0 * ua / a.y_wall);
+  float ut = sqrt_fast(a.nu0 * ua * rcp_fast(a.y_wall));
   for (int it = 0; it < a.newton_iters; ++it) {
     const float yp = a.y_wall * ut * a.inv_nu0;
     float up, dup;
     wall_law(a, yp, up, dup);
-    ut -= (ut * up - ua) / (up + yp * dup);
+    ut -= (ut * up - ua) * rcp_fast(up + yp * dup);  // the steps' own rounding is corrected by the next
   }
   return ut;
 }

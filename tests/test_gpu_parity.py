@@ -14,8 +14,9 @@ import torch
 
 import oracle as O
 from paper_2304_04214_amd import _abi as A
+from paper_2304_04214_amd import synthetic as S
 from paper_2304_04214_amd.channel import Channel
-from parity_cases import Case, rel_linf
+from parity_cases import Case, reference_offsets, rel_linf
 from test_gpu_adjoint import storage_round
 
 pytestmark = [pytest.mark.gpu,
@@ -164,6 +165,45 @@ def test_fp32_x_range_dispatches_full_field(wall_avg):
     e_s = np.abs(means - acc / (5 * c.nz)).max() / np.abs(acc / (5 * c.nz)).max()
     _say("  rel Linf %.3e, outlet history %.3e, statistics %.3e" % (err, rel_linf(hist_g, hist_or), e_s))
     assert err <= TOL32 and rel_linf(hist_g, hist_or) <= TOL32 and e_s <= TOL32
+
+
+@pytest.mark.parametrize("storage", ["f32", "f16dev", "f16ref"])
+def test_fp64_initial_equilibrium_matches_oracle(storage):
+    """lbm_init_equilibrium_f64 (Eq. (27) from FP64 fields, with a perturbation): the stored
+    state is the oracle's FP64 state rounded once to the storage.  FP32: at most one unit in
+    the last place (the two FP64 evaluations differ in operation order only); FP16: the
+    deviations within one half-precision rounding of the oracle's.  The outlet history is the
+    state's outlet plane."""
+    nx, ny, nz = 8, 10, 70
+    cfg = O.make_cfg(nx, ny, nz, ywall=2, xbc=1, wall_model=1, tau0=0.52, cs_smag=0.1, u_conv=0.1)
+    U = O.reichardt_inflow(cfg, 0.008369396673286735)
+    du, dp = S.perturbations(nx, ny, nz, seed_offset=3)
+    u = U[:, None, :, None] + 1e-3 * du
+    f_or, h_or = O.init(cfg, u, pert=dp, eps=0.05)
+    ch = Channel(nx, ny, nz, tau0=0.52, storage="f16dev" if storage == "f16ref" else storage, ywall="slip",
+                 xbc="inflow", wall_model=True, u_conv=0.1)
+    dref = None
+    if storage == "f16ref":
+        U_g = ch.inflow_reichardt(0.008369396673286735)
+        ch.set_reference(U_g)
+        dref = reference_offsets(U_g.cpu().numpy())
+    ch.init(u, pert=dp, eps=0.05)
+    ch.sync()
+    f_g, h_g = ch.populations().cpu().numpy().astype(np.float64), ch.state()[1].cpu().numpy().astype(np.float64)
+    ch.close()
+    if storage == "f32":
+        ulp = np.abs(f_g - f_or.astype(np.float32)) / np.spacing(np.abs(f_or).astype(np.float32))
+        _say("  FP32: max %.1f ulp, %.2e of the values differ" % (ulp.max(), np.mean(ulp > 0)))
+        assert ulp.max() <= 1.0
+    else:
+        w = O.tables()["w"][:, None, None, None]
+        r = 0.0 if dref is None else dref.astype(np.float64)[:, None, :, None]
+        h_exact = f_or - w - r
+        h_got = f_g - w - r
+        bound = np.spacing(np.abs(h_exact).astype(np.float16)).astype(np.float64) + 1e-12
+        _say("  FP16: max |h - h_oracle| / half ulp %.2f" % (np.abs(h_got - h_exact) / bound).max())
+        assert np.all(np.abs(h_got - h_exact) <= bound)
+    assert np.abs(h_g - h_or.astype(np.float32)).max() <= np.spacing(np.float32(1.0))
 
 
 def test_statistics_match_oracle():
