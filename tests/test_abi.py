@@ -74,6 +74,8 @@ def test_bad_configurations_are_rejected_without_a_device():
     assert L.lbm_create(None, buf, buf, None, None, None, C.byref(h)) == A.LBM_ERR_ARG
     assert L.lbm_step(None, None, 1) == A.LBM_ERR_ARG
     assert L.lbm_copy_probe(buf, buf, 15, None) == A.LBM_ERR_ARG
+    assert L.lbm_init_equilibrium_f64(None, None, buf, None, 0.0) == A.LBM_ERR_ARG
+    assert L.lbm_init_equilibrium(None, None, buf, None, 0.0) == A.LBM_ERR_ARG
     d, p = C.c_int32(-1), C.c_int32(-1)
     assert L.lbm_collide_dispatches(None, C.byref(d), C.byref(p)) == A.LBM_ERR_ARG
     assert (d.value, p.value) == (-1, -1)  # outputs untouched on error
