@@ -251,8 +251,9 @@ lbm_status stg_inlet_fill_noalloc(lbm_handle h, const lbm_stg* stg, double t);
  * pull-stream / boundary / wall-model / MRT-Smagorinsky collision runs over
  * all nodes, on the handle's stream.  With LBM_STORE_F16DEV the blocks away
  * from the inlet, outlet and statistics planes (wall rows included) run in a
- * lean kernel after a general kernel for the other blocks; with LBM_STORE_F32
- * one general kernel covers all blocks.
+ * lean kernel after a general kernel for the other blocks (one fused launch on
+ * lattices of up to 2^24 nodes); with LBM_STORE_F32 the general kernel covers
+ * all blocks, one dispatch per range of x-planes (lbm_collide_dispatches).
  * stg: bound when non-NULL; required (now or earlier) with LBM_X_INFLOW.
  * Asynchronous on the handle's stream.
  */
