@@ -310,9 +310,9 @@ lbm_status stg_inlet_fill_noalloc(lbm_handle h, const lbm_stg* stg, double t) {
 // then the bulk blocks, both reading s_n and writing disjoint nodes of
 // s_{n+1}, as two launches or, on lattices up to FUSED_MAX_NODES, one
 // (running the boundary blocks concurrently on a second stream cost more in
-// cross-stream waits than it hid).  The inlet planes of up to STG_BATCH steps come from one launch
-// into a ring; the plane of the last step also goes to the bound u_in /
-// fluct.
+// cross-stream waits than it hid).  The inlet planes of up to STG_BATCH steps
+// come from one launch into a ring; the plane of the last step also goes to
+// the bound u_in / fluct.
 hipError_t enqueue_steps(lbm_ctx* h, int cur, int64_t time, int32_t nsteps, hipStream_t st) {
   const bool inflow = h->cfg.xbc == LBM_X_INFLOW;
   const size_t plane = (size_t)3 * h->cfg.ny * h->cfg.nz;
