@@ -219,7 +219,8 @@ def time_adjoint(device, name="c4", storage="f32", steps=400, segment=20, warmup
         adjoint_vs_forward=round(adj_ms / fwd_ms, 3),
         roofline={"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                   "frac": round(achieved / HBM_PEAK_GBS, 4),
-                  "traffic": measured_traffic("adjoint_traffic_256x64x64.json", "c4:adjoint") if name == "c4" else None,
+                  "traffic": (measured_traffic("adjoint_traffic_256x64x64.json", "c4:adjoint") if name == "c4" else
+                              measured_traffic("adjoint_traffic_512x64x128.json", "c5a:adjoint:" + storage)),
                   "kernel": "adjoint_kernel<%s> (one launch per adjoint step; time per step includes the "
                             "line-model probe when configured)" % storage,
                   "bytes_per_node": bpn},
@@ -466,6 +467,8 @@ def main():
     ap.add_argument("--repeats", type=int, default=REPEATS)
     ap.add_argument("--copy-only", action="store_true", help="run the 2 GiB copy kernel only (counter calibration)")
     ap.add_argument("--adj-steps", type=int, default=400, help="steps of the adjoint workload (loss horizon)")
+    ap.add_argument("--adj-large-steps", type=int, default=2000,
+                    help="steps of the 512x64x128 adjoint workload (--only adjoint-large[-dev]; counter runs)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: the library runs on one GPU only (the path shards over x-slabs by design, "
@@ -483,7 +486,8 @@ def main():
         return
     if args.only in ("adjoint-large", "adjoint-large-dev"):
         storage = "f16dev" if args.only.endswith("-dev") else "f16ref"
-        print(json.dumps(time_adjoint(device, "c5a", storage, steps=2000, segment=45, repeats=rep)), flush=True)
+        print(json.dumps(time_adjoint(device, "c5a", storage, steps=args.adj_large_steps, segment=45, repeats=rep)),
+              flush=True)
         return
     if args.only == "accuracy":
         print(json.dumps(fp16_oracle_profile_error(device)), flush=True)

@@ -29,7 +29,9 @@ def test_traffic_records_match_the_current_sources():
                                  ("collide_traffic_re5200_1536x256x384.json", "c5:f32", 152, 1536 * 256 * 384),
                                  ("collide_traffic_re1000_768x64x192.json", "c2:f32", 152, 768 * 64 * 192),
                                  ("collide_traffic_re1000_768x64x192.json", "c2:f16dev", 76, 768 * 64 * 192),
-                                 ("adjoint_traffic_256x64x64.json", "c4:adjoint", 228, 256 * 64 * 64)]:
+                                 ("adjoint_traffic_256x64x64.json", "c4:adjoint", 228, 256 * 64 * 64),
+                                 ("adjoint_traffic_512x64x128.json", "c5a:adjoint:f16ref", 190, 512 * 64 * 128),
+                                 ("adjoint_traffic_512x64x128.json", "c5a:adjoint:f16dev", 190, 512 * 64 * 128)]:
         t = bench.measured_traffic(rec, key)
         assert t is not None, (rec, key)
         assert abs(t / (bpn * nodes) - 1) < 0.02, (rec, key, t / (bpn * nodes))
