@@ -749,11 +749,15 @@ __global__ __launch_bounds__(BLOCK) void recode_kernel(CollideArgs a, _Float16* 
   }
 }
 
-// One 16-byte vector per thread, streamed (the bandwidth reference of the benchmark).
+// One 16-byte vector per thread, non-temporal load and store (the bandwidth
+// reference of the benchmark: 6.54-6.58 TB/s for 2-11 GiB, against 6.20-6.36
+// with plain loads and 5.6-6.1 with 2-8 vectors per thread).  The pull kernels
+// keep plain loads: each source row is read by up to nine destination rows,
+// which must hit in L2.
 typedef float vec4f __attribute__((ext_vector_type(4)));
 __global__ void copy_kernel(const vec4f* __restrict__ src, vec4f* __restrict__ dst, int64_t n4) {
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (k < n4) __builtin_nontemporal_store(src[k], dst + k);
+  if (k < n4) __builtin_nontemporal_store(__builtin_nontemporal_load(src + k), dst + k);
 }
 
 }  // namespace
