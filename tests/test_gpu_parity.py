@@ -206,6 +206,20 @@ def test_fp64_initial_equilibrium_matches_oracle(storage):
     assert np.abs(h_g - h_or.astype(np.float32)).max() <= np.spacing(np.float32(1.0))
 
 
+def test_copy_probe_copies_bit_exactly():
+    """The bandwidth reference kernel (non-temporal loads and stores) copies every byte, also
+    for a size that ends inside a block of threads."""
+    from paper_2304_04214_amd.channel import copy_probe
+    g = torch.Generator(device="cuda")
+    g.manual_seed(5)
+    for n in (1 << 20, (1 << 20) + 4 * 37):  # floats: whole blocks, and a ragged tail of 37 float4
+        src = torch.rand(n, generator=g, device="cuda")
+        dst = torch.zeros_like(src)
+        copy_probe(src, dst)
+        torch.cuda.synchronize()
+        assert torch.equal(src, dst)
+
+
 def test_statistics_match_oracle():
     c = Case(8, 10, 70, ywall="slip", xbc="inflow", wall_model=True, n_modes=30)
     planes = [1, 4, 7]
