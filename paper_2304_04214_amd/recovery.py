@@ -38,9 +38,12 @@ def setup(re_tau, H, storage="f32", n_modes=200, seed=7, spectrum=False, device=
     nx, ny, nz = 20 * delta, 2 * delta, int(round(1.6 * delta))
     u_tau = S.U_TAU_OF_RE[float(re_tau)]
     nu0 = u_tau * delta / re_tau
-    ch = Channel(nx, ny, nz, tau0=0.5 + 3 * nu0, storage=storage, ywall="slip", xbc="inflow", wall_model=True,
-                 cs_smag=S.CS_SMAG, u_conv=S.U_C, sponge_cells=delta, sponge_nu=SPONGE_NU, device=device)
+    ch = Channel(nx, ny, nz, tau0=0.5 + 3 * nu0, storage="f16dev" if storage == "f16ref" else storage,
+                 ywall="slip", xbc="inflow", wall_model=True, cs_smag=S.CS_SMAG, u_conv=S.U_C, sponge_cells=delta,
+                 sponge_nu=SPONGE_NU, device=device)
     U = ch.inflow_reichardt(u_tau)
+    if storage == "f16ref":  # FP16 deviations from the equilibrium at the mean inflow profile
+        ch.set_reference(U)
     ab, boy = S.amp_bins(ny)
     R = S.reynolds_stress(ny, u_tau)
     if spectrum:
@@ -103,7 +106,9 @@ def main():
     ap.add_argument("--re", type=float, nargs="+", default=[1000.0, 2000.0, 5200.0])
     ap.add_argument("--h", type=int, nargs="+", default=[20])
     ap.add_argument("--periods", type=int, default=10)
-    ap.add_argument("--storage", default="f32")
+    ap.add_argument("--storage", default="f32", choices=["f32", "f16dev", "f16ref"],
+                    help="populations in FP32, FP16 deviations from the weights, or FP16 deviations from the "
+                         "equilibrium at the mean inflow profile")
     ap.add_argument("--spectrum", action="store_true", help="per-row STG spectrum from synthetic RANS k, omega")
     a = ap.parse_args()
     for re_tau in a.re:

@@ -532,10 +532,15 @@ def test_fp16_mean_profiles_long_horizon():
 
 def test_recovery_run_executes():
     """The inflow-recovery driver on the H = 20 channel for one domain-through time
-    (statistics from the start): finite results, u_tau / u_theory near 1."""
+    (statistics from the start): finite results, u_tau / u_theory near 1; with FP16 storage
+    relative to the mean inflow the friction-velocity ratio stays within 2e-3 of FP32's."""
     from paper_2304_04214_amd import recovery
     r = recovery.run(1000.0, 20, periods=1, stats_from=0)
     ratio = np.asarray(r["u_tau_ratio"])
     _say("recovery: u_tau ratio range %.3f .. %.3f" % (ratio.min(), ratio.max()))
     assert np.all(np.isfinite(ratio)) and np.abs(ratio - 1).max() < 0.2
     assert all(np.isfinite(p["uv_plus_err_l2"]) for p in r["planes"])
+    r16 = recovery.run(1000.0, 20, periods=1, stats_from=0, storage="f16ref")
+    d = np.abs(np.asarray(r16["u_tau_ratio"]) - ratio).max()
+    _say("recovery: FP16 (reference storage) u_tau ratio differs from FP32 by %.2e" % d)
+    assert d < 2e-3
