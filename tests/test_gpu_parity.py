@@ -426,6 +426,32 @@ def test_degenerate_calls(storage):
     assert not eta_p.any() and not g_uin.any() and not grad.any()
 
 
+@pytest.mark.parametrize("storage,ref,avg", [("f32", False, "local"), ("f16dev", False, "local"),
+                                             ("f16dev", True, "local"), ("f32", False, "line")])
+def test_checkpoint_resume_is_bit_exact(storage, ref, avg):
+    """A run resumed from a checkpoint (the populations, their outlet history and the step index,
+    restored with lbm_set_state) continues bit for bit like the uninterrupted run: populations,
+    outlet history and the last inlet plane, also when the resumed calls split the steps (and so
+    the batches of inlet planes) differently."""
+    c = Case(7, 10, 70, ywall="slip", xbc="inflow", wall_model=True, storage=storage, reference=ref,
+             wall_avg=avg, n_modes=40)
+    ch = c.ch
+    ch.stats_attach([2, 4])
+    ch.step(5)
+    f_k, h_k = [t.clone() for t in ch.state()]
+    t_k = ch.time
+    ch.step(40)
+    p_ref, h_ref, u_ref = ch.populations().clone(), ch.state()[1].clone(), ch.u_in.clone()
+    ch.set_state(f_k, h_k, t_k)
+    ch.step(13)
+    ch.step(27)
+    ch.sync()
+    assert ch.time == t_k + 40
+    assert torch.equal(ch.populations(), p_ref)
+    assert torch.equal(ch.state()[1], h_ref)
+    assert torch.equal(ch.u_in, u_ref)
+
+
 @pytest.mark.parametrize("name", ["slip-inflow-wallmodel", "periodic-smag-force", "slip-inflow-wallmodel-sponge",
                                   "slip-inflow-musker-wall-law", "slip-inflow-line-averaged-utau",
                                   "bounceback-wallmodel", "bounceback-inflow-ny4", "slip-inflow-nz1",
